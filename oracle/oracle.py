@@ -1,0 +1,257 @@
+"""FP64 CPU oracle of the seismic saliency hot path -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this module.  The product library never does.
+
+This is a thin ctypes binding over ``sal_oracle.c`` (plain C, FP64, OpenMP):
+argument marshalling only, all arithmetic lives in the C file.  It follows
+Shafiq, Long, Di, AlRegib (ACI 2021), Section 2:
+
+* local 3D DFT of each window (Sec. 2 step 1, Eq. 2) -- ``local_spectra``;
+* spectral projection and features E_m (Eq. 1, third step) -- ``features``;
+* directional center-surround S_m (Eq. 3) -- ``dcs``, ``saliency_at``;
+* fusion weights and the combined map S (Eq. 4) -- ``fusion_weights``,
+  ``combine``; the adjoint of the whole chain -- ``backward``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sal_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+WINDOWS = {"hann": 0, "rect": 1}
+FUSION_MODES = {"equal": 0, "fixed": 1, "adapt_ls": 2}
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so next to the source (gcc, -O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wno-unknown-pragmas",
+               _SRC, "-o", tmp, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib = ctypes.CDLL(_LIB_PATH)
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _i64(v):
+    return ctypes.c_int64(int(v))
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError("oracle %s failed with code %d" % (what, rc))
+
+
+def max_threads() -> int:
+    return int(_load().orc_max_threads())
+
+
+def _nthreads(nthreads):
+    return ctypes.c_int(0 if nthreads is None else int(nthreads))
+
+
+def _vol(V):
+    V = np.ascontiguousarray(V, dtype=np.float32)
+    if V.ndim != 3:
+        raise ValueError("V must be [T][IL][XL]")
+    return V
+
+
+def window(n: int, kind="hann") -> np.ndarray:
+    h = np.zeros(n, np.float64)
+    _check(_load().orc_window(ctypes.c_int(n), ctypes.c_int(WINDOWS.get(kind, kind)), _p(h)), "window")
+    return h
+
+
+def local_spectra(V, n: int, kind, centers) -> np.ndarray:
+    """Unshifted spectra F[cnt][n][n][n] (complex128) at voxel centres [cnt][3]."""
+    V = _vol(V)
+    c = np.ascontiguousarray(centers, dtype=np.int64).reshape(-1, 3)
+    F = np.zeros((c.shape[0], n, n, n, 2), np.float64)
+    rc = _load().orc_local_spectra(_p(V), _i64(V.shape[0]), _i64(V.shape[1]), _i64(V.shape[2]), ctypes.c_int(n),
+                                   ctypes.c_int(WINDOWS.get(kind, kind)), _p(c), _i64(c.shape[0]), _p(F))
+    _check(rc, "local_spectra")
+    return F[..., 0] + 1j * F[..., 1]
+
+
+def grid_shape(shape, s):
+    return tuple(-(-int(N) // int(s)) for N in shape)
+
+
+def features(V, n: int, s: int, kind="hann", nthreads=None) -> np.ndarray:
+    """E[3][Tg][ILg][XLg] in FP64 (planes t, x=XL, y=IL)."""
+    V = _vol(V)
+    gs = grid_shape(V.shape, s)
+    E = np.zeros((3,) + gs, np.float64)
+    rc = _load().orc_features(_p(V), _i64(V.shape[0]), _i64(V.shape[1]), _i64(V.shape[2]), ctypes.c_int(n),
+                              ctypes.c_int(s), ctypes.c_int(WINDOWS.get(kind, kind)), _p(E), _nthreads(nthreads))
+    _check(rc, "features")
+    return E
+
+
+def features_at(V, n: int, s: int, kind, g, nthreads=None) -> np.ndarray:
+    """E at grid points g[cnt][3]; returns [cnt][3]."""
+    V = _vol(V)
+    g = np.ascontiguousarray(g, dtype=np.int64).reshape(-1, 3)
+    E = np.zeros((g.shape[0], 3), np.float64)
+    rc = _load().orc_features_at(_p(V), _i64(V.shape[0]), _i64(V.shape[1]), _i64(V.shape[2]), ctypes.c_int(n),
+                                 ctypes.c_int(s), ctypes.c_int(WINDOWS.get(kind, kind)), _p(g), _i64(g.shape[0]),
+                                 _p(E), _nthreads(nthreads))
+    _check(rc, "features_at")
+    return E
+
+
+def default_weights(offsets) -> np.ndarray:
+    off = np.ascontiguousarray(offsets, dtype=np.int32).reshape(-1, 3)
+    w = np.zeros(off.shape[0], np.float64)
+    _check(_load().orc_default_weights(ctypes.c_int(off.shape[0]), _p(off), _p(w)), "default_weights")
+    return w
+
+
+def _stencil(offsets, weights):
+    off = np.ascontiguousarray(offsets, dtype=np.int32).reshape(-1, 3)
+    w = default_weights(off) if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+    if w.shape != (off.shape[0],):
+        raise ValueError("one weight per offset")
+    return off, w
+
+
+def dcs(E, s: int, offsets, weights=None, literal=False) -> np.ndarray:
+    """S_m on the grid from E (both [3][Tg][ILg][XLg])."""
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    off, w = _stencil(offsets, weights)
+    S = np.zeros_like(E)
+    rc = _load().orc_dcs(_p(E), _i64(E.shape[1]), _i64(E.shape[2]), _i64(E.shape[3]), ctypes.c_int(s),
+                         ctypes.c_int(off.shape[0]), _p(off), _p(w), ctypes.c_int(int(bool(literal))), _p(S))
+    _check(rc, "dcs")
+    return S
+
+
+def saliency_at(V, n, s, kind, offsets, weights, literal, g, nthreads=None):
+    """(S_m[cnt][3], E[cnt][3]) at grid points g, features recomputed from V."""
+    V = _vol(V)
+    off, w = _stencil(offsets, weights)
+    g = np.ascontiguousarray(g, dtype=np.int64).reshape(-1, 3)
+    Sm = np.zeros((g.shape[0], 3), np.float64)
+    E = np.zeros((g.shape[0], 3), np.float64)
+    rc = _load().orc_saliency_at(_p(V), _i64(V.shape[0]), _i64(V.shape[1]), _i64(V.shape[2]), ctypes.c_int(n),
+                                 ctypes.c_int(s), ctypes.c_int(WINDOWS.get(kind, kind)), ctypes.c_int(off.shape[0]),
+                                 _p(off), _p(w), ctypes.c_int(int(bool(literal))), _p(g), _i64(g.shape[0]), _p(Sm),
+                                 _p(E), _nthreads(nthreads))
+    _check(rc, "saliency_at")
+    return Sm, E
+
+
+def fusion_weights(Sm, D=None, mask=None, mode="equal", wfix=None, delta=0.0):
+    """(W[3], fallback, stats[11]) -- Eq. 4 weights; stats only for adapt_ls."""
+    Sm = np.ascontiguousarray(Sm, dtype=np.float64)
+    G = Sm[0].size
+    Dp = None if D is None else np.ascontiguousarray(D, dtype=np.float32).reshape(-1)
+    Mp = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
+    wf = None if wfix is None else np.ascontiguousarray(wfix, dtype=np.float64)
+    W = np.zeros(3, np.float64)
+    st = np.zeros(11, np.float64)
+    fb = ctypes.c_int(0)
+    rc = _load().orc_fusion_weights(_p(Sm), _i64(G), _p(Dp), _p(Mp), ctypes.c_int(FUSION_MODES.get(mode, mode)),
+                                    _p(wf), ctypes.c_double(delta), _p(W), ctypes.byref(fb), _p(st))
+    _check(rc, "fusion_weights")
+    return W, int(fb.value), st
+
+
+def combine(Sm, W, shape, s: int) -> np.ndarray:
+    Sm = np.ascontiguousarray(Sm, dtype=np.float64)
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    T, IL, XL = shape
+    S = np.zeros((T, IL, XL), np.float64)
+    rc = _load().orc_combine(_p(Sm), _i64(Sm.shape[1]), _i64(Sm.shape[2]), _i64(Sm.shape[3]), _p(W), _i64(T),
+                             _i64(IL), _i64(XL), ctypes.c_int(s), _p(S))
+    _check(rc, "combine")
+    return S
+
+
+@dataclass
+class Params:
+    """Everything the method takes besides V (Sec. 2)."""
+    n: int = 8
+    s: int = 1
+    window: str = "hann"
+    offsets: np.ndarray = field(default_factory=lambda: np.zeros((0, 3), np.int32))
+    weights: Optional[np.ndarray] = None
+    literal: bool = False
+    fusion: str = "equal"
+    wfix: Optional[np.ndarray] = None
+    delta: float = 0.0
+    D: Optional[np.ndarray] = None
+    mask: Optional[np.ndarray] = None
+
+
+def forward(V, p: Params, nthreads=None) -> dict:
+    """E, S_m, W, fallback flag and S for the whole volume."""
+    V = _vol(V)
+    E = features(V, p.n, p.s, p.window, nthreads)
+    Sm = dcs(E, p.s, p.offsets, p.weights, p.literal)
+    W, fb, st = fusion_weights(Sm, p.D, p.mask, p.fusion, p.wfix, p.delta)
+    S = combine(Sm, W, V.shape, p.s)
+    return {"E": E, "Sm": Sm, "W": W, "fallback": fb, "stats": st, "S": S}
+
+
+def backward(V, p: Params, gS, nthreads=None):
+    """(gV, W, fallback): gradient of sum(gS * S) with respect to V."""
+    V = _vol(V)
+    off, w = _stencil(p.offsets, p.weights)
+    gS = np.ascontiguousarray(gS, dtype=np.float32)
+    if gS.shape != V.shape:
+        raise ValueError("gS must match V")
+    Dp = None if p.D is None else np.ascontiguousarray(p.D, dtype=np.float32).reshape(-1)
+    Mp = None if p.mask is None else np.ascontiguousarray(p.mask, dtype=np.uint8).reshape(-1)
+    wf = None if p.wfix is None else np.ascontiguousarray(p.wfix, dtype=np.float64)
+    gV = np.zeros(V.shape, np.float64)
+    W = np.zeros(3, np.float64)
+    fb = ctypes.c_int(0)
+    rc = _load().orc_backward(_p(V), _i64(V.shape[0]), _i64(V.shape[1]), _i64(V.shape[2]), ctypes.c_int(p.n),
+                              ctypes.c_int(p.s), ctypes.c_int(WINDOWS.get(p.window, p.window)),
+                              ctypes.c_int(off.shape[0]), _p(off), _p(w), ctypes.c_int(int(bool(p.literal))),
+                              ctypes.c_int(FUSION_MODES.get(p.fusion, p.fusion)), _p(wf), ctypes.c_double(p.delta),
+                              _p(Dp), _p(Mp), _p(gS), _p(gV), _p(W), ctypes.byref(fb), _nthreads(nthreads))
+    _check(rc, "backward")
+    return gV, W, int(fb.value)
+
+
+def backward_at(V, p: Params, gS, pts, nthreads=None) -> np.ndarray:
+    """gV at voxels pts[cnt][3] for equal or fixed fusion."""
+    V = _vol(V)
+    off, w = _stencil(p.offsets, p.weights)
+    gS = np.ascontiguousarray(gS, dtype=np.float32)
+    pts = np.ascontiguousarray(pts, dtype=np.int64).reshape(-1, 3)
+    wf = None if p.wfix is None else np.ascontiguousarray(p.wfix, dtype=np.float64)
+    gV = np.zeros(pts.shape[0], np.float64)
+    rc = _load().orc_backward_at(_p(V), _i64(V.shape[0]), _i64(V.shape[1]), _i64(V.shape[2]), ctypes.c_int(p.n),
+                                 ctypes.c_int(p.s), ctypes.c_int(WINDOWS.get(p.window, p.window)),
+                                 ctypes.c_int(off.shape[0]), _p(off), _p(w), ctypes.c_int(int(bool(p.literal))),
+                                 ctypes.c_int(FUSION_MODES.get(p.fusion, p.fusion)), _p(wf), _p(gS), _p(pts),
+                                 _i64(pts.shape[0]), _p(gV), _nthreads(nthreads))
+    _check(rc, "backward_at")
+    return gV
