@@ -1,0 +1,180 @@
+/*
+ * sal.h -- C ABI of libsal, the MI355X (gfx950) implementation of the seismic
+ * saliency hot path of Shafiq, Long, Di, AlRegib, "A novel attention model
+ * for salient structure detection in seismic volumes" (ACI 2021,
+ * arXiv 2201.06174), Section 2.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Volume V: float32 [T][IL][XL], XL fastest (time, inline, crossline; the
+ *   paper's T x X x Y volume, Sec. 2 first paragraph).
+ * Grid: window centres at g*s on each axis, Tg = ceil(T/s) etc.  Feature and
+ *   saliency maps are planar float32 [3][Tg][ILg][XLg] with plane order
+ *   (t, x = crossline = XL axis, y = inline = IL axis), the order of Eq. 1/4.
+ * Window: side n (even), samples c-n/2 .. c+n/2-1 around the centre c, taper
+ *   periodic Hann sin^2(pi a/n) or flat; indices outside the volume are
+ *   reflected half-sample symmetrically (-1 -> 0, N -> N-1), so every axis
+ *   must hold at least n/2 voxels.
+ * Memory: every pointer named in a call is caller-owned; device pointers must
+ *   be device memory of the current HIP device, host pointers are read during
+ *   the call only.  No call keeps a pointer past its return (plans excepted,
+ *   see sal_plan_create).
+ * Execution: all device work is enqueued on the given stream; no call
+ *   synchronises the host with the device, so every call can be captured
+ *   in a HIP graph.  Results are bitwise identical run to run.
+ * Errors: every call validates its arguments on the host before launching
+ *   anything and returns a sal_status; sal_last_error() then gives a message
+ *   (thread-local).  NaN/Inf inputs propagate without a check.
+ */
+#ifndef SAL_H
+#define SAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* sal_stream; /* a hipStream_t; NULL is the null stream */
+
+typedef enum {
+    SAL_OK = 0,
+    SAL_ERR_ARG = 1,         /* bad pointer, size, or option value */
+    SAL_ERR_SHAPE = 2,       /* inconsistent shapes (e.g. an axis shorter than n/2) */
+    SAL_ERR_UNSUPPORTED = 3, /* valid for the method, not built into this library (e.g. n = 10) */
+    SAL_ERR_NOMEM = 4,       /* workspace too small or allocation failed */
+    SAL_ERR_DEVICE = 5       /* a HIP runtime call failed */
+} sal_status;
+
+typedef enum { SAL_WINDOW_HANN = 0, SAL_WINDOW_RECT = 1 } sal_window;
+
+/* Arithmetic of the windowed-DFT contractions.  FP32: fp32 matrix-core
+ * products; SPLIT_BF16: each operand split into hi + lo bfloat16 parts, three
+ * bf16 products (hi*hi + hi*lo + lo*hi) accumulated in fp32; FP16: one fp16
+ * product accumulated in fp32.  Every other step runs in fp32 (fp64 for the
+ * fusion statistics). */
+typedef enum { SAL_PREC_FP32 = 0, SAL_PREC_SPLIT_BF16 = 1, SAL_PREC_FP16 = 2 } sal_precision;
+
+/* Window and sampling (Sec. 2 step 1: local cube of side n, sliding window
+ * with more than 50 % overlap).  n in {4, 8, 12, 16}; 1 <= s < n/2. */
+typedef struct {
+    int32_t n;         /* cube side (even) */
+    int32_t s;         /* stride between window centres, voxels */
+    int32_t window;    /* sal_window */
+    int32_t precision; /* sal_precision */
+} sal_spec;
+
+/* Directional center-surround stencil (Sec. 2 step 4, Eq. 3 and Fig. 4).
+ * offsets: host int32 [q][3] (dt, dil, dxl) in voxels, each a multiple of s,
+ * not all zero; 1 <= q <= SAL_MAX_STENCIL.  weights: host float [q], or NULL
+ * for Gaussian weights exp(-|o|^2 / 2d^2) (d = the stencil's Chebyshev reach)
+ * scaled to mean 1.  literal = 0 puts the weight outside the modulus,
+ * w |E(c) - E(c+o)|; literal = 1 keeps Eq. 3 as printed, |E(c) - w E(c+o)|. */
+#define SAL_MAX_STENCIL 64
+typedef struct {
+    int32_t q;
+    const int32_t* offsets;
+    const float* weights;
+    int32_t literal;
+} sal_stencil;
+
+typedef enum { SAL_FUSE_EQUAL = 0, SAL_FUSE_FIXED = 1, SAL_FUSE_ADAPT_LS = 2 } sal_fusion_mode;
+
+/* Fusion of the three directional maps (Sec. 2 step 5, Eq. 4).  EQUAL: 1/3
+ * each; FIXED: w_fixed (the "empirical" template); ADAPT_LS: the
+ * least-squares weights W = (G + delta I)^-1 p, G = sum u u^T, p = sum u D
+ * over the masked grid points, u = (S_t, S_x, S_y) -- the fixed point the
+ * paper's LMS/NLMS/RLS adaptation converges to.  A Gram matrix that is not
+ * numerically positive definite falls back to EQUAL and raises the status
+ * word (see sal_fuse). */
+typedef struct {
+    int32_t mode;
+    double w_fixed[3];
+    double delta; /* >= 0 */
+} sal_fusion;
+
+/* Human-readable message of the last failed call on this thread. */
+const char* sal_last_error(void);
+
+/* Library version string. */
+const char* sal_version(void);
+
+/* Grid extent along an axis of N voxels: ceil(N / s). */
+int64_t sal_grid_extent(int64_t N, int32_t s);
+
+/*
+ * sal_local_spectra -- Sec. 2 step 1, Eq. 2.
+ * The full, unnormalised local 3D DFT F(k) = sum_a H(a) V(c - n/2 + a)
+ * e^{-2 pi i k.a/n} at cnt arbitrary voxel centres.
+ *   V        device float [T][IL][XL]
+ *   centers  device int32 [cnt][3] voxel coordinates (t, il, xl), each inside the volume
+ *   F_out    device float [cnt][n][n][n][2]: bins (kt, ki, kx) unshifted, interleaved re/im
+ * spec->precision is ignored (fp32).  Intended for checks; cnt may be 0.
+ */
+sal_status sal_local_spectra(const float* V, int64_t T, int64_t IL, int64_t XL, const sal_spec* spec,
+                             const int32_t* centers, int64_t cnt, float* F_out, sal_stream stream);
+
+/*
+ * sal_project -- Sec. 2 steps 1-3, Eq. 1-2.
+ * Features E_m(g) = n^-3 sum_{k != 0} alpha_m(k) |F_g(k)| with
+ * alpha_t = sqrt(ki^2 + kx^2)/|k|, alpha_x = sqrt(kt^2 + ki^2)/|k|,
+ * alpha_y = sqrt(kt^2 + kx^2)/|k| (signed bin frequencies; the DC bin, the
+ * centre of the spectral cube, is not computed).
+ *   V      device float [T][IL][XL]
+ *   E_out  device float [3][Tg][ILg][XLg]
+ */
+sal_status sal_project(const float* V, int64_t T, int64_t IL, int64_t XL, const sal_spec* spec, float* E_out,
+                       sal_stream stream);
+
+/*
+ * sal_center_surround -- Sec. 2 step 4, Eq. 3.
+ * S_m(g) = (1/Q_g) sum over in-grid neighbours g + o/s of w_o |E_m(g) - E_m(g + o/s)|
+ * (or the literal form), Q_g = the number of in-grid neighbours (S = 0 if none).
+ *   E       device float [3][Tg][ILg][XLg]
+ *   Sm_out  device float [3][Tg][ILg][XLg] (must not alias E)
+ */
+sal_status sal_center_surround(const float* E, int64_t Tg, int64_t ILg, int64_t XLg, int32_t s,
+                               const sal_stencil* stencil, float* Sm_out, sal_stream stream);
+
+/*
+ * sal_fuse -- Sec. 2 step 5, Eq. 4.
+ * Weights W (per fusion->mode) and the full-resolution map
+ * S(v) = sum_m W_m S_m(g(v)), g(v) the nearest grid centre (ties to the lower).
+ *   Sm      device float [3][Tg][ILg][XLg]
+ *   D       device float [Tg][ILg][XLg] desired map (ADAPT_LS only, else ignored)
+ *   mask    device uint8 [Tg][ILg][XLg] points used for the fit, or NULL for all
+ *   W_out   device double [4]: W_t, W_x, W_y, then the status word (0, or 1 if
+ *           ADAPT_LS fell back to equal weights)
+ *   S_out   device float [T][IL][XL]
+ *   ws      device workspace of at least sal_fuse_workspace_size() bytes (ADAPT_LS)
+ */
+size_t sal_fuse_workspace_size(int64_t Tg, int64_t ILg, int64_t XLg);
+sal_status sal_fuse(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion* fusion, const float* D,
+                    const uint8_t* mask, int64_t T, int64_t IL, int64_t XL, int32_t s, double* W_out, float* S_out,
+                    void* ws, size_t ws_bytes, sal_stream stream);
+
+/*
+ * sal_backward -- adjoint of the whole path (sal_project, sal_center_surround,
+ * sal_fuse) for the scalar loss L = sum_v gS(v) S(v): gV = dL/dV.  Local
+ * spectra are recomputed from V, never stored.  With ADAPT_LS the weights'
+ * dependence on the maps is differentiated (D is held fixed); where a |.| or
+ * |F| has a kink the subgradient 0 is used.
+ *   V, E, Sm     the forward's inputs and outputs (device)
+ *   W            device double [4] from sal_fuse
+ *   D, mask      as given to sal_fuse
+ *   gS           device float [T][IL][XL]
+ *   gV_out       device float [T][IL][XL]
+ *   ws           device workspace of at least sal_backward_workspace_size() bytes
+ */
+size_t sal_backward_workspace_size(int64_t T, int64_t IL, int64_t XL, const sal_spec* spec);
+sal_status sal_backward(const float* V, int64_t T, int64_t IL, int64_t XL, const sal_spec* spec,
+                        const sal_stencil* stencil, const sal_fusion* fusion, const float* E, const float* Sm,
+                        const double* W, const float* D, const uint8_t* mask, const float* gS, float* gV_out,
+                        void* ws, size_t ws_bytes, sal_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SAL_H */

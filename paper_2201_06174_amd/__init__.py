@@ -1,0 +1,202 @@
+"""MI355X-native seismic saliency (Shafiq, Long, Di, AlRegib, ACI 2021, Sec. 2).
+
+Thin PyTorch-facing binding of libsal: it checks tensors, passes their device
+pointers and torch's current HIP stream to the C ABI, and nothing else -- all
+arithmetic runs in the library's HIP kernels.  There is no CPU path: calling
+any operation without the built library or without a GPU raises.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+from . import _lib
+
+__all__ = ["Config", "local_spectra", "project", "center_surround", "fuse", "saliency", "backward", "SaliencyFn",
+           "grid_shape", "fuse_workspace_size", "backward_workspace_size"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def grid_shape(shape, s):
+    return tuple(-(-int(N) // int(s)) for N in shape)
+
+
+def _stream():
+    torch = _torch()
+    return ctypes_void(torch.cuda.current_stream().cuda_stream)
+
+
+def ctypes_void(v):
+    import ctypes
+    return ctypes.c_void_p(int(v))
+
+
+def _ptr(t):
+    return None if t is None else ctypes_void(t.data_ptr())
+
+
+def _need(t, dtype, name, shape=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    return t
+
+
+@dataclass
+class Config:
+    """Parameters of the method besides the volume (Sec. 2)."""
+    n: int = 8
+    s: int = 1
+    window: str = "hann"
+    precision: str = "fp32"
+    offsets: np.ndarray = field(default_factory=lambda: np.zeros((0, 3), np.int32))
+    weights: Optional[np.ndarray] = None
+    literal: bool = False
+    fusion: str = "equal"
+    wfix: Optional[tuple] = None
+    delta: float = 0.0
+
+
+def local_spectra(V, centers, n, window="hann"):
+    """F[cnt][n][n][n] complex64 at voxel centres (device int32 [cnt][3])."""
+    torch = _torch()
+    _need(V, torch.float32, "V")
+    _need(centers, torch.int32, "centers")
+    cnt = centers.shape[0]
+    F = torch.empty((cnt, n, n, n, 2), dtype=torch.float32, device=V.device)
+    spec = _lib.make_spec(n, 1, window)
+    T, IL, XL = V.shape
+    _lib.check(_lib.load().sal_local_spectra(_ptr(V), T, IL, XL, spec, _ptr(centers), cnt, _ptr(F), _stream()))
+    return torch.view_as_complex(F)
+
+
+def project(V, n, s, window="hann", precision="fp32"):
+    """Features E[3][Tg][ILg][XLg] (planes t, x = XL, y = IL)."""
+    torch = _torch()
+    _need(V, torch.float32, "V")
+    if V.dim() != 3:
+        raise ValueError("V must be [T][IL][XL]")
+    T, IL, XL = V.shape
+    E = torch.empty((3,) + grid_shape(V.shape, s), dtype=torch.float32, device=V.device)
+    spec = _lib.make_spec(n, s, window, precision)
+    _lib.check(_lib.load().sal_project(_ptr(V), T, IL, XL, spec, _ptr(E), _stream()))
+    return E
+
+
+def center_surround(E, s, offsets, weights=None, literal=False):
+    torch = _torch()
+    _need(E, torch.float32, "E")
+    if E.dim() != 4 or E.shape[0] != 3:
+        raise ValueError("E must be [3][Tg][ILg][XLg]")
+    Sm = torch.empty_like(E)
+    st, keep = _lib.make_stencil(offsets, weights, literal)
+    _lib.check(_lib.load().sal_center_surround(_ptr(E), E.shape[1], E.shape[2], E.shape[3], s, st, _ptr(Sm),
+                                               _stream()))
+    del keep
+    return Sm
+
+
+def fuse_workspace_size(grid):
+    return int(_lib.load().sal_fuse_workspace_size(*grid))
+
+
+def fuse(Sm, shape, s, mode="equal", wfix=None, delta=0.0, D=None, mask=None, ws=None):
+    """(S[T][IL][XL], W[4] float64: W_t, W_x, W_y, fallback flag)."""
+    torch = _torch()
+    _need(Sm, torch.float32, "Sm")
+    grid = tuple(Sm.shape[1:])
+    if D is not None:
+        _need(D, torch.float32, "D", grid)
+    if mask is not None:
+        _need(mask, torch.uint8, "mask", grid)
+    T, IL, XL = shape
+    S = torch.empty((T, IL, XL), dtype=torch.float32, device=Sm.device)
+    W = torch.empty(4, dtype=torch.float64, device=Sm.device)
+    nbytes = fuse_workspace_size(grid)
+    if ws is None:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=Sm.device)
+    f = _lib.make_fusion(mode, wfix, delta)
+    _lib.check(_lib.load().sal_fuse(_ptr(Sm), grid[0], grid[1], grid[2], f, _ptr(D), _ptr(mask), T, IL, XL, s,
+                                    _ptr(W), _ptr(S), _ptr(ws), ws.numel(), _stream()))
+    return S, W
+
+
+def saliency(V, cfg: Config, D=None, mask=None):
+    """Whole forward path: returns dict(E, Sm, S, W)."""
+    E = project(V, cfg.n, cfg.s, cfg.window, cfg.precision)
+    Sm = center_surround(E, cfg.s, cfg.offsets, cfg.weights, cfg.literal)
+    S, W = fuse(Sm, tuple(V.shape), cfg.s, cfg.fusion, cfg.wfix, cfg.delta, D, mask)
+    return {"E": E, "Sm": Sm, "S": S, "W": W}
+
+
+def backward_workspace_size(shape, n, s, window="hann", precision="fp32"):
+    spec = _lib.make_spec(n, s, window, precision)
+    return int(_lib.load().sal_backward_workspace_size(shape[0], shape[1], shape[2], spec))
+
+
+def backward(V, cfg: Config, E, Sm, W, gS, D=None, mask=None):
+    """gV = d(sum gS * S)/dV through the hand-written adjoint (spectra recomputed)."""
+    torch = _torch()
+    _need(V, torch.float32, "V")
+    _need(gS, torch.float32, "gS", tuple(V.shape))
+    _need(E, torch.float32, "E")
+    _need(Sm, torch.float32, "Sm")
+    _need(W, torch.float64, "W")
+    T, IL, XL = V.shape
+    gV = torch.empty_like(V)
+    spec = _lib.make_spec(cfg.n, cfg.s, cfg.window, cfg.precision)
+    st, keep = _lib.make_stencil(cfg.offsets, cfg.weights, cfg.literal)
+    f = _lib.make_fusion(cfg.fusion, cfg.wfix, cfg.delta)
+    nbytes = backward_workspace_size(V.shape, cfg.n, cfg.s, cfg.window, cfg.precision)
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=V.device)
+    _lib.check(_lib.load().sal_backward(_ptr(V), T, IL, XL, spec, st, f, _ptr(E), _ptr(Sm), _ptr(W), _ptr(D),
+                                        _ptr(mask), _ptr(gS), _ptr(gV), _ptr(ws), ws.numel(), _stream()))
+    del keep
+    return gV
+
+
+def _make_fn():
+    torch = _torch()
+
+    class SaliencyFn(torch.autograd.Function):
+        """S = saliency(V); backward through libsal's adjoint.  Saves V, E, S_m and W
+        (never the local spectra, which the adjoint recomputes)."""
+
+        @staticmethod
+        def forward(ctx, V, cfg, D=None, mask=None):
+            r = saliency(V, cfg, D, mask)
+            ctx.cfg = cfg
+            ctx.save_for_backward(V, r["E"], r["Sm"], r["W"], D, mask)
+            return r["S"]
+
+        @staticmethod
+        def backward(ctx, gS):
+            V, E, Sm, W, D, mask = ctx.saved_tensors
+            gV = backward(V, ctx.cfg, E, Sm, W, gS.contiguous(), D, mask)
+            return gV, None, None, None
+
+    return SaliencyFn
+
+
+class _Lazy:
+    _fn = None
+
+    def __getattr__(self, item):
+        if _Lazy._fn is None:
+            _Lazy._fn = _make_fn()
+        return getattr(_Lazy._fn, item)
+
+
+SaliencyFn = _Lazy()

@@ -1,0 +1,119 @@
+"""ctypes binding of libsal.so (the C ABI declared in include/sal.h).
+
+Argument marshalling only.  The library must have been built
+(``python -m paper_2201_06174_amd.build``); there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_int64, c_size_t, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsal.so")
+
+SAL_OK = 0
+STATUS_NAMES = {0: "SAL_OK", 1: "SAL_ERR_ARG", 2: "SAL_ERR_SHAPE", 3: "SAL_ERR_UNSUPPORTED", 4: "SAL_ERR_NOMEM",
+                5: "SAL_ERR_DEVICE"}
+WINDOW = {"hann": 0, "rect": 1}
+PRECISION = {"fp32": 0, "split_bf16": 1, "fp16": 2}
+FUSION = {"equal": 0, "fixed": 1, "adapt_ls": 2}
+MAX_STENCIL = 64
+
+
+class SalSpec(ctypes.Structure):
+    _fields_ = [("n", c_int32), ("s", c_int32), ("window", c_int32), ("precision", c_int32)]
+
+
+class SalStencil(ctypes.Structure):
+    _fields_ = [("q", c_int32), ("offsets", POINTER(c_int32)), ("weights", POINTER(c_float)), ("literal", c_int32)]
+
+
+class SalFusion(ctypes.Structure):
+    _fields_ = [("mode", c_int32), ("w_fixed", c_double * 3), ("delta", c_double)]
+
+
+class SalError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(code, str(code)), msg))
+        self.code = code
+
+
+# name -> (restype, argtypes); every entry point of include/sal.h
+SIGNATURES = {
+    "sal_last_error": (c_char_p, []),
+    "sal_version": (c_char_p, []),
+    "sal_grid_extent": (c_int64, [c_int64, c_int32]),
+    "sal_local_spectra": (c_int32, [c_void_p, c_int64, c_int64, c_int64, POINTER(SalSpec), c_void_p, c_int64, c_void_p,
+                                    c_void_p]),
+    "sal_project": (c_int32, [c_void_p, c_int64, c_int64, c_int64, POINTER(SalSpec), c_void_p, c_void_p]),
+    "sal_center_surround": (c_int32, [c_void_p, c_int64, c_int64, c_int64, c_int32, POINTER(SalStencil), c_void_p,
+                                      c_void_p]),
+    "sal_fuse_workspace_size": (c_size_t, [c_int64, c_int64, c_int64]),
+    "sal_fuse": (c_int32, [c_void_p, c_int64, c_int64, c_int64, POINTER(SalFusion), c_void_p, c_void_p, c_int64,
+                           c_int64, c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "sal_backward_workspace_size": (c_size_t, [c_int64, c_int64, c_int64, POINTER(SalSpec)]),
+    "sal_backward": (c_int32, [c_void_p, c_int64, c_int64, c_int64, POINTER(SalSpec), POINTER(SalStencil),
+                               POINTER(SalFusion), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                               c_void_p, c_void_p, c_size_t, c_void_p]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libsal.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libsal.so is not built (run `python -m paper_2201_06174_amd.build`)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            if not hasattr(lib, name):
+                continue
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def exported_symbols():
+    lib = load()
+    return [name for name in SIGNATURES if hasattr(lib, name)]
+
+
+def check(rc):
+    if rc != SAL_OK:
+        msg = load().sal_last_error()
+        raise SalError(rc, msg.decode() if msg else "")
+
+
+def make_stencil(offsets, weights=None, literal=False):
+    """SalStencil plus the host arrays it points to (keep both alive)."""
+    import numpy as np
+    off = np.ascontiguousarray(offsets, dtype=np.int32).reshape(-1, 3)
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float32).reshape(-1)
+    st = SalStencil()
+    st.q = off.shape[0]
+    st.offsets = off.ctypes.data_as(POINTER(c_int32))
+    st.weights = w.ctypes.data_as(POINTER(c_float)) if w is not None else POINTER(c_float)()
+    st.literal = 1 if literal else 0
+    return st, (off, w)
+
+
+def make_fusion(mode="equal", wfix=None, delta=0.0):
+    f = SalFusion()
+    f.mode = FUSION[mode] if isinstance(mode, str) else int(mode)
+    w = [0.0, 0.0, 0.0] if wfix is None else [float(v) for v in wfix]
+    f.w_fixed = (c_double * 3)(*w)
+    f.delta = float(delta)
+    return f
+
+
+def make_spec(n, s, window="hann", precision="fp32"):
+    sp = SalSpec()
+    sp.n, sp.s = int(n), int(s)
+    sp.window = WINDOW[window] if isinstance(window, str) else int(window)
+    sp.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    return sp

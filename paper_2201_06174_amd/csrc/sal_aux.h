@@ -1,0 +1,37 @@
+// sal_aux.h -- launchers of the bandwidth-bound kernels (not part of the ABI).
+#pragma once
+
+#include "sal_internal.h"
+
+namespace sal {
+
+constexpr int kStats = 11;       // G00 G01 G02 G11 G12 G22 p0 p1 p2 sum(D^2) count
+constexpr int kFuseParts = 256;  // fixed number of partial-sum blocks (deterministic reduction)
+
+// Stencil in grid units, passed by value as a kernel argument.
+struct DcsStencil {
+    int q;
+    int literal;
+    int o[SAL_MAX_STENCIL][3];
+    float w[SAL_MAX_STENCIL];
+};
+
+sal_status launch_local_spectra(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int window,
+                                const int32_t* centers, int64_t cnt, float* F, hipStream_t stream);
+sal_status launch_dcs(const float* E, float* S, int64_t Tg, int64_t ILg, int64_t XLg, const DcsStencil& st,
+                      hipStream_t stream);
+sal_status launch_dcs_adjoint(const float* E, const float* gSm, float* gE, int64_t Tg, int64_t ILg, int64_t XLg,
+                              const DcsStencil& st, hipStream_t stream);
+size_t fuse_workspace_bytes();
+sal_status launch_fuse(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion& f, const float* D,
+                       const uint8_t* mask, int64_t T, int64_t IL, int64_t XL, int s, double* W, float* S, double* ws,
+                       hipStream_t stream);
+size_t fuse_adjoint_workspace_bytes();
+sal_status launch_fuse_adjoint(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion& f,
+                               const float* D, const uint8_t* mask, const double* W, const float* gS, int64_t T,
+                               int64_t IL, int64_t XL, int s, float* cell, double* ws, float* gSm,
+                               hipStream_t stream);
+sal_status launch_project_fp32(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s, const Tables* tb,
+                               float* E, hipStream_t stream);
+
+}  // namespace sal

@@ -1,0 +1,464 @@
+// sal_aux.hip -- the bandwidth-bound steps: full local spectra (checks), directional
+// center-surround (Sec. 2 step 4, Eq. 3) and fusion (Sec. 2 step 5, Eq. 4), with
+// their adjoints.
+#include "sal_aux.h"
+
+namespace sal {
+
+// Half-sample reflection, then a clamp that keeps any (invalid) far-off index in bounds.
+__device__ __forceinline__ int64_t reflect_index(int64_t p, int64_t N) {
+    if (p < 0) p = -1 - p;
+    if (p >= N) p = 2 * N - 1 - p;
+    return p < 0 ? 0 : (p >= N ? N - 1 : p);
+}
+
+// ---------------------------------------------------------------- local spectra (Eq. 2)
+// One workgroup per centre: gather the tapered cube into LDS, then three complex
+// DFT passes (xl, il, t), each output a direct n-term sum.
+__global__ __launch_bounds__(256) void k_local_spectra(const float* __restrict__ V, int64_t T, int64_t IL, int64_t XL,
+                                                       int n, int window, const int32_t* __restrict__ centers,
+                                                       float* __restrict__ F) {
+    extern __shared__ float sh[];
+    const int n3 = n * n * n;
+    float* xr = sh;
+    float* xi = sh + n3;
+    float* yr = sh + 2 * n3;
+    float* yi = sh + 3 * n3;
+    float* tw = sh + 4 * n3;  // [n][n][2] cos/sin(2 pi k a / n)
+    float* h = tw + 2 * n * n;
+    const int64_t c = blockIdx.x;
+    const int64_t ct = centers[3 * c], ci = centers[3 * c + 1], cx = centers[3 * c + 2];
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int k = e / n, a = e % n;
+        const int r = (k * a) % n;
+        float sn, cs;
+        sincospif(2.0f * (float)r / (float)n, &sn, &cs);
+        tw[2 * e] = cs;
+        tw[2 * e + 1] = sn;
+    }
+    for (int a = threadIdx.x; a < n; a += blockDim.x) {
+        const float v = sinpif((float)a / (float)n);
+        h[a] = window == SAL_WINDOW_HANN ? v * v : 1.0f;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n3; e += blockDim.x) {
+        const int at = e / (n * n), ai = (e / n) % n, ax = e % n;
+        const int64_t pt = reflect_index(ct - n / 2 + at, T), pi = reflect_index(ci - n / 2 + ai, IL),
+                      px = reflect_index(cx - n / 2 + ax, XL);
+        xr[e] = h[at] * h[ai] * h[ax] * V[(pt * IL + pi) * XL + px];
+        xi[e] = 0.f;
+    }
+    __syncthreads();
+    float *inr = xr, *ini = xi, *outr = yr, *outi = yi;
+    for (int axis = 2; axis >= 0; axis--) {
+        const int stride = axis == 0 ? n * n : (axis == 1 ? n : 1);
+        for (int e = threadIdx.x; e < n3; e += blockDim.x) {
+            const int k = (e / stride) % n;
+            const int base = e - k * stride;
+            float sr = 0.f, si = 0.f;
+            for (int a = 0; a < n; a++) {
+                const float cr = tw[2 * (k * n + a)], cs = -tw[2 * (k * n + a) + 1];
+                const float vr = inr[base + a * stride], vi = ini[base + a * stride];
+                sr = fmaf(vr, cr, fmaf(-vi, cs, sr));
+                si = fmaf(vr, cs, fmaf(vi, cr, si));
+            }
+            outr[e] = sr;
+            outi[e] = si;
+        }
+        __syncthreads();
+        float* t;
+        t = inr; inr = outr; outr = t;
+        t = ini; ini = outi; outi = t;
+    }
+    for (int e = threadIdx.x; e < n3; e += blockDim.x) {
+        F[(c * n3 + e) * 2] = inr[e];
+        F[(c * n3 + e) * 2 + 1] = ini[e];
+    }
+}
+
+sal_status launch_local_spectra(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int window,
+                                const int32_t* centers, int64_t cnt, float* F, hipStream_t stream) {
+    if (cnt == 0) return SAL_OK;
+    const size_t lds = sizeof(float) * (4 * (size_t)n * n * n + 2 * n * n + n);
+    static bool attr = false;
+    if (!attr) {
+        sal_status st = check_hip(hipFuncSetAttribute((const void*)k_local_spectra,
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024),
+                                  "hipFuncSetAttribute(local_spectra)");
+        if (st) return st;
+        attr = true;
+    }
+    for (int64_t off = 0; off < cnt; off += (1 << 30)) {
+        const int64_t m = cnt - off < (1 << 30) ? cnt - off : (1 << 30);
+        hipLaunchKernelGGL(k_local_spectra, dim3((unsigned)m), dim3(256), lds, stream, V, T, IL, XL, n, window,
+                           centers + 3 * off, F + off * 2 * (int64_t)n * n * n);
+        sal_status st = check_hip(hipGetLastError(), "launch k_local_spectra");
+        if (st) return st;
+    }
+    return SAL_OK;
+}
+
+// ---------------------------------------------------------------- center-surround (Eq. 3)
+
+__global__ __launch_bounds__(256) void k_dcs(const float* __restrict__ E, float* __restrict__ S, int64_t Tg,
+                                             int64_t ILg, int64_t XLg, DcsStencil st) {
+    const int64_t G = Tg * ILg * XLg;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= G) return;
+    const int64_t gx = j % XLg, gi = (j / XLg) % ILg, gt = j / (XLg * ILg);
+    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
+    const float e0 = E[j], e1 = E[G + j], e2 = E[2 * G + j];
+    int Q = 0;
+    for (int k = 0; k < st.q; k++) {
+        const int64_t nt = gt + st.o[k][0], ni = gi + st.o[k][1], nx = gx + st.o[k][2];
+        if (nt < 0 || nt >= Tg || ni < 0 || ni >= ILg || nx < 0 || nx >= XLg) continue;
+        const int64_t jn = (nt * ILg + ni) * XLg + nx;
+        const float w = st.w[k];
+        if (st.literal) {
+            acc0 += fabsf(e0 - w * E[jn]);
+            acc1 += fabsf(e1 - w * E[G + jn]);
+            acc2 += fabsf(e2 - w * E[2 * G + jn]);
+        } else {
+            acc0 += w * fabsf(e0 - E[jn]);
+            acc1 += w * fabsf(e1 - E[G + jn]);
+            acc2 += w * fabsf(e2 - E[2 * G + jn]);
+        }
+        Q++;
+    }
+    S[j] = Q ? acc0 / (float)Q : 0.f;
+    S[G + j] = Q ? acc1 / (float)Q : 0.f;
+    S[2 * G + j] = Q ? acc2 / (float)Q : 0.f;
+}
+
+sal_status launch_dcs(const float* E, float* S, int64_t Tg, int64_t ILg, int64_t XLg, const DcsStencil& st,
+                      hipStream_t stream) {
+    const int64_t G = Tg * ILg * XLg;
+    if (G == 0) return SAL_OK;
+    const int64_t blocks = (G + 255) / 256;
+    hipLaunchKernelGGL(k_dcs, dim3((unsigned)blocks), dim3(256), 0, stream, E, S, Tg, ILg, XLg, st);
+    return check_hip(hipGetLastError(), "launch k_dcs");
+}
+
+// Adjoint of Eq. 3 as a gather: each grid point collects its own terms and the
+// terms in which it is the neighbour of g - o.  sgn(0) = 0.
+__global__ __launch_bounds__(256) void k_dcs_adjoint(const float* __restrict__ E, const float* __restrict__ gSm,
+                                                     float* __restrict__ gE, int64_t Tg, int64_t ILg, int64_t XLg,
+                                                     DcsStencil st) {
+    const int64_t G = Tg * ILg * XLg;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= G) return;
+    const int64_t gx = j % XLg, gi = (j / XLg) % ILg, gt = j / (XLg * ILg);
+    auto inside = [&](int64_t a, int64_t b, int64_t c) {
+        return a >= 0 && a < Tg && b >= 0 && b < ILg && c >= 0 && c < XLg;
+    };
+    auto count = [&](int64_t a, int64_t b, int64_t c) {
+        int Q = 0;
+        for (int k = 0; k < st.q; k++) Q += inside(a + st.o[k][0], b + st.o[k][1], c + st.o[k][2]);
+        return Q;
+    };
+    for (int m = 0; m < 3; m++) {
+        const float* Em = E + m * G;
+        const float* gm = gSm + m * G;
+        const float e0 = Em[j];
+        float acc = 0.f;
+        const int Qg = count(gt, gi, gx);
+        if (Qg) {
+            const float cg = gm[j] / (float)Qg;
+            for (int k = 0; k < st.q; k++) {
+                const int64_t nt = gt + st.o[k][0], ni = gi + st.o[k][1], nx = gx + st.o[k][2];
+                if (!inside(nt, ni, nx)) continue;
+                const float e1 = Em[(nt * ILg + ni) * XLg + nx];
+                const float d = st.literal ? e0 - st.w[k] * e1 : e0 - e1;
+                const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
+                acc += cg * (st.literal ? 1.f : st.w[k]) * sg;
+            }
+        }
+        for (int k = 0; k < st.q; k++) {
+            const int64_t pt = gt - st.o[k][0], pi = gi - st.o[k][1], px = gx - st.o[k][2];
+            if (!inside(pt, pi, px)) continue;
+            const int64_t jp = (pt * ILg + pi) * XLg + px;
+            const int Qp = count(pt, pi, px);
+            const float ep = Em[jp];
+            const float d = st.literal ? ep - st.w[k] * e0 : ep - e0;
+            const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
+            acc -= gm[jp] / (float)Qp * st.w[k] * sg;
+        }
+        gE[m * G + j] = acc;
+    }
+}
+
+sal_status launch_dcs_adjoint(const float* E, const float* gSm, float* gE, int64_t Tg, int64_t ILg, int64_t XLg,
+                              const DcsStencil& st, hipStream_t stream) {
+    const int64_t G = Tg * ILg * XLg;
+    if (G == 0) return SAL_OK;
+    hipLaunchKernelGGL(k_dcs_adjoint, dim3((unsigned)((G + 255) / 256)), dim3(256), 0, stream, E, gSm, gE, Tg, ILg,
+                       XLg, st);
+    return check_hip(hipGetLastError(), "launch k_dcs_adjoint");
+}
+
+// ---------------------------------------------------------------- fusion (Eq. 4)
+
+// Per-block FP64 partial sums over the masked grid points of
+// u u^T (6), u D (3), D^2, count, in a fixed order (deterministic).
+__global__ __launch_bounds__(256) void k_fuse_stats(const float* __restrict__ Sm, const float* __restrict__ D,
+                                                    const uint8_t* __restrict__ mask, int64_t G,
+                                                    double* __restrict__ part) {
+    __shared__ double red[256];
+    double st[kStats];
+    for (int k = 0; k < kStats; k++) st[k] = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < G; j += stride) {
+        if (mask && !mask[j]) continue;
+        const double u0 = Sm[j], u1 = Sm[G + j], u2 = Sm[2 * G + j], d = D[j];
+        st[0] += u0 * u0; st[1] += u0 * u1; st[2] += u0 * u2;
+        st[3] += u1 * u1; st[4] += u1 * u2; st[5] += u2 * u2;
+        st[6] += u0 * d; st[7] += u1 * d; st[8] += u2 * d;
+        st[9] += d * d; st[10] += 1.0;
+    }
+    for (int k = 0; k < kStats; k++) {
+        red[threadIdx.x] = st[k];
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kStats + k] = red[0];
+        __syncthreads();
+    }
+}
+
+__device__ int chol3(const double A[9], const double b[3], double x[3]) {
+    double dmax = 0.0;
+    for (int i = 0; i < 3; i++) {
+        if (!isfinite(A[4 * i])) return 1;
+        dmax = A[4 * i] > dmax ? A[4 * i] : dmax;
+    }
+    if (!(dmax > 0.0)) return 1;
+    double L[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int j = 0; j < 3; j++) {
+        double d = A[3 * j + j];
+        for (int k = 0; k < j; k++) d -= L[3 * j + k] * L[3 * j + k];
+        if (!(d > 1e-12 * dmax) || !isfinite(d)) return 1;
+        L[3 * j + j] = sqrt(d);
+        for (int i = j + 1; i < 3; i++) {
+            double v = A[3 * i + j];
+            for (int k = 0; k < j; k++) v -= L[3 * i + k] * L[3 * j + k];
+            L[3 * i + j] = v / L[3 * j + j];
+        }
+    }
+    double y[3];
+    for (int i = 0; i < 3; i++) {
+        double v = b[i];
+        for (int k = 0; k < i; k++) v -= L[3 * i + k] * y[k];
+        y[i] = v / L[3 * i + i];
+    }
+    for (int i = 2; i >= 0; i--) {
+        double v = y[i];
+        for (int k = i + 1; k < 3; k++) v -= L[3 * k + i] * x[k];
+        x[i] = v / L[3 * i + i];
+    }
+    return 0;
+}
+
+// One block: fixed-order reduction of the partials and the 3x3 solve.  Writes
+// W[0..2] and the status word W[3]; also the reduced statistics to stats_out.
+__global__ __launch_bounds__(64) void k_fuse_solve(const double* __restrict__ part, int nparts, int mode,
+                                                   double w0, double w1, double w2, double delta,
+                                                   double* __restrict__ W, double* __restrict__ stats_out) {
+    __shared__ double st[kStats];
+    if (threadIdx.x < kStats && mode == SAL_FUSE_ADAPT_LS) {
+        double s = 0.0;
+        for (int b = 0; b < nparts; b++) s += part[(int64_t)b * kStats + threadIdx.x];
+        st[threadIdx.x] = s;
+        if (stats_out) stats_out[threadIdx.x] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    if (mode == SAL_FUSE_EQUAL) {
+        W[0] = W[1] = W[2] = 1.0 / 3.0;
+        W[3] = 0.0;
+        return;
+    }
+    if (mode == SAL_FUSE_FIXED) {
+        W[0] = w0; W[1] = w1; W[2] = w2;
+        W[3] = 0.0;
+        return;
+    }
+    const double A[9] = {st[0] + delta, st[1], st[2], st[1], st[3] + delta, st[4], st[2], st[4], st[5] + delta};
+    const double b[3] = {st[6], st[7], st[8]};
+    double x[3];
+    if (chol3(A, b, x)) {
+        W[0] = W[1] = W[2] = 1.0 / 3.0;
+        W[3] = 1.0;
+    } else {
+        W[0] = x[0]; W[1] = x[1]; W[2] = x[2];
+        W[3] = 0.0;
+    }
+}
+
+__device__ __forceinline__ int64_t cell_of(int64_t v, int s, int64_t Ng) {
+    const int64_t g = (v + (s - 1) / 2) / s;
+    return g < Ng - 1 ? g : Ng - 1;
+}
+
+// S(v) = sum_m W_m S_m(g(v)); one thread per voxel.
+__global__ __launch_bounds__(256) void k_combine(const float* __restrict__ Sm, const double* __restrict__ W,
+                                                 int64_t Tg, int64_t ILg, int64_t XLg, int64_t T, int64_t IL,
+                                                 int64_t XL, int s, float* __restrict__ S) {
+    const int64_t NV = T * IL * XL;
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= NV) return;
+    const int64_t x = v % XL, i = (v / XL) % IL, t = v / (XL * IL);
+    const int64_t G = Tg * ILg * XLg;
+    const int64_t j = (cell_of(t, s, Tg) * ILg + cell_of(i, s, ILg)) * XLg + cell_of(x, s, XLg);
+    const double r = W[0] * (double)Sm[j] + W[1] * (double)Sm[G + j] + W[2] * (double)Sm[2 * G + j];
+    S[v] = (float)r;
+}
+
+size_t fuse_workspace_bytes() { return sizeof(double) * (kFuseParts * kStats + 16); }
+
+sal_status launch_fuse(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion& f, const float* D,
+                       const uint8_t* mask, int64_t T, int64_t IL, int64_t XL, int s, double* W, float* S, double* ws,
+                       hipStream_t stream) {
+    const int64_t G = Tg * ILg * XLg;
+    if (f.mode == SAL_FUSE_ADAPT_LS) {
+        hipLaunchKernelGGL(k_fuse_stats, dim3(kFuseParts), dim3(256), 0, stream, Sm, D, mask, G, ws);
+        sal_status st = check_hip(hipGetLastError(), "launch k_fuse_stats");
+        if (st) return st;
+    }
+    hipLaunchKernelGGL(k_fuse_solve, dim3(1), dim3(64), 0, stream, ws, kFuseParts, f.mode, f.w_fixed[0], f.w_fixed[1],
+                       f.w_fixed[2], f.delta, W, f.mode == SAL_FUSE_ADAPT_LS ? ws + kFuseParts * kStats : nullptr);
+    sal_status st = check_hip(hipGetLastError(), "launch k_fuse_solve");
+    if (st) return st;
+    const int64_t NV = T * IL * XL;
+    if (NV == 0) return SAL_OK;
+    hipLaunchKernelGGL(k_combine, dim3((unsigned)((NV + 255) / 256)), dim3(256), 0, stream, Sm, W, Tg, ILg, XLg, T, IL,
+                       XL, s, S);
+    return check_hip(hipGetLastError(), "launch k_combine");
+}
+
+// ---------------------------------------------------------------- fusion adjoint
+
+// Cell sums c(g) = sum of gS over the voxels whose nearest centre is g.
+__global__ __launch_bounds__(256) void k_cell_sum(const float* __restrict__ gS, int64_t T, int64_t IL, int64_t XL,
+                                                  int s, int64_t Tg, int64_t ILg, int64_t XLg,
+                                                  float* __restrict__ cell) {
+    const int64_t G = Tg * ILg * XLg;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= G) return;
+    const int64_t gx = j % XLg, gi = (j / XLg) % ILg, gt = j / (XLg * ILg);
+    const int64_t N3[3] = {T, IL, XL}, Ng[3] = {Tg, ILg, XLg}, g3[3] = {gt, gi, gx};
+    int64_t lo[3], hi[3];
+    for (int a = 0; a < 3; a++) {
+        lo[a] = g3[a] * s - (s - 1) / 2;
+        if (lo[a] < 0) lo[a] = 0;
+        hi[a] = (g3[a] == Ng[a] - 1) ? N3[a] - 1 : g3[a] * s + s - 1 - (s - 1) / 2;
+        if (hi[a] > N3[a] - 1) hi[a] = N3[a] - 1;
+    }
+    double acc = 0.0;
+    for (int64_t t = lo[0]; t <= hi[0]; t++)
+        for (int64_t i = lo[1]; i <= hi[1]; i++)
+            for (int64_t x = lo[2]; x <= hi[2]; x++) acc += (double)gS[(t * IL + i) * XL + x];
+    cell[j] = (float)acc;
+}
+
+// Per-block FP64 partials of gW_m = sum_g S_m(g) c(g), and (ADAPT_LS) nothing else:
+// the lambda terms need the solved gW first.
+__global__ __launch_bounds__(256) void k_gw_partials(const float* __restrict__ Sm, const float* __restrict__ cell,
+                                                     int64_t G, double* __restrict__ part) {
+    __shared__ double red[256];
+    double a[3] = {0.0, 0.0, 0.0};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < G; j += stride) {
+        const double c = cell[j];
+        a[0] += (double)Sm[j] * c;
+        a[1] += (double)Sm[G + j] * c;
+        a[2] += (double)Sm[2 * G + j] * c;
+    }
+    for (int k = 0; k < 3; k++) {
+        red[threadIdx.x] = a[k];
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * 3 + k] = red[0];
+        __syncthreads();
+    }
+}
+
+// lambda = (G + delta I)^-1 gW, from the reduced statistics of the forward.
+__global__ __launch_bounds__(64) void k_gw_solve(const double* __restrict__ part, int nparts,
+                                                 const double* __restrict__ stats, double delta,
+                                                 double* __restrict__ lam) {
+    __shared__ double gw[3];
+    if (threadIdx.x < 3) {
+        double s = 0.0;
+        for (int b = 0; b < nparts; b++) s += part[(int64_t)b * 3 + threadIdx.x];
+        gw[threadIdx.x] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double A[9] = {stats[0] + delta, stats[1], stats[2], stats[1], stats[3] + delta, stats[4],
+                         stats[2], stats[4], stats[5] + delta};
+    double x[3] = {0.0, 0.0, 0.0};
+    if (chol3(A, gw, x)) x[0] = x[1] = x[2] = 0.0;
+    lam[0] = x[0]; lam[1] = x[1]; lam[2] = x[2];
+}
+
+// gSm(g) = W_m c(g) (+ on the mask, ADAPT_LS: lambda_m (D - W.u) - W_m (lambda.u)).
+__global__ __launch_bounds__(256) void k_gsm(const float* __restrict__ Sm, const float* __restrict__ cell,
+                                             const double* __restrict__ W, const double* __restrict__ lam,
+                                             const float* __restrict__ D, const uint8_t* __restrict__ mask, int64_t G,
+                                             int adapt, float* __restrict__ gSm) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= G) return;
+    const double c = cell[j];
+    double g[3] = {W[0] * c, W[1] * c, W[2] * c};
+    if (adapt && W[3] == 0.0 && (!mask || mask[j])) {
+        const double u0 = Sm[j], u1 = Sm[G + j], u2 = Sm[2 * G + j];
+        const double r = (double)D[j] - (W[0] * u0 + W[1] * u1 + W[2] * u2);
+        const double lu = lam[0] * u0 + lam[1] * u1 + lam[2] * u2;
+        for (int m = 0; m < 3; m++) g[m] += lam[m] * r - W[m] * lu;
+    }
+    gSm[j] = (float)g[0];
+    gSm[G + j] = (float)g[1];
+    gSm[2 * G + j] = (float)g[2];
+}
+
+sal_status launch_fuse_adjoint(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion& f,
+                               const float* D, const uint8_t* mask, const double* W, const float* gS, int64_t T,
+                               int64_t IL, int64_t XL, int s, float* cell, double* ws, float* gSm,
+                               hipStream_t stream) {
+    const int64_t G = Tg * ILg * XLg;
+    if (G == 0) return SAL_OK;
+    const unsigned blocks = (unsigned)((G + 255) / 256);
+    hipLaunchKernelGGL(k_cell_sum, dim3(blocks), dim3(256), 0, stream, gS, T, IL, XL, s, Tg, ILg, XLg, cell);
+    sal_status st = check_hip(hipGetLastError(), "launch k_cell_sum");
+    if (st) return st;
+    const int adapt = f.mode == SAL_FUSE_ADAPT_LS;
+    double* lam = ws + kFuseParts * kStats + 11;  // after the forward's reduced statistics
+    if (adapt) {
+        // statistics of the forward, recomputed here so the adjoint does not depend on workspace state
+        hipLaunchKernelGGL(k_fuse_stats, dim3(kFuseParts), dim3(256), 0, stream, Sm, D, mask, G, ws);
+        if ((st = check_hip(hipGetLastError(), "launch k_fuse_stats"))) return st;
+        hipLaunchKernelGGL(k_fuse_solve, dim3(1), dim3(64), 0, stream, ws, kFuseParts, (int)SAL_FUSE_ADAPT_LS, 0.0,
+                           0.0, 0.0, f.delta, ws + kFuseParts * kStats + 16 + 3 * kFuseParts,
+                           ws + kFuseParts * kStats);
+        if ((st = check_hip(hipGetLastError(), "launch k_fuse_solve"))) return st;
+        double* gwp = ws + kFuseParts * kStats + 16;
+        hipLaunchKernelGGL(k_gw_partials, dim3(kFuseParts), dim3(256), 0, stream, Sm, cell, G, gwp);
+        if ((st = check_hip(hipGetLastError(), "launch k_gw_partials"))) return st;
+        hipLaunchKernelGGL(k_gw_solve, dim3(1), dim3(64), 0, stream, gwp, kFuseParts, ws + kFuseParts * kStats,
+                           f.delta, lam);
+        if ((st = check_hip(hipGetLastError(), "launch k_gw_solve"))) return st;
+    }
+    hipLaunchKernelGGL(k_gsm, dim3(blocks), dim3(256), 0, stream, Sm, cell, W, lam, D, mask, G, adapt, gSm);
+    return check_hip(hipGetLastError(), "launch k_gsm");
+}
+
+size_t fuse_adjoint_workspace_bytes() {
+    return sizeof(double) * (kFuseParts * kStats + 16 + 3 * kFuseParts + 16);
+}
+
+}  // namespace sal

@@ -1,0 +1,62 @@
+// sal_internal.h -- shared host/device helpers of libsal (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/sal.h"
+
+namespace sal {
+
+// ---------------------------------------------------------------- errors
+
+void set_error(const std::string& msg);
+sal_status fail(sal_status code, const std::string& msg);
+sal_status check_hip(hipError_t e, const char* what);
+
+// ---------------------------------------------------------------- shapes
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Validates n, s, window, precision and the volume extents; returns SAL_OK or an error
+// (with the message set).
+sal_status check_spec(const sal_spec* spec, int64_t T, int64_t IL, int64_t XL);
+
+// ---------------------------------------------------------------- constant tables
+
+// Per (device, n, window) device tables, built once on the host in double and
+// uploaded (the first call for a configuration copies synchronously).
+struct Tables {
+    int n = 0;
+    int window = 0;
+    const float* passA = nullptr;   // [KH][n][2]: h(a) cos(2 pi k a/n), -h(a) sin(2 pi k a/n)
+    const float* mat = nullptr;     // [16][n]: packed taper*DFT rows c0, c_{n/2}, c1, s1, c2, s2, ...
+    const float* wts = nullptr;     // [KH][n][16][4]: bin weights mult(kx) alpha_m / n^3 per packed row
+    const float* inv = nullptr;     // [16 a][16 r]: h(a) * trig row r at sample a (transpose of `mat`), zero padded
+    const uint16_t* mat_hi = nullptr;  // bf16 hi/lo and fp16 forms of `mat`, padded to K = 16 per step
+    const uint16_t* mat_lo = nullptr;
+    const uint16_t* mat_h16 = nullptr;
+};
+
+sal_status get_tables(int n, int window, const Tables** out);
+
+// Packed row r of an n-point transform: its frequency q and whether it is a sine row.
+// Rows: 0 -> cos 0, 1 -> cos n/2, 2q -> cos q, 2q+1 -> sin q (1 <= q < n/2), r >= n -> zero.
+inline void packed_row(int r, int n, int* q, int* is_sin, int* valid) {
+    *valid = r < n;
+    if (r == 0) { *q = 0; *is_sin = 0; }
+    else if (r == 1) { *q = n / 2; *is_sin = 0; }
+    else { *q = r / 2; *is_sin = r & 1; }
+}
+
+// ---------------------------------------------------------------- launch configuration of the fused feature kernel
+
+struct ProjTile {
+    int CT;     // t-centres per tile (<= 8 * CTW)
+    int RT, RI, RX, RXp;
+    size_t lds_bytes;
+};
+
+}  // namespace sal

@@ -1,0 +1,105 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point that include/sal.h declares, and rejects bad arguments on the
+host before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2201_06174_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(sal_[a-z0-9_]+)\s*\(", src))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    declared = _declared()
+    assert "sal_project" in declared and "sal_backward" in declared
+    missing = [n for n in sorted(declared) if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding knows each of them
+    assert declared <= set(_lib.SIGNATURES), sorted(declared - set(_lib.SIGNATURES))
+
+
+def test_version_and_grid_extent():
+    lib = _lib.load()
+    assert lib.sal_version().startswith(b"libsal")
+    assert lib.sal_grid_extent(600, 2) == 300 and lib.sal_grid_extent(7, 3) == 3 and lib.sal_grid_extent(0, 2) == 0
+
+
+def _err(rc):
+    return _lib.STATUS_NAMES[rc]
+
+
+@pytest.mark.parametrize("n,s,window,prec,shape,code", [
+    (10, 1, 0, 0, (32, 32, 32), "SAL_ERR_UNSUPPORTED"),   # valid for the method, not built
+    (7, 1, 0, 0, (32, 32, 32), "SAL_ERR_ARG"),            # odd side
+    (8, 4, 0, 0, (32, 32, 32), "SAL_ERR_ARG"),            # overlap not above 50 %
+    (8, 0, 0, 0, (32, 32, 32), "SAL_ERR_ARG"),
+    (8, 1, 5, 0, (32, 32, 32), "SAL_ERR_ARG"),            # window
+    (8, 1, 0, 9, (32, 32, 32), "SAL_ERR_ARG"),            # precision
+    (16, 2, 0, 0, (7, 32, 32), "SAL_ERR_SHAPE"),          # axis shorter than n/2
+])
+def test_project_rejects_bad_spec(n, s, window, prec, shape, code):
+    lib = _lib.load()
+    sp = _lib.SalSpec(n, s, window, prec)
+    rc = lib.sal_project(ctypes.c_void_p(16), shape[0], shape[1], shape[2], sp, ctypes.c_void_p(16), None)
+    assert _err(rc) == code
+    assert lib.sal_last_error()
+
+
+def test_null_buffers_rejected():
+    lib = _lib.load()
+    sp = _lib.SalSpec(8, 1, 0, 0)
+    assert _err(lib.sal_project(None, 32, 32, 32, sp, ctypes.c_void_p(16), None)) == "SAL_ERR_ARG"
+    assert _err(lib.sal_project(ctypes.c_void_p(16), 32, 32, 32, None, ctypes.c_void_p(16), None)) == "SAL_ERR_ARG"
+
+
+def test_stencil_validation():
+    lib = _lib.load()
+    E, S = ctypes.c_void_p(16), ctypes.c_void_p(32)
+    st, keep = _lib.make_stencil([[1, 0, 0]])
+    assert _err(lib.sal_center_surround(E, 4, 4, 4, 2, st, S, None)) == "SAL_ERR_ARG"  # off the stride-2 grid
+    st, keep = _lib.make_stencil([[0, 0, 0]])
+    assert _err(lib.sal_center_surround(E, 4, 4, 4, 1, st, S, None)) == "SAL_ERR_ARG"  # no direction
+    st, keep = _lib.make_stencil(np.ones((65, 3)))
+    assert _err(lib.sal_center_surround(E, 4, 4, 4, 1, st, S, None)) == "SAL_ERR_ARG"  # too many
+    st, keep = _lib.make_stencil([[1, 0, 0]])
+    assert _err(lib.sal_center_surround(E, 4, 4, 4, 1, st, E, None)) == "SAL_ERR_ARG"  # aliasing
+
+
+def test_fuse_validation():
+    lib = _lib.load()
+    p = ctypes.c_void_p(64)
+    f = _lib.make_fusion("adapt_ls")
+    # ADAPT_LS without a desired map
+    assert _err(lib.sal_fuse(p, 4, 4, 4, f, None, None, 8, 8, 8, 2, p, p, p, 1 << 20, None)) == "SAL_ERR_ARG"
+    # grid extents inconsistent with the volume
+    f = _lib.make_fusion("equal")
+    assert _err(lib.sal_fuse(p, 4, 4, 5, f, None, None, 8, 8, 8, 2, p, p, None, 0, None)) == "SAL_ERR_SHAPE"
+    # workspace too small
+    f = _lib.make_fusion("adapt_ls")
+    assert _err(lib.sal_fuse(p, 4, 4, 4, f, p, None, 8, 8, 8, 2, p, p, p, 8, None)) == "SAL_ERR_NOMEM"
+    f = _lib.make_fusion("adapt_ls", delta=-1.0)
+    assert _err(lib.sal_fuse(p, 4, 4, 4, f, p, None, 8, 8, 8, 2, p, p, p, 1 << 20, None)) == "SAL_ERR_ARG"
+    f = _lib.make_fusion(7)
+    assert _err(lib.sal_fuse(p, 4, 4, 4, f, p, None, 8, 8, 8, 2, p, p, p, 1 << 20, None)) == "SAL_ERR_ARG"
+
+
+def test_python_binding_refuses_cpu_tensors():
+    import torch
+    import paper_2201_06174_amd as sal
+    with pytest.raises(TypeError):
+        sal.project(torch.zeros(8, 8, 8), 8, 1)

@@ -1,0 +1,180 @@
+"""Parity of the HIP forward path with the FP64 oracle (element by element on
+small volumes spanning several tiles with ragged tails; sampled outputs at the
+survey size).  FP32 path bar: max|gpu - oracle| / max|oracle| <= 1e-5 per output."""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2201_06174_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP32 = 1e-5
+
+
+def _rel(x, ref):
+    """max |x - ref| / max |ref|; complex values compared as complex numbers."""
+    x = np.asarray(x)
+    ref = np.asarray(ref)
+    dt = np.complex128 if (np.iscomplexobj(x) or np.iscomplexobj(ref)) else np.float64
+    x, ref = x.astype(dt), ref.astype(dt)
+    return float(np.max(np.abs(x - ref)) / max(np.max(np.abs(ref)), 1e-30))
+
+
+@pytest.fixture(scope="module")
+def torch_sal():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2201_06174_amd as sal
+    return torch, sal
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("n", [4, 8, 12, 16])
+def test_local_spectra(torch_sal, n):
+    torch, sal = torch_sal
+    print("local_spectra n=%d" % n, flush=True)
+    V = np.random.default_rng(n).standard_normal((20, 19, 18)).astype(np.float32)
+    c = np.array([[0, 0, 0], [19, 18, 17], [10, 9, 8], [3, 17, 1], [n // 2, 2, 16]], np.int32)
+    for window in ("hann", "rect"):
+        F = sal.local_spectra(_dev(torch, V), _dev(torch, c), n, window).cpu().numpy()
+        ref = orc.local_spectra(V, n, window, c.astype(np.int64))
+        assert _rel(F, ref) < TOL_FP32
+
+
+CASES = [
+    # (shape, n, s, window)
+    ((37, 29, 23), 8, 1, "hann"),
+    ((30, 41, 27), 8, 2, "hann"),
+    ((21, 19, 26), 8, 3, "rect"),
+    ((45, 26, 35), 16, 2, "hann"),
+    ((17, 23, 19), 16, 1, "hann"),
+    ((36, 31, 29), 12, 2, "hann"),
+    ((40, 9, 13), 4, 1, "hann"),
+    ((8, 8, 8), 16, 7, "hann"),      # each axis exactly n/2 long, largest stride
+    ((4, 5, 6), 8, 1, "rect"),       # minimal extents
+]
+
+
+@pytest.mark.parametrize("shape,n,s,window", CASES)
+def test_project_matches_oracle(torch_sal, shape, n, s, window):
+    torch, sal = torch_sal
+    print("project shape=%s n=%d s=%d %s" % (shape, n, s, window), flush=True)
+    V = np.random.default_rng(sum(shape) + n + s).standard_normal(shape).astype(np.float32)
+    E = sal.project(_dev(torch, V), n, s, window).cpu().numpy()
+    ref = orc.features(V, n, s, window)
+    assert E.shape == ref.shape
+    for m in range(3):
+        assert _rel(E[m], ref[m]) < TOL_FP32, (m, _rel(E[m], ref[m]))
+
+
+def test_project_constant_and_plane_wave(torch_sal):
+    torch, sal = torch_sal
+    V = np.full((24, 20, 18), 1.5, np.float32)
+    E = sal.project(_dev(torch, V), 8, 1).cpu().numpy()
+    closed = 1.5 * (3 / 8 + np.sqrt(2) / 8 + np.sqrt(6) / 24)
+    assert np.max(np.abs(E - closed)) < 1e-5 * closed
+    n, a, N = 16, 3, 48
+    t = np.arange(N)
+    V = np.broadcast_to(np.cos(2 * np.pi * a * t / n + 0.2)[:, None, None], (N, N, N)).astype(np.float32)
+    E = sal.project(_dev(torch, np.ascontiguousarray(V)), n, 2).cpu().numpy()
+    g = E[:, 8:16, 8:16, 8:16]  # interior windows
+    assert np.max(np.abs(g[0] - 0.275493)) < 2e-6 and np.max(np.abs(g[1:] - 0.972097)) < 2e-6
+
+
+@pytest.mark.parametrize("s,off,literal", [(1, synth.axis_stencil(2), False), (2, synth.cube_stencil(4), False),
+                                           (2, synth.cube_stencil(2), True), (1, np.array([[0, 40, 0]]), False)])
+def test_center_surround_matches_oracle(torch_sal, s, off, literal):
+    torch, sal = torch_sal
+    E = np.random.default_rng(5).uniform(size=(3, 13, 11, 17)).astype(np.float32)
+    S = sal.center_surround(_dev(torch, E), s, off, None, literal).cpu().numpy()
+    ref = orc.dcs(E.astype(np.float64), s, off, None, literal)
+    assert _rel(S, ref) < TOL_FP32
+
+
+@pytest.mark.parametrize("mode", ["equal", "fixed", "adapt_ls"])
+@pytest.mark.parametrize("s", [1, 2, 3])
+def test_fuse_matches_oracle(torch_sal, mode, s):
+    torch, sal = torch_sal
+    shape = (19, 14, 23)
+    gs = orc.grid_shape(shape, s)
+    rng = np.random.default_rng(6 + s)
+    Sm = rng.uniform(size=(3,) + gs).astype(np.float32)
+    D = (0.5 * Sm[0] + 0.25 * Sm[2] + 0.1 * rng.uniform(size=gs)).astype(np.float32)
+    mask = (rng.uniform(size=gs) < 0.4).astype(np.uint8)
+    wfix = (0.6, 0.3, 0.1)
+    S, W = sal.fuse(_dev(torch, Sm), shape, s, mode, wfix, 1e-6, _dev(torch, D), _dev(torch, mask))
+    Wr, fb, _ = orc.fusion_weights(Sm.astype(np.float64), D, mask, mode, wfix, 1e-6)
+    W = W.cpu().numpy()
+    assert W[3] == fb == 0
+    assert np.max(np.abs(W[:3] - Wr)) < 1e-9 * max(1.0, np.abs(Wr).max())
+    ref = orc.combine(Sm.astype(np.float64), Wr, shape, s)
+    assert _rel(S.cpu().numpy(), ref) < TOL_FP32
+
+
+def test_fuse_fallback_flag(torch_sal):
+    torch, sal = torch_sal
+    Sm = np.ones((3, 4, 4, 4), np.float32)
+    S, W = sal.fuse(_dev(torch, Sm), (8, 8, 8), 2, "adapt_ls", None, 0.0, _dev(torch, np.ones((4, 4, 4), np.float32)))
+    W = W.cpu().numpy()
+    assert W[3] == 1.0 and np.allclose(W[:3], 1 / 3)
+
+
+def test_small_workload_end_to_end(torch_sal):
+    """64^3, window 8^3 Hann, stride 1, six neighbours at offset 4: every
+    output of the whole forward against the oracle, equal and adapted fusion."""
+    torch, sal = torch_sal
+    w = synth.workload("small")
+    V, M = synth.make_volume(w.spec, w.seed, with_mask=True)
+    D, mask = synth.desired_map(M, w.s)
+    for fusion in ("equal", "adapt_ls"):
+        cfg = sal.Config(n=w.n, s=w.s, offsets=w.offsets, fusion=fusion, delta=1e-6)
+        r = sal.saliency(_dev(torch, V), cfg, _dev(torch, D), _dev(torch, mask))
+        p = orc.Params(n=w.n, s=w.s, offsets=w.offsets, fusion=fusion, delta=1e-6, D=D, mask=mask)
+        o = orc.forward(V, p)
+        for m in range(3):
+            assert _rel(r["E"][m].cpu().numpy(), o["E"][m]) < TOL_FP32
+            assert _rel(r["Sm"][m].cpu().numpy(), o["Sm"][m]) < TOL_FP32
+        W = r["W"].cpu().numpy()
+        assert W[3] == o["fallback"] == 0
+        assert np.max(np.abs(W[:3] - o["W"])) < 1e-5 * np.abs(o["W"]).max()
+        assert _rel(r["S"].cpu().numpy(), o["S"]) < TOL_FP32
+
+
+def test_survey_workload_sampled(torch_sal):
+    """256 x 400 x 600, window 16^3 Hann, stride 2, 26 neighbours at offset 8:
+    E and S_m at sampled grid points (interior, faces, corners) against the
+    oracle computed point by point; W through the normal equations of the fit;
+    S through its definition from the GPU's S_m and W."""
+    torch, sal = torch_sal
+    w = synth.workload("survey")
+    V, M = synth.make_volume(w.spec, w.seed, with_mask=True)
+    D, mask = synth.desired_map(M, w.s)
+    cfg = sal.Config(n=w.n, s=w.s, offsets=w.offsets, fusion="adapt_ls", delta=1e-6)
+    r = sal.saliency(_dev(torch, V), cfg, _dev(torch, D), _dev(torch, mask))
+    E, Sm, S, W = (r[k].cpu().numpy() for k in ("E", "Sm", "S", "W"))
+    gs = Sm.shape[1:]
+    rng = np.random.default_rng(7)
+    g = np.stack([rng.integers(0, N, 48) for N in gs], 1)
+    corners = np.array([[a, b, c] for a in (0, gs[0] - 1) for b in (0, gs[1] - 1) for c in (0, gs[2] - 1)])
+    g = np.concatenate([g, corners, [[0, gs[1] // 2, 5], [gs[0] // 2, 0, gs[2] - 1]]]).astype(np.int64)
+    Sr, Er = orc.saliency_at(V, w.n, w.s, "hann", w.offsets, None, False, g)
+    Eg = E[:, g[:, 0], g[:, 1], g[:, 2]].T
+    Sg = Sm[:, g[:, 0], g[:, 1], g[:, 2]].T
+    assert _rel(Eg, Er) < TOL_FP32
+    assert _rel(Sg, Sr) < TOL_FP32
+    # W: residual of the normal equations of the masked fit, in FP64 on the host
+    U = Sm.reshape(3, -1).T.astype(np.float64)[mask.reshape(-1) == 1]
+    d = D.reshape(-1)[mask.reshape(-1) == 1].astype(np.float64)
+    assert W[3] == 0
+    Wr = np.linalg.solve(U.T @ U + 1e-6 * np.eye(3), U.T @ d)
+    assert np.max(np.abs(W[:3] - Wr)) < 1e-8 * np.abs(Wr).max()
+    # S from its definition at sampled voxels
+    v = np.stack([rng.integers(0, N, 4096) for N in V.shape], 1)
+    gv = np.minimum(v // w.s, np.array(gs) - 1)
+    ref = (W[:3, None] * Sm[:, gv[:, 0], gv[:, 1], gv[:, 2]].astype(np.float64)).sum(0)
+    assert _rel(S[v[:, 0], v[:, 1], v[:, 2]], ref) < TOL_FP32
