@@ -1,0 +1,195 @@
+"""Benchmark of the saliency hot path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload survey|salt|small|grad]
+                    [--precision fp32|split_bf16|fp16] [--no-cpu-baseline] [--no-extra]
+
+One step = one whole forward pass (local spectra + projection features,
+directional center-surround, adapted fusion and the full-resolution combine)
+over one synthetic volume already resident in HBM.  Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Published MI355X peaks used as roofline denominators
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
+PEAK_HBM_GBS = 8000.0
+
+
+def algorithmic_flops_per_window(n: int) -> float:
+    """Real-input 3D FFT of one n^3 local cube: 2.5 n^3 log2(n^3) flops."""
+    return 2.5 * n ** 3 * math.log2(n ** 3)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="survey")
+    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--fusion", default="adapt_ls")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+class Pipeline:
+    """Preallocated buffers and direct C-ABI calls (no allocation in the timed loop)."""
+
+    def __init__(self, torch, lib, V, w, precision, fusion, D, mask):
+        from paper_2201_06174_amd import _lib, grid_shape
+        self.torch, self.lib, self._lib = torch, lib, _lib
+        self.V = V
+        self.shape = tuple(V.shape)
+        self.grid = grid_shape(self.shape, w.s)
+        dev = V.device
+        self.E = torch.empty((3,) + self.grid, dtype=torch.float32, device=dev)
+        self.Sm = torch.empty_like(self.E)
+        self.S = torch.empty(self.shape, dtype=torch.float32, device=dev)
+        self.W = torch.empty(4, dtype=torch.float64, device=dev)
+        nb = int(lib.sal_fuse_workspace_size(*self.grid))
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+        self.spec = _lib.make_spec(w.n, w.s, "hann", precision)
+        self.stencil, self._keep = _lib.make_stencil(w.offsets)
+        self.fusion = _lib.make_fusion(fusion, None, 1e-6)
+        self.D, self.mask = D, mask
+        self.s = w.s
+
+    def stream(self):
+        return ctypes.c_void_p(self.torch.cuda.current_stream().cuda_stream)
+
+    def project(self):
+        T, IL, XL = self.shape
+        self._lib.check(self.lib.sal_project(ctypes.c_void_p(self.V.data_ptr()), T, IL, XL, self.spec,
+                                             ctypes.c_void_p(self.E.data_ptr()), self.stream()))
+
+    def rest(self):
+        T, IL, XL = self.shape
+        Tg, ILg, XLg = self.grid
+        st = self.stream()
+        self._lib.check(self.lib.sal_center_surround(ctypes.c_void_p(self.E.data_ptr()), Tg, ILg, XLg, self.s,
+                                                     self.stencil, ctypes.c_void_p(self.Sm.data_ptr()), st))
+        self._lib.check(self.lib.sal_fuse(ctypes.c_void_p(self.Sm.data_ptr()), Tg, ILg, XLg, self.fusion,
+                                          ctypes.c_void_p(self.D.data_ptr()), ctypes.c_void_p(self.mask.data_ptr()),
+                                          T, IL, XL, self.s, ctypes.c_void_p(self.W.data_ptr()),
+                                          ctypes.c_void_p(self.S.data_ptr()), ctypes.c_void_p(self.ws.data_ptr()),
+                                          self.ws.numel(), st))
+
+
+def time_forward(torch, pipe, steps, warmup):
+    for _ in range(warmup):
+        pipe.project()
+        pipe.rest()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for k in range(steps):
+        ev[k][0].record()
+        pipe.project()
+        ev[k][1].record()
+        pipe.rest()
+    end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = start.elapsed_time(end)
+    kern_ms = [a.elapsed_time(b) for a, b in ev]
+    return total_ms / steps, float(np.mean(kern_ms)), wall
+
+
+def cpu_baseline(V, w, seconds):
+    """The FP64 oracle on a bounded sample of windows of the same volume, on all host cores."""
+    from oracle import oracle as orc
+    gs = orc.grid_shape(V.shape, w.s)
+    rng = np.random.default_rng(123)
+    nth = orc.max_threads()
+    cnt = 64
+    elapsed = 0.0
+    total_windows = 0
+    while True:
+        g = np.stack([rng.integers(0, N, cnt) for N in gs], 1).astype(np.int64)
+        t0 = time.perf_counter()
+        orc.features_at(V, w.n, w.s, "hann", g, nthreads=nth)
+        dt = time.perf_counter() - t0
+        elapsed += dt
+        total_windows += cnt
+        if elapsed >= seconds or cnt >= 1 << 22:
+            break
+        cnt = int(min(max(cnt * 2, cnt * (seconds - elapsed) / max(dt, 1e-3) * 0.9), 1 << 22))
+    voxels_per_window = w.s ** 3
+    mvox = total_windows * voxels_per_window / elapsed / 1e6
+    return {"value": round(mvox, 4), "unit": "Mvoxel/s", "cores": nth, "kind": "oracle",
+            "sample": "%d random windows (features of %d^3 Hann cubes, stride %d) of the %s volume, %.1f s; "
+                      "each window stands for s^3 output voxels" % (total_windows, w.n, w.s, "x".join(
+                          str(v) for v in V.shape), elapsed)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (requested --gpus %d)" % args.gpus)
+        sys.exit(2)
+    import torch
+    from paper_2201_06174_amd import _lib, synth
+    lib = _lib.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = synth.workload(args.workload)
+    V, M = synth.make_volume(w.spec, w.seed, with_mask=True)
+    D, mask = synth.desired_map(M, w.s)
+    dev = torch.device("cuda:0")
+    Vd = torch.from_numpy(V).to(dev)
+    Dd = torch.from_numpy(D).to(dev)
+    Md = torch.from_numpy(mask).to(dev)
+    pipe = Pipeline(torch, lib, Vd, w, args.precision, args.fusion, Dd, Md)
+    ms, kern_ms, wall = time_forward(torch, pipe, args.steps, args.warmup)
+    nvox = int(np.prod(V.shape))
+    nwin = int(np.prod(pipe.grid))
+    value = nvox / (ms * 1e-3) / 1e6
+    alg = algorithmic_flops_per_window(w.n) * nwin
+    achieved = alg / (kern_ms * 1e-3) / 1e12
+    peak = PEAK_FP32_MFMA_TFLOPS if args.precision == "fp32" else PEAK_BF16_MFMA_TFLOPS
+    out = {
+        "metric": "Mvoxel/s saliency fwd (FP32 vs split-BF16 @<=1e-3 rel) and fwd+bwd on 1 GPU",
+        "value": round(value, 3),
+        "unit": "Mvoxel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "%s: %s volume, window %d^3 Hann, stride %d, %d neighbours, %s fusion" % (
+            args.workload, "x".join(str(v) for v in V.shape), w.n, w.s, len(w.offsets), args.fusion),
+            "precision": args.precision, "voxels": nvox, "windows": nwin},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel": "k_project_fp32 (sal_project)", "kernel_ms": round(kern_ms, 4),
+                     "flops_per_window": algorithmic_flops_per_window(w.n)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(V, w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -100,7 +100,8 @@ sal_status sal_project(const float* V, int64_t T, int64_t IL, int64_t XL, const 
         case SAL_PREC_FP32:
             return launch_project_fp32(V, T, IL, XL, spec->n, spec->s, tb, E_out, (hipStream_t)stream);
         default:
-            return fail(SAL_ERR_UNSUPPORTED, "precision not built yet");
+            return launch_project_lowp(V, T, IL, XL, spec->n, spec->s, spec->precision, tb, E_out,
+                                       (hipStream_t)stream);
     }
 }
 

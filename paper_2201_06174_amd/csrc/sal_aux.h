@@ -16,6 +16,9 @@ struct DcsStencil {
     float w[SAL_MAX_STENCIL];
 };
 
+// Resolves a stencil (validation, Gaussian default weights) into grid units.
+sal_status make_stencil(const sal_stencil* st, int s, DcsStencil* out);
+
 sal_status launch_local_spectra(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int window,
                                 const int32_t* centers, int64_t cnt, float* F, hipStream_t stream);
 sal_status launch_dcs(const float* E, float* S, int64_t Tg, int64_t ILg, int64_t XLg, const DcsStencil& st,
@@ -31,6 +34,8 @@ sal_status launch_fuse_adjoint(const float* Sm, int64_t Tg, int64_t ILg, int64_t
                                const float* D, const uint8_t* mask, const double* W, const float* gS, int64_t T,
                                int64_t IL, int64_t XL, int s, float* cell, double* ws, float* gSm,
                                hipStream_t stream);
+sal_status launch_project_lowp(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s, int precision,
+                               const Tables* tb, float* E, hipStream_t stream);
 sal_status launch_project_fp32(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s, const Tables* tb,
                                float* E, hipStream_t stream);
 

@@ -1,16 +1,543 @@
-// sal_backward.hip -- adjoint of the saliency path (placeholder until the adjoint kernels land).
+// sal_backward.hip -- hand-written adjoint of the saliency path.
+//
+// For the loss L = sum_v gS(v) S(v):
+//   1. fusion adjoint (Eq. 4): gS_m(g) = W_m c(g), c(g) the cell sum of gS, plus,
+//      for adapted weights, the terms through W = (G + delta I)^-1 p;
+//   2. center-surround adjoint (Eq. 3), a gather with sgn(0) = 0;
+//   3. spectral adjoint (Eq. 1-2 and the feature step): per window, recompute
+//      F (the same three passes as the forward), form
+//      Y(k) = c(k) F(k)/|F(k)| with c(k) = sum_m gE_m mult(kx) alpha_m(k) / n^3,
+//      and run the transposed passes: inverse DFT along t with the taper and an
+//      overlap-add over the window centres, the same along il, and along xl the
+//      real part accumulated in registers over every kx.  Local spectra are
+//      never stored.
+// Each workgroup writes the unfolded contribution of its tile region to a
+// workspace; a gather kernel then sums, for every voxel, the regions that cover
+// it directly or through the border reflection, in a fixed order (no atomics,
+// bitwise reproducible).
 #include "sal_aux.h"
+
+namespace sal {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int64_t reflect_clamp_b(int64_t p, int64_t N) {
+    if (p < 0) p = -1 - p;
+    if (p >= N) p = 2 * N - 1 - p;
+    return p < 0 ? 0 : (p >= N ? N - 1 : p);
+}
+
+__device__ __forceinline__ f4 mfma4b(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ void lds_fence() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+constexpr int kAdjCT = 8;  // t-centres per adjoint tile (one per wave in the t-slot loops)
+
+struct AdjParams {
+    const float* V;
+    int64_t T, IL, XL;
+    int64_t Tg, ILg, XLg;
+    int64_t tilesT, tilesI, tilesX, ntiles;
+    const float* gE;
+    const float* passA;
+    const float* mat;
+    const float* inv;
+    const float4* wts;
+    float* part;  // [ntiles][RT][RI][RX]
+};
+
+template <int N, int S>
+struct AdjGeom {
+    static constexpr int CT = kAdjCT;
+    static constexpr int KH = N / 2 + 1;
+    static constexpr int NK = N / 4;
+    static constexpr int RT = (CT - 1) * S + N;
+    static constexpr int RI = 3 * S + N;
+    static constexpr int RX = 3 * S + N;
+    static constexpr int RXp = RX | 1;
+    static constexpr int ROWS = (RT * RI + 511) / 512;
+    static constexpr size_t lds_floats = (size_t)RT * RI * RXp + 2 * (size_t)RT * RI * 4 + 2 * (size_t)N * RT * 16 +
+                                         (size_t)KH * N * 2;
+    static_assert(lds_floats * sizeof(float) <= 160 * 1024, "adjoint tile exceeds the LDS");
+};
+
+template <int N, int S>
+__global__ __launch_bounds__(512) void k_spectral_adjoint(AdjParams p) {
+    using Gm = AdjGeom<N, S>;
+    constexpr int CT = Gm::CT, KH = Gm::KH, NK = Gm::NK, RT = Gm::RT, RI = Gm::RI, RX = Gm::RX, RXp = Gm::RXp,
+                  ROWS = Gm::ROWS;
+    extern __shared__ float lds[];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int col = lane & 15;
+    const int grp = lane >> 4;
+
+    const int64_t per = (p.ntiles + 7) / 8;
+    const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (tile >= p.ntiles) return;
+    const int64_t tx = tile % p.tilesX;
+    const int64_t ti = (tile / p.tilesX) % p.tilesI;
+    const int64_t tt = tile / (p.tilesX * p.tilesI);
+
+    float* Vt = lds;                          // [RT][RI][RXp]
+    float* Ab = Vt + (size_t)RT * RI * RXp;   // [2][RT][RI][4]  forward A, then adjoint A'
+    float* Gb = Ab + (size_t)2 * RT * RI * 4; // [2][N][RT][16]  forward G, then adjoint G'
+    float* tab = Gb + (size_t)2 * N * RT * 16;  // [KH][N][2] h cos, -h sin
+    constexpr int abStride = RT * RI * 4;
+    constexpr int gbStride = N * RT * 16;
+
+    const int64_t t0 = tt * CT * S - N / 2, i0 = ti * 4 * S - N / 2, x0 = tx * 4 * S - N / 2;
+    for (int e = tid; e < RT * RI * RX; e += 512) {
+        const int rx = e % RX;
+        const int r = e / RX;
+        const int ri = r % RI, rt = r / RI;
+        const int64_t gt = reflect_clamp_b(t0 + rt, p.T), gi = reflect_clamp_b(i0 + ri, p.IL),
+                      gx = reflect_clamp_b(x0 + rx, p.XL);
+        Vt[(rt * RI + ri) * RXp + rx] = p.V[(gt * p.IL + gi) * p.XL + gx];
+    }
+    for (int e = tid; e < KH * N * 2; e += 512) tab[e] = p.passA[e];
+
+    float amat[NK], ainvB[NK], ainvC[4];
+#pragma unroll
+    for (int ks = 0; ks < NK; ks++) {
+        amat[ks] = p.mat[col * N + 4 * ks + grp];
+        ainvB[ks] = p.inv[col * 16 + 4 * ks + grp];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++) ainvC[j] = p.inv[col * 16 + 4 * grp + j];
+
+    // upstream gradient of the features of this lane's windows (zero outside the grid)
+    const int64_t G = p.Tg * p.ILg * p.XLg;
+    float ge[CT][3];
+#pragma unroll
+    for (int tc = 0; tc < CT; tc++) {
+        const int64_t gt = tt * CT + tc, gi = ti * 4 + (col >> 2), gx = tx * 4 + (col & 3);
+        const bool ok = gt < p.Tg && gi < p.ILg && gx < p.XLg;
+        const int64_t j = ok ? (gt * p.ILg + gi) * p.XLg + gx : 0;
+#pragma unroll
+        for (int m = 0; m < 3; m++) ge[tc][m] = ok ? p.gE[m * G + j] : 0.f;
+    }
+
+    float acc[ROWS][RX];
+#pragma unroll
+    for (int r = 0; r < ROWS; r++)
+#pragma unroll
+        for (int x = 0; x < RX; x++) acc[r][x] = 0.f;
+
+    __syncthreads();
+
+    for (int kx = 0; kx < KH; kx++) {
+        const float* tk = tab + kx * N * 2;
+        // ---- forward pass A (as in the feature kernel)
+        for (int r = tid; r < RT * RI; r += 512) {
+            const float* row = Vt + r * RXp;
+            float o[8];
+#pragma unroll
+            for (int xc = 0; xc < 4; xc++) {
+                float ar = 0.f, ai = 0.f;
+#pragma unroll
+                for (int a = 0; a < N; a++) {
+                    const float v = row[xc * S + a];
+                    ar = fmaf(tk[2 * a], v, ar);
+                    ai = fmaf(tk[2 * a + 1], v, ai);
+                }
+                o[xc] = ar;
+                o[4 + xc] = ai;
+            }
+            *(float4*)&Ab[r * 4] = make_float4(o[0], o[1], o[2], o[3]);
+            *(float4*)&Ab[abStride + r * 4] = make_float4(o[4], o[5], o[6], o[7]);
+        }
+        __syncthreads();
+        // ---- forward pass B
+        {
+            const int ilc = col >> 2, xc = col & 3;
+            for (int rt = wave; rt < RT; rt += 8) {
+                f4 dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < NK; ks++) {
+                    const int idx = (rt * RI + ilc * S + 4 * ks + grp) * 4 + xc;
+                    dr = mfma4b(amat[ks], Ab[idx], dr);
+                    di = mfma4b(amat[ks], Ab[abStride + idx], di);
+                }
+#pragma unroll
+                for (int pr = 0; pr < 2; pr++) {
+                    const int ra = 4 * grp + 2 * pr;
+                    if (ra >= N) continue;
+                    const float Ca = dr[2 * pr], Sb = dr[2 * pr + 1], Cai = di[2 * pr], Sbi = di[2 * pr + 1];
+                    int u1, u2;
+                    float g1r, g1i, g2r, g2i;
+                    if (ra == 0) {
+                        u1 = 0; u2 = N / 2;
+                        g1r = Ca; g1i = Cai; g2r = Sb; g2i = Sbi;
+                    } else {
+                        const int q = ra >> 1;
+                        u1 = q; u2 = N - q;
+                        g1r = Ca + Sbi; g1i = Cai - Sb;
+                        g2r = Ca - Sbi; g2i = Cai + Sb;
+                    }
+                    Gb[(u1 * RT + rt) * 16 + col] = g1r;
+                    Gb[gbStride + (u1 * RT + rt) * 16 + col] = g1i;
+                    Gb[(u2 * RT + rt) * 16 + col] = g2r;
+                    Gb[gbStride + (u2 * RT + rt) * 16 + col] = g2i;
+                }
+            }
+        }
+        __syncthreads();
+        // ---- pass C, Y = c F/|F|, and the transposed pass C with overlap-add over the t-centres.
+        // One wave owns each ki slot u, so its rows of Gb are read and then rewritten by it alone.
+        for (int u = wave; u < N; u += 8) {
+            const float4* wrow = p.wts + ((size_t)(kx * N + u) * 16 + 4 * grp);
+            const float4 w0 = wrow[0], w1 = wrow[1], w2 = wrow[2], w3 = wrow[3];
+            float y[CT][8];
+#pragma unroll
+            for (int tc = 0; tc < CT; tc++) {
+                f4 dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};
+                const float* gr = Gb + (u * RT + tc * S + grp) * 16 + col;
+#pragma unroll
+                for (int ks = 0; ks < NK; ks++) {
+                    dr = mfma4b(amat[ks], gr[ks * 64], dr);
+                    di = mfma4b(amat[ks], gr[gbStride + ks * 64], di);
+                }
+#pragma unroll
+                for (int pr = 0; pr < 2; pr++) {
+                    const bool sp = (grp == 0) && (pr == 0);
+                    const float Ca = dr[2 * pr], Sb = dr[2 * pr + 1], Cai = di[2 * pr], Sbi = di[2 * pr + 1];
+                    const float re1 = sp ? Ca : Ca + Sbi, im1 = sp ? Cai : Cai - Sb;
+                    const float re2 = sp ? Sb : Ca - Sbi, im2 = sp ? Sbi : Cai + Sb;
+                    const float4 wa = pr ? w2 : w0, wb = pr ? w3 : w1;
+                    const float c1 = fmaf(ge[tc][0], wa.x, fmaf(ge[tc][1], wa.y, ge[tc][2] * wa.z));
+                    const float c2 = fmaf(ge[tc][0], wb.x, fmaf(ge[tc][1], wb.y, ge[tc][2] * wb.z));
+                    const float q1 = fmaf(re1, re1, im1 * im1), q2 = fmaf(re2, re2, im2 * im2);
+                    const float s1 = q1 > 0.f ? c1 * __builtin_amdgcn_rsqf(q1) : 0.f;
+                    const float s2 = q2 > 0.f ? c2 * __builtin_amdgcn_rsqf(q2) : 0.f;
+                    const float y1r = s1 * re1, y1i = s1 * im1, y2r = s2 * re2, y2i = s2 * im2;
+                    // packed inverse-DFT inputs: cos row gets Y(+q) + Y(-q), sin row i (Y(+q) - Y(-q))
+                    y[tc][4 * pr + 0] = sp ? y1r : y1r + y2r;   // real chain, cos row
+                    y[tc][4 * pr + 1] = sp ? y2r : y2i - y1i;   // real chain, sin row
+                    y[tc][4 * pr + 2] = sp ? y1i : y1i + y2i;   // imaginary chain, cos row
+                    y[tc][4 * pr + 3] = sp ? y2i : y1r - y2r;   // imaginary chain, sin row
+                }
+            }
+            lds_fence();
+            for (int e = lane; e < RT * 16; e += 64) {
+                Gb[u * RT * 16 + e] = 0.f;
+                Gb[gbStride + u * RT * 16 + e] = 0.f;
+            }
+            lds_fence();
+#pragma unroll
+            for (int tc = 0; tc < CT; tc++) {
+                f4 zr = {0.f, 0.f, 0.f, 0.f}, zi = {0.f, 0.f, 0.f, 0.f};
+                // K-permuted contraction: step j takes packed row 4*grp + j from this lane's registers
+                zr = mfma4b(ainvC[0], y[tc][0], zr);
+                zi = mfma4b(ainvC[0], y[tc][2], zi);
+                zr = mfma4b(ainvC[1], y[tc][1], zr);
+                zi = mfma4b(ainvC[1], y[tc][3], zi);
+                zr = mfma4b(ainvC[2], y[tc][4], zr);
+                zi = mfma4b(ainvC[2], y[tc][6], zi);
+                zr = mfma4b(ainvC[3], y[tc][5], zr);
+                zi = mfma4b(ainvC[3], y[tc][7], zi);
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const int a = 4 * grp + j;
+                    if (a < N) {
+                        float* dst = Gb + (u * RT + tc * S + a) * 16 + col;
+                        dst[0] += zr[j];
+                        dst[gbStride] += zi[j];
+                    }
+                }
+                lds_fence();
+            }
+        }
+        for (int e = tid; e < 2 * abStride; e += 512) Ab[e] = 0.f;
+        __syncthreads();
+        // ---- transposed pass B (ki -> il samples) with overlap-add over the il-centres
+        {
+            const int ilc = col >> 2, xc = col & 3;
+            for (int rt = wave; rt < RT; rt += 8) {
+                f4 zr = {0.f, 0.f, 0.f, 0.f}, zi = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < NK; ks++) {
+                    const int r = 4 * ks + grp;
+                    float xr, xi;
+                    if (r == 0 || r == 1) {
+                        const int u = r == 0 ? 0 : N / 2;
+                        xr = Gb[(u * RT + rt) * 16 + col];
+                        xi = Gb[gbStride + (u * RT + rt) * 16 + col];
+                    } else {
+                        const int q = r >> 1;
+                        const float pr_ = Gb[(q * RT + rt) * 16 + col], pi_ = Gb[gbStride + (q * RT + rt) * 16 + col];
+                        const float mr_ = Gb[((N - q) * RT + rt) * 16 + col],
+                                    mi_ = Gb[gbStride + ((N - q) * RT + rt) * 16 + col];
+                        if (r & 1) {  // sin row: i (G(+q) - G(-q))
+                            xr = mi_ - pi_;
+                            xi = pr_ - mr_;
+                        } else {
+                            xr = pr_ + mr_;
+                            xi = pi_ + mi_;
+                        }
+                    }
+                    zr = mfma4b(ainvB[ks], xr, zr);
+                    zi = mfma4b(ainvB[ks], xi, zi);
+                }
+                // rows b = 4 grp + j of column (ilc, xc): add into il row ilc*S + b, one ilc at a time
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    if (ilc == k) {
+#pragma unroll
+                        for (int j = 0; j < 4; j++) {
+                            const int b = 4 * grp + j;
+                            if (b < N) {
+                                float* dst = Ab + (rt * RI + k * S + b) * 4 + xc;
+                                dst[0] += zr[j];
+                                dst[abStride] += zi[j];
+                            }
+                        }
+                    }
+                    lds_fence();
+                }
+            }
+        }
+        __syncthreads();
+        // ---- transposed pass A: real part of the kx term into the register accumulators
+#pragma unroll
+        for (int rr = 0; rr < ROWS; rr++) {
+            const int r = tid + 512 * rr;
+            if (r < RT * RI) {
+#pragma unroll
+                for (int xc = 0; xc < 4; xc++) {
+                    const float ar = Ab[r * 4 + xc], ai = Ab[abStride + r * 4 + xc];
+#pragma unroll
+                    for (int a = 0; a < N; a++) acc[rr][xc * S + a] = fmaf(ar, tk[2 * a], fmaf(ai, tk[2 * a + 1], acc[rr][xc * S + a]));
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // stage the tile's contributions through LDS for coalesced workspace writes
+#pragma unroll
+    for (int rr = 0; rr < ROWS; rr++) {
+        const int r = tid + 512 * rr;
+        if (r < RT * RI) {
+#pragma unroll
+            for (int x = 0; x < RX; x++) Vt[r * RXp + x] = acc[rr][x];
+        }
+    }
+    __syncthreads();
+    float* out = p.part + tile * (int64_t)(RT * RI * RX);
+    for (int e = tid; e < RT * RI * RX; e += 512) {
+        const int rx = e % RX, r = e / RX;
+        out[e] = Vt[r * RXp + rx];
+    }
+}
+
+// gV(p) = sum over tiles and reflections of the tile contributions at virtual positions
+// q with reflect(q) = p, in a fixed order.
+struct GatherParams {
+    const float* part;
+    float* gV;
+    int64_t N3[3];
+    int64_t tiles[3];
+    int C[3];   // centres per tile along each axis
+    int R[3];   // region extent along each axis
+    int n, s;
+};
+
+__global__ __launch_bounds__(256) void k_gather(GatherParams p) {
+    const int64_t NV = p.N3[0] * p.N3[1] * p.N3[2];
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= NV) return;
+    const int64_t c3[3] = {v / (p.N3[1] * p.N3[2]), (v / p.N3[2]) % p.N3[1], v % p.N3[2]};
+    int64_t tl[3][16];
+    int off[3][16];
+    int cnt[3] = {0, 0, 0};
+    const int half = p.n / 2;
+    for (int a = 0; a < 3; a++) {
+        const int64_t Na = p.N3[a], pa = c3[a];
+        int64_t qs[3];
+        int nq = 0;
+        qs[nq++] = pa;
+        if (-1 - pa >= -half) qs[nq++] = -1 - pa;
+        if (2 * Na - 1 - pa < Na + half) qs[nq++] = 2 * Na - 1 - pa;
+        const int64_t step = (int64_t)p.C[a] * p.s;
+        for (int k = 0; k < nq; k++) {
+            const int64_t q = qs[k] + half;  // position relative to the start of tile 0's region
+            int64_t lo = q - p.R[a] + 1;
+            lo = lo <= 0 ? 0 : (lo + step - 1) / step;
+            int64_t hi = q / step;
+            if (hi > p.tiles[a] - 1) hi = p.tiles[a] - 1;
+            for (int64_t tix = lo; tix <= hi && cnt[a] < 16; tix++) {
+                tl[a][cnt[a]] = tix;
+                off[a][cnt[a]] = (int)(q - tix * step);
+                cnt[a]++;
+            }
+        }
+    }
+    const int64_t regsz = (int64_t)p.R[0] * p.R[1] * p.R[2];
+    float acc = 0.f;
+    for (int i = 0; i < cnt[0]; i++)
+        for (int j = 0; j < cnt[1]; j++)
+            for (int k = 0; k < cnt[2]; k++) {
+                const int64_t tile = (tl[0][i] * p.tiles[1] + tl[1][j]) * p.tiles[2] + tl[2][k];
+                acc += p.part[tile * regsz + ((int64_t)off[0][i] * p.R[1] + off[1][j]) * p.R[2] + off[2][k]];
+            }
+    p.gV[v] = acc;
+}
+
+struct AdjLayout {
+    int RT, RI, RX;
+    int64_t tilesT, tilesI, tilesX, ntiles;
+    size_t lds;
+    size_t part_bytes;
+};
+
+template <int N, int S>
+static AdjLayout adj_layout(int64_t T, int64_t IL, int64_t XL) {
+    using Gm = AdjGeom<N, S>;
+    AdjLayout L;
+    L.RT = Gm::RT; L.RI = Gm::RI; L.RX = Gm::RX;
+    L.tilesT = ceil_div(ceil_div(T, S), Gm::CT);
+    L.tilesI = ceil_div(ceil_div(IL, S), 4);
+    L.tilesX = ceil_div(ceil_div(XL, S), 4);
+    L.ntiles = L.tilesT * L.tilesI * L.tilesX;
+    L.lds = Gm::lds_floats * sizeof(float);
+    L.part_bytes = (size_t)L.ntiles * Gm::RT * Gm::RI * Gm::RX * sizeof(float);
+    return L;
+}
+
+static sal_status adj_layout_dispatch(int n, int s, int64_t T, int64_t IL, int64_t XL, AdjLayout* L) {
+#define SAL_ADJ_CASE(NN, SS) \
+    if (n == NN && s == SS) { *L = adj_layout<NN, SS>(T, IL, XL); return SAL_OK; }
+    SAL_ADJ_CASE(4, 1)
+    SAL_ADJ_CASE(8, 1) SAL_ADJ_CASE(8, 2) SAL_ADJ_CASE(8, 3)
+    SAL_ADJ_CASE(12, 1) SAL_ADJ_CASE(12, 2) SAL_ADJ_CASE(12, 3)
+    SAL_ADJ_CASE(16, 1) SAL_ADJ_CASE(16, 2)
+#undef SAL_ADJ_CASE
+    return fail(SAL_ERR_UNSUPPORTED, "adjoint built for n = 4 (s = 1), n = 8 and 12 (s <= 3) and n = 16 (s <= 2)");
+}
+
+template <int N, int S>
+static sal_status launch_adj(const AdjParams& p, const AdjLayout& L, hipStream_t stream) {
+    static bool attr = false;
+    if (!attr) {
+        sal_status st = check_hip(hipFuncSetAttribute((const void*)k_spectral_adjoint<N, S>,
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024),
+                                  "hipFuncSetAttribute(adjoint)");
+        if (st) return st;
+        attr = true;
+    }
+    const int64_t grid = 8 * ((L.ntiles + 7) / 8);
+    hipLaunchKernelGGL((k_spectral_adjoint<N, S>), dim3((unsigned)grid), dim3(512), L.lds, stream, p);
+    return check_hip(hipGetLastError(), "launch k_spectral_adjoint");
+}
+
+static sal_status launch_adj_dispatch(int n, int s, const AdjParams& p, const AdjLayout& L, hipStream_t stream) {
+#define SAL_ADJ_CASE(NN, SS) \
+    if (n == NN && s == SS) return launch_adj<NN, SS>(p, L, stream);
+    SAL_ADJ_CASE(4, 1)
+    SAL_ADJ_CASE(8, 1) SAL_ADJ_CASE(8, 2) SAL_ADJ_CASE(8, 3)
+    SAL_ADJ_CASE(12, 1) SAL_ADJ_CASE(12, 2) SAL_ADJ_CASE(12, 3)
+    SAL_ADJ_CASE(16, 1) SAL_ADJ_CASE(16, 2)
+#undef SAL_ADJ_CASE
+    return fail(SAL_ERR_UNSUPPORTED, "adjoint not built for this window/stride");
+}
+
+// Workspace layout of sal_backward (each part 256-byte aligned):
+//   cell [G] f32 | gSm [3G] f32 | gE [3G] f32 | fusion-adjoint doubles | tile partials
+struct BwdWs {
+    size_t cell, gsm, ge, fus, part, total;
+};
+
+static size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+
+static BwdWs bwd_ws(int64_t G, const AdjLayout& L) {
+    BwdWs w;
+    w.cell = 0;
+    w.gsm = w.cell + al256(sizeof(float) * G);
+    w.ge = w.gsm + al256(sizeof(float) * 3 * G);
+    w.fus = w.ge + al256(sizeof(float) * 3 * G);
+    w.part = w.fus + al256(fuse_adjoint_workspace_bytes());
+    w.total = w.part + al256(L.part_bytes);
+    return w;
+}
+
+}  // namespace sal
 
 using namespace sal;
 
 extern "C" {
 
-size_t sal_backward_workspace_size(int64_t, int64_t, int64_t, const sal_spec*) { return 0; }
+size_t sal_backward_workspace_size(int64_t T, int64_t IL, int64_t XL, const sal_spec* spec) {
+    if (check_spec(spec, T, IL, XL) != SAL_OK) return 0;
+    AdjLayout L;
+    if (adj_layout_dispatch(spec->n, spec->s, T, IL, XL, &L) != SAL_OK) return 0;
+    const int64_t G = ceil_div(T, spec->s) * ceil_div(IL, spec->s) * ceil_div(XL, spec->s);
+    return bwd_ws(G, L).total;
+}
 
-sal_status sal_backward(const float*, int64_t, int64_t, int64_t, const sal_spec*, const sal_stencil*,
-                        const sal_fusion*, const float*, const float*, const double*, const float*, const uint8_t*,
-                        const float*, float*, void*, size_t, sal_stream) {
-    return fail(SAL_ERR_UNSUPPORTED, "adjoint not built yet");
+sal_status sal_backward(const float* V, int64_t T, int64_t IL, int64_t XL, const sal_spec* spec,
+                        const sal_stencil* stencil, const sal_fusion* fusion, const float* E, const float* Sm,
+                        const double* W, const float* D, const uint8_t* mask, const float* gS, float* gV_out,
+                        void* ws, size_t ws_bytes, sal_stream stream_) {
+    hipStream_t stream = (hipStream_t)stream_;
+    sal_status st = check_spec(spec, T, IL, XL);
+    if (st) return st;
+    if (spec->precision != SAL_PREC_FP32) return fail(SAL_ERR_UNSUPPORTED, "the adjoint runs in fp32 only");
+    if (!V || !E || !Sm || !W || !gS || !gV_out) return fail(SAL_ERR_ARG, "NULL buffer");
+    if (!fusion) return fail(SAL_ERR_ARG, "fusion is NULL");
+    if (fusion->mode != SAL_FUSE_EQUAL && fusion->mode != SAL_FUSE_FIXED && fusion->mode != SAL_FUSE_ADAPT_LS)
+        return fail(SAL_ERR_ARG, "unknown fusion mode");
+    if (fusion->mode == SAL_FUSE_ADAPT_LS && (!D || !(fusion->delta >= 0.0)))
+        return fail(SAL_ERR_ARG, "ADAPT_LS needs D and delta >= 0");
+    DcsStencil ds;
+    if ((st = make_stencil(stencil, spec->s, &ds))) return st;
+    AdjLayout L;
+    if ((st = adj_layout_dispatch(spec->n, spec->s, T, IL, XL, &L))) return st;
+    const int s = spec->s;
+    const int64_t Tg = ceil_div(T, s), ILg = ceil_div(IL, s), XLg = ceil_div(XL, s), G = Tg * ILg * XLg;
+    const BwdWs lay = bwd_ws(G, L);
+    if (!ws || ws_bytes < lay.total) return fail(SAL_ERR_NOMEM, "workspace smaller than sal_backward_workspace_size()");
+    char* base = (char*)ws;
+    float* cell = (float*)(base + lay.cell);
+    float* gSm = (float*)(base + lay.gsm);
+    float* gE = (float*)(base + lay.ge);
+    double* fws = (double*)(base + lay.fus);
+    float* part = (float*)(base + lay.part);
+    const Tables* tb = nullptr;
+    if ((st = get_tables(spec->n, spec->window, &tb))) return st;
+
+    if ((st = launch_fuse_adjoint(Sm, Tg, ILg, XLg, *fusion, D, mask, W, gS, T, IL, XL, s, cell, fws, gSm, stream)))
+        return st;
+    if ((st = launch_dcs_adjoint(E, gSm, gE, Tg, ILg, XLg, ds, stream))) return st;
+
+    AdjParams p;
+    p.V = V;
+    p.T = T; p.IL = IL; p.XL = XL;
+    p.Tg = Tg; p.ILg = ILg; p.XLg = XLg;
+    p.tilesT = L.tilesT; p.tilesI = L.tilesI; p.tilesX = L.tilesX; p.ntiles = L.ntiles;
+    p.gE = gE;
+    p.passA = tb->passA;
+    p.mat = tb->mat;
+    p.inv = tb->inv;
+    p.wts = (const float4*)tb->wts;
+    p.part = part;
+    if ((st = launch_adj_dispatch(spec->n, s, p, L, stream))) return st;
+
+    GatherParams gp;
+    gp.part = part;
+    gp.gV = gV_out;
+    gp.N3[0] = T; gp.N3[1] = IL; gp.N3[2] = XL;
+    gp.tiles[0] = L.tilesT; gp.tiles[1] = L.tilesI; gp.tiles[2] = L.tilesX;
+    gp.C[0] = kAdjCT; gp.C[1] = 4; gp.C[2] = 4;
+    gp.R[0] = L.RT; gp.R[1] = L.RI; gp.R[2] = L.RX;
+    gp.n = spec->n;
+    gp.s = s;
+    const int64_t NV = T * IL * XL;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)((NV + 255) / 256)), dim3(256), 0, stream, gp);
+    return check_hip(hipGetLastError(), "launch k_gather");
 }
 
 }  // extern "C"

@@ -149,17 +149,44 @@ sal_status get_tables(int n, int window, const Tables** out) {
             }
         }
     }
-    // low-precision forms of the packed matrix, K padded to 16 per row
-    std::vector<uint16_t> hi(16 * 16, 0), lo(16 * 16, 0), h16(16 * 16, 0);
-    for (int r = 0; r < 16; r++)
-        for (int a = 0; a < n; a++) {
-            float v = mat[size_t(r) * n + a];
-            uint16_t bh = to_bf16(v);
-            hi[r * 16 + a] = bh;
-            lo[r * 16 + a] = to_bf16(v - from_bf16(bh));
-            h16[r * 16 + a] = to_f16(v);
+    // natural-order bin weights and the complex DFT operands of the reduced-precision passes
+    std::vector<float> wnat(size_t(KH) * n * 16 * 4, 0.f);
+    for (int kx = 0; kx < KH; kx++) {
+        double mult = (kx == 0 || kx == n / 2) ? 1.0 : 2.0;
+        for (int u = 0; u < n; u++) {
+            double ki = signed_freq(u, n);
+            for (int r = 0; r < n; r++) {
+                double kt = signed_freq(r, n);
+                double k2 = kt * kt + ki * ki + double(kx) * kx;
+                if (k2 == 0.0) continue;
+                double kn = std::sqrt(k2);
+                float* w = &wnat[((size_t(kx) * n + u) * 16 + r) * 4];
+                w[0] = float(mult * std::sqrt(ki * ki + double(kx) * kx) / kn / n3);
+                w[1] = float(mult * std::sqrt(kt * kt + ki * ki) / kn / n3);
+                w[2] = float(mult * std::sqrt(kt * kt + double(kx) * kx) / kn / n3);
+            }
         }
-    size_t bytes = (passA.size() + mat.size() + wts.size() + inv.size()) * 4 + 3 * 256 * 2 + 8 * 256;
+    }
+    std::vector<uint16_t> chi(2 * 16 * 32, 0), clo(2 * 16 * 32, 0), ch16(2 * 16 * 32, 0);
+    for (int c = 0; c < 2; c++)
+        for (int r = 0; r < 16; r++)
+            for (int k = 0; k < 32; k++) {
+                const int half = k / 16, b = k % 16;
+                double v = 0.0;
+                if (r < n && b < n) {
+                    const int kf = ((r % n) + n) % n;  // bin r as a non-negative frequency mod n
+                    const double h = taper(b, n, window);
+                    const double cs = cos_k(kf, b, n), sn = sin_k(kf, b, n);
+                    if (c == 0) v = half == 0 ? h * cs : h * sn;
+                    else v = half == 0 ? -h * sn : h * cs;
+                }
+                const float f = float(v);
+                const uint16_t bh = to_bf16(f);
+                chi[(c * 16 + r) * 32 + k] = bh;
+                clo[(c * 16 + r) * 32 + k] = to_bf16(f - from_bf16(bh));
+                ch16[(c * 16 + r) * 32 + k] = to_f16(f);
+            }
+    size_t bytes = (passA.size() + mat.size() + wts.size() + inv.size() + wnat.size()) * 4 + 3 * 1024 * 2 + 10 * 256;
     void* base = nullptr;
     st = check_hip(hipMalloc(&base, bytes), "hipMalloc(tables)");
     if (st) return st;
@@ -177,10 +204,12 @@ sal_status get_tables(int n, int window, const Tables** out) {
     dt.t.mat = (const float*)put(mat.data(), mat.size() * 4);
     dt.t.wts = (const float*)put(wts.data(), wts.size() * 4);
     dt.t.inv = (const float*)put(inv.data(), inv.size() * 4);
-    dt.t.mat_hi = (const uint16_t*)put(hi.data(), 512);
-    dt.t.mat_lo = (const uint16_t*)put(lo.data(), 512);
-    dt.t.mat_h16 = (const uint16_t*)put(h16.data(), 512);
-    if (!dt.t.passA || !dt.t.mat || !dt.t.wts || !dt.t.inv || !dt.t.mat_hi || !dt.t.mat_lo || !dt.t.mat_h16) {
+    dt.t.wts_nat = (const float*)put(wnat.data(), wnat.size() * 4);
+    dt.t.cpx_hi = (const uint16_t*)put(chi.data(), chi.size() * 2);
+    dt.t.cpx_lo = (const uint16_t*)put(clo.data(), clo.size() * 2);
+    dt.t.cpx_h16 = (const uint16_t*)put(ch16.data(), ch16.size() * 2);
+    if (!dt.t.passA || !dt.t.mat || !dt.t.wts || !dt.t.inv || !dt.t.wts_nat || !dt.t.cpx_hi || !dt.t.cpx_lo ||
+        !dt.t.cpx_h16) {
         hipFree(base);
         return fail(SAL_ERR_DEVICE, "uploading constant tables failed");
     }

@@ -35,9 +35,13 @@ struct Tables {
     const float* mat = nullptr;     // [16][n]: packed taper*DFT rows c0, c_{n/2}, c1, s1, c2, s2, ...
     const float* wts = nullptr;     // [KH][n][16][4]: bin weights mult(kx) alpha_m / n^3 per packed row
     const float* inv = nullptr;     // [16 a][16 r]: h(a) * trig row r at sample a (transpose of `mat`), zero padded
-    const uint16_t* mat_hi = nullptr;  // bf16 hi/lo and fp16 forms of `mat`, padded to K = 16 per step
-    const uint16_t* mat_lo = nullptr;
-    const uint16_t* mat_h16 = nullptr;
+    const float* wts_nat = nullptr; // [KH][n][16][4]: bin weights for natural-order rows (row r = bin r)
+    // complex DFT operands of the reduced-precision passes, [2 (re, im)][16 rows][32 K]:
+    // row r is bin r (signed frequency), K = [real part samples 0..15 | imaginary part samples 0..15],
+    // re rows h cos | h sin, im rows -h sin | h cos; bf16 hi and lo parts and fp16
+    const uint16_t* cpx_hi = nullptr;
+    const uint16_t* cpx_lo = nullptr;
+    const uint16_t* cpx_h16 = nullptr;
 };
 
 sal_status get_tables(int n, int window, const Tables** out);

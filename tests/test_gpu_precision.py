@@ -1,0 +1,66 @@
+"""Reduced-precision DFT contractions against the FP64 oracle.
+
+SPLIT_BF16 (hi + lo bfloat16 operands, three products, fp32 accumulate) is
+gated at 1e-3 relative per output; FP16 (one product) is reported, with only a
+loose sanity bound.  Errors are printed for the record."""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2201_06174_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "split_bf16": 1e-3, "fp16": 2e-2}
+
+
+@pytest.fixture(scope="module")
+def torch_sal():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2201_06174_amd as sal
+    return torch, sal
+
+
+def _rel(x, ref):
+    return float(np.max(np.abs(np.asarray(x, np.float64) - ref)) / np.max(np.abs(ref)))
+
+
+CASES = [((37, 29, 23), 8, 1, "hann"), ((30, 41, 27), 8, 2, "hann"), ((45, 26, 35), 16, 2, "hann"),
+         ((17, 23, 19), 16, 1, "rect"), ((36, 31, 29), 12, 2, "hann"), ((21, 19, 26), 12, 3, "hann"),
+         ((40, 9, 13), 4, 1, "hann"), ((8, 8, 8), 16, 7, "hann")]
+
+
+@pytest.mark.parametrize("precision", ["split_bf16", "fp16"])
+@pytest.mark.parametrize("shape,n,s,window", CASES)
+def test_project_reduced_precision(torch_sal, precision, shape, n, s, window):
+    torch, sal = torch_sal
+    print("project %s shape=%s n=%d s=%d" % (precision, shape, n, s), flush=True)
+    V = np.random.default_rng(sum(shape) + n).standard_normal(shape).astype(np.float32)
+    E = sal.project(torch.from_numpy(V).cuda(), n, s, window, precision).cpu().numpy()
+    ref = orc.features(V, n, s, window)
+    errs = [_rel(E[m], ref[m]) for m in range(3)]
+    print("  rel err per plane (t, x, y): %s" % ", ".join("%.2e" % e for e in errs))
+    assert max(errs) < TOL[precision]
+
+
+def test_salt_workload_sampled(torch_sal):
+    """512^3 salt-dome volume, window 16^3, stride 2: E in fp32, split-bf16 and
+    fp16 at sampled grid points against the oracle, errors stated."""
+    torch, sal = torch_sal
+    w = synth.workload("salt")
+    V = synth.make_volume(w.spec, w.seed)
+    Vd = torch.from_numpy(V).cuda()
+    gs = orc.grid_shape(V.shape, w.s)
+    rng = np.random.default_rng(11)
+    g = np.stack([rng.integers(0, N, 192) for N in gs], 1).astype(np.int64)
+    g[:8] = [[a, b, c] for a in (0, gs[0] - 1) for b in (0, gs[1] - 1) for c in (0, gs[2] - 1)]
+    ref = orc.features_at(V, w.n, w.s, "hann", g)
+    for prec in ("fp32", "split_bf16", "fp16"):
+        E = sal.project(Vd, w.n, w.s, "hann", prec)
+        Eg = E[:, g[:, 0], g[:, 1], g[:, 2]].T.cpu().numpy()
+        errs = [_rel(Eg[:, m], ref[:, m]) for m in range(3)]
+        print("salt %s: rel err per plane (t, x, y): %s" % (prec, ", ".join("%.2e" % e for e in errs)))
+        assert max(errs) < TOL[prec]
+        del E
