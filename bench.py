@@ -114,6 +114,87 @@ def time_forward(torch, pipe, steps, warmup):
     return total_ms / steps, float(np.mean(kern_ms)), wall
 
 
+def time_fwd_bwd(torch, w_name, steps, warmup):
+    """Forward plus the hand-written adjoint on one workload (equal fusion)."""
+    import paper_2201_06174_amd as sal
+    from paper_2201_06174_amd import synth
+    w = synth.workload(w_name)
+    V = synth.make_volume(w.spec, w.seed)
+    Vd = torch.from_numpy(V).cuda()
+    gS = torch.from_numpy(synth.loss_weights(V.shape, 5001)).cuda()
+    cfg = sal.Config(n=w.n, s=w.s, offsets=w.offsets, fusion="equal")
+    for _ in range(warmup):
+        r = sal.saliency(Vd, cfg)
+        sal.backward(Vd, cfg, r["E"], r["Sm"], r["W"], gS)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    c = torch.cuda.Event(enable_timing=True)
+    fwd = bwd = 0.0
+    for _ in range(steps):
+        a.record()
+        r = sal.saliency(Vd, cfg)
+        b.record()
+        sal.backward(Vd, cfg, r["E"], r["Sm"], r["W"], gS)
+        c.record()
+        torch.cuda.synchronize()
+        fwd += a.elapsed_time(b)
+        bwd += b.elapsed_time(c)
+    fwd /= steps
+    bwd /= steps
+    nvox = int(np.prod(V.shape))
+    return {"workload": "%s: %s, window %d^3, stride %d, loss sum(S * U(0,1))" % (
+        w_name, "x".join(str(v) for v in V.shape), w.n, w.s),
+        "fwd_ms": round(fwd, 4), "bwd_ms": round(bwd, 4),
+        "fwd_bwd_mvoxel_s": round(nvox / ((fwd + bwd) * 1e-3) / 1e6, 3)}
+
+
+def time_batch(torch, lib, steps, count=96):
+    """The 96-member batch: one captured plan vs the three calls per member launched separately."""
+    import paper_2201_06174_amd as sal
+    from paper_2201_06174_amd import synth
+    members, pipes = [], []
+    nvox = 0
+    for i in range(count):
+        w = synth.workload("batch", i)
+        V, M = synth.make_volume(w.spec, w.seed, with_mask=True)
+        D, mask = synth.desired_map(M, w.s)
+        Vd, Dd, Md = (torch.from_numpy(a).cuda() for a in (V, D, mask))
+        cfg = sal.Config(n=w.n, s=w.s, offsets=w.offsets, fusion="adapt_ls", delta=1e-6)
+        members.append({"V": Vd, "cfg": cfg, "D": Dd, "mask": Md})
+        pipes.append(Pipeline(torch, lib, Vd, w, "fp32", "adapt_ls", Dd, Md))
+        nvox += int(np.prod(V.shape))
+    t0 = time.perf_counter()
+    plan = sal.Plan(members, autotune=True)
+    create_s = time.perf_counter() - t0
+    desc = plan.describe()
+
+    def run_plan():
+        plan.launch()
+
+    def run_separate():
+        for pp in pipes:
+            pp.project()
+            pp.rest()
+
+    out = {"members": count, "voxels": nvox, "plan_create_s": round(create_s, 3), "plan": desc.strip().split("\n")}
+    for name, fn in (("graph", run_plan), ("separate", run_separate)):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        out[name + "_ms"] = round(ms, 4)
+        out[name + "_mvoxel_s"] = round(nvox / (ms * 1e-3) / 1e6, 3)
+    plan.close()
+    return out
+
+
 def cpu_baseline(V, w, seconds):
     """The FP64 oracle on a bounded sample of windows of the same volume, on all host cores."""
     from oracle import oracle as orc
@@ -186,6 +267,25 @@ def main():
                      "kernel": "k_project_fp32 (sal_project)", "kernel_ms": round(kern_ms, 4),
                      "flops_per_window": algorithmic_flops_per_window(w.n)},
     }
+    if not args.no_extra:
+        extra = {}
+        forms = {}
+        for prec in ("fp32", "split_bf16", "fp16"):
+            if prec == args.precision:
+                forms[prec] = {"ms_per_step": round(ms, 4), "kernel_ms": round(kern_ms, 4),
+                               "mvoxel_s": round(value, 3)}
+                continue
+            pp = Pipeline(torch, lib, Vd, w, prec, args.fusion, Dd, Md)
+            m2, k2, _ = time_forward(torch, pp, max(3, args.steps // 2), 2)
+            forms[prec] = {"ms_per_step": round(m2, 4), "kernel_ms": round(k2, 4),
+                           "mvoxel_s": round(nvox / (m2 * 1e-3) / 1e6, 3)}
+            del pp
+        for prec in forms:
+            forms[prec]["speedup_vs_fp32"] = round(forms["fp32"]["ms_per_step"] / forms[prec]["ms_per_step"], 3)
+        extra["precision_forms"] = forms
+        extra["fwd_bwd"] = time_fwd_bwd(torch, "grad", 5, 2)
+        extra["batch"] = time_batch(torch, lib, 5)
+        out["extra"] = extra
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(V, w, args.cpu_seconds)
     print(json.dumps(out), flush=True)

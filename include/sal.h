@@ -173,6 +173,54 @@ sal_status sal_backward(const float* V, int64_t T, int64_t IL, int64_t XL, const
                         const double* W, const float* D, const uint8_t* mask, const float* gS, float* gV_out,
                         void* ws, size_t ws_bytes, sal_stream stream);
 
+/*
+ * Batched form: the whole forward path (sal_project, sal_center_surround,
+ * sal_fuse) for many volumes of uneven sizes and window classes, replayed as
+ * one captured HIP graph of persistent kernels (Sec. 2 applied to every
+ * member).  Each member's outputs equal those of the single-volume calls
+ * bit for bit.
+ */
+typedef struct {
+    const float* V;       /* device float [T][IL][XL] */
+    int64_t T, IL, XL;
+    sal_spec spec;        /* n, s, window, precision of this member */
+    sal_stencil stencil;  /* host arrays, copied by sal_plan_create */
+    sal_fusion fusion;
+    const float* D;       /* device [Tg][ILg][XLg], ADAPT_LS only */
+    const uint8_t* mask;  /* device [Tg][ILg][XLg] or NULL */
+    float* E_out;         /* device [3][Tg][ILg][XLg] */
+    float* Sm_out;        /* device [3][Tg][ILg][XLg] */
+    double* W_out;        /* device [4] (as in sal_fuse) */
+    float* S_out;         /* device [T][IL][XL] */
+} sal_batch_item;
+
+#define SAL_PLAN_AUTOTUNE 1u /* time the candidate tile depths of every window class at creation */
+#define SAL_PLAN_NO_GRAPH 2u /* enqueue the kernels directly at each launch instead of replaying a graph */
+
+typedef struct sal_plan_s sal_plan;
+
+/*
+ * sal_plan_create -- validates every member, groups them into window classes
+ * (n, s, window, precision), picks a tile depth per class (the deepest that
+ * fits, or, with SAL_PLAN_AUTOTUNE, the fastest of the candidates, timed on
+ * the members themselves and remembered for the process), uploads the
+ * descriptor tables and captures the launch sequence in a HIP graph.  The
+ * plan keeps the member pointers: the buffers must stay allocated and at the
+ * same addresses until sal_plan_destroy.  Creation synchronises the device.
+ *   items  host array [count]; count >= 1
+ *   out    receives the plan
+ */
+sal_status sal_plan_create(const sal_batch_item* items, int64_t count, uint32_t flags, sal_plan** out);
+
+/* Enqueues one run of the whole batch on the stream (graph replay). */
+sal_status sal_plan_launch(sal_plan* plan, sal_stream stream);
+
+/* Human-readable description of the classes, tile depths and timings (owned by the plan). */
+const char* sal_plan_describe(const sal_plan* plan);
+
+/* Frees the plan's device tables and graph (the member buffers are the caller's). */
+sal_status sal_plan_destroy(sal_plan* plan);
+
 #ifdef __cplusplus
 }
 #endif

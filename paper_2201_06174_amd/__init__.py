@@ -15,7 +15,7 @@ import numpy as np
 from . import _lib
 
 __all__ = ["Config", "local_spectra", "project", "center_surround", "fuse", "saliency", "backward", "SaliencyFn",
-           "grid_shape", "fuse_workspace_size", "backward_workspace_size"]
+           "grid_shape", "fuse_workspace_size", "backward_workspace_size", "Plan"]
 
 
 def _torch():
@@ -200,3 +200,66 @@ class _Lazy:
 
 
 SaliencyFn = _Lazy()
+
+
+class Plan:
+    """The whole forward path over many volumes as one captured graph of
+    persistent kernels (libsal's sal_plan_*).  Members: dicts with keys V
+    (device float32 [T][IL][XL]), cfg (Config), and optionally D, mask.  The
+    plan allocates each member's outputs; launch() runs the batch on the
+    current stream, output(i) returns member i's E, Sm, S and W."""
+
+    def __init__(self, members, autotune=False, graph=True):
+        import ctypes
+        torch = _torch()
+        self._keep = []
+        self._out = []
+        arr = (_lib.SalBatchItem * len(members))()
+        for i, m in enumerate(members):
+            V, cfg = m["V"], m["cfg"]
+            _need(V, torch.float32, "V")
+            D, mask = m.get("D"), m.get("mask")
+            grid = grid_shape(V.shape, cfg.s)
+            out = {"E": torch.empty((3,) + grid, dtype=torch.float32, device=V.device),
+                   "Sm": torch.empty((3,) + grid, dtype=torch.float32, device=V.device),
+                   "S": torch.empty(tuple(V.shape), dtype=torch.float32, device=V.device),
+                   "W": torch.empty(4, dtype=torch.float64, device=V.device)}
+            self._out.append(out)
+            st, keep = _lib.make_stencil(cfg.offsets, cfg.weights, cfg.literal)
+            self._keep.append((V, D, mask, keep))
+            it = arr[i]
+            it.V = V.data_ptr()
+            it.T, it.IL, it.XL = V.shape
+            it.spec = _lib.make_spec(cfg.n, cfg.s, cfg.window, cfg.precision)
+            it.stencil = st
+            it.fusion = _lib.make_fusion(cfg.fusion, cfg.wfix, cfg.delta)
+            it.D = None if D is None else _need(D, torch.float32, "D", grid).data_ptr()
+            it.mask = None if mask is None else _need(mask, torch.uint8, "mask", grid).data_ptr()
+            it.E_out = out["E"].data_ptr()
+            it.Sm_out = out["Sm"].data_ptr()
+            it.W_out = out["W"].data_ptr()
+            it.S_out = out["S"].data_ptr()
+        flags = (_lib.PLAN_AUTOTUNE if autotune else 0) | (0 if graph else _lib.PLAN_NO_GRAPH)
+        h = ctypes.c_void_p()
+        _lib.check(_lib.load().sal_plan_create(arr, len(members), flags, ctypes.byref(h)))
+        self._h = h
+
+    def launch(self):
+        _lib.check(_lib.load().sal_plan_launch(self._h, _stream()))
+
+    def output(self, i):
+        return self._out[i]
+
+    def describe(self):
+        return _lib.load().sal_plan_describe(self._h).decode()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().sal_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

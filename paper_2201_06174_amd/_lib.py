@@ -33,6 +33,16 @@ class SalFusion(ctypes.Structure):
     _fields_ = [("mode", c_int32), ("w_fixed", c_double * 3), ("delta", c_double)]
 
 
+class SalBatchItem(ctypes.Structure):
+    _fields_ = [("V", c_void_p), ("T", c_int64), ("IL", c_int64), ("XL", c_int64), ("spec", SalSpec),
+                ("stencil", SalStencil), ("fusion", SalFusion), ("D", c_void_p), ("mask", c_void_p),
+                ("E_out", c_void_p), ("Sm_out", c_void_p), ("W_out", c_void_p), ("S_out", c_void_p)]
+
+
+PLAN_AUTOTUNE = 1
+PLAN_NO_GRAPH = 2
+
+
 class SalError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("%s: %s" % (STATUS_NAMES.get(code, str(code)), msg))
@@ -56,6 +66,10 @@ SIGNATURES = {
     "sal_backward": (c_int32, [c_void_p, c_int64, c_int64, c_int64, POINTER(SalSpec), POINTER(SalStencil),
                                POINTER(SalFusion), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                c_void_p, c_void_p, c_size_t, c_void_p]),
+    "sal_plan_create": (c_int32, [POINTER(SalBatchItem), c_int64, ctypes.c_uint32, POINTER(c_void_p)]),
+    "sal_plan_launch": (c_int32, [c_void_p, c_void_p]),
+    "sal_plan_describe": (c_char_p, [c_void_p]),
+    "sal_plan_destroy": (c_int32, [c_void_p]),
 }
 
 _lib = None

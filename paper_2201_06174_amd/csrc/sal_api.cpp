@@ -70,6 +70,8 @@ static sal_status check_fusion(const sal_fusion* f, const float* D) {
     return SAL_OK;
 }
 
+sal_status check_fusion_args(const sal_fusion* f, const float* D) { return check_fusion(f, D); }
+
 }  // namespace sal
 
 using namespace sal;

@@ -1,6 +1,8 @@
 // sal_aux.h -- launchers of the bandwidth-bound kernels (not part of the ABI).
 #pragma once
 
+#include <vector>
+
 #include "sal_internal.h"
 
 namespace sal {
@@ -38,5 +40,22 @@ sal_status launch_project_lowp(const float* V, int64_t T, int64_t IL, int64_t XL
                                const Tables* tb, float* E, hipStream_t stream);
 sal_status launch_project_fp32(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s, const Tables* tb,
                                float* E, hipStream_t stream);
+
+// Batched (persistent) feature launches over many volumes of one window class.  The
+// per-volume kernel parameters are opaque blocks of *_param_bytes() bytes.
+void project_fp32_ct_candidates(int n, int s, std::vector<int>* out);
+void project_lowp_ct_candidates(int n, int s, int precision, std::vector<int>* out);
+size_t project_fp32_param_bytes();
+size_t project_lowp_param_bytes();
+sal_status project_fp32_params(int n, int s, int CT, const float* V, int64_t T, int64_t IL, int64_t XL,
+                               const Tables* tb, float* E, void* out, int64_t* ntiles, size_t* lds);
+sal_status project_lowp_params(int n, int s, int precision, int CT, const float* V, int64_t T, int64_t IL,
+                               int64_t XL, const Tables* tb, float* E, void* out, int64_t* ntiles, size_t* lds);
+sal_status project_fp32_batch(int n, int s, const void* items, const int64_t* prefix, int nitems, int64_t total,
+                              size_t lds, int grid, hipStream_t stream);
+sal_status project_lowp_batch(int n, int s, int precision, const void* items, const int64_t* prefix, int nitems,
+                              int64_t total, size_t lds, int grid, hipStream_t stream);
+sal_status project_fp32_batch_occupancy(int n, int s, size_t lds, int* per_cu);
+sal_status project_lowp_batch_occupancy(int n, int s, int precision, size_t lds, int* per_cu);
 
 }  // namespace sal

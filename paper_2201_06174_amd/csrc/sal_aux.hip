@@ -1,7 +1,7 @@
 // sal_aux.hip -- the bandwidth-bound steps: full local spectra (checks), directional
 // center-surround (Sec. 2 step 4, Eq. 3) and fusion (Sec. 2 step 5, Eq. 4), with
 // their adjoints.
-#include "sal_aux.h"
+#include "sal_device.h"
 
 namespace sal {
 
@@ -102,32 +102,9 @@ sal_status launch_local_spectra(const float* V, int64_t T, int64_t IL, int64_t X
 
 __global__ __launch_bounds__(256) void k_dcs(const float* __restrict__ E, float* __restrict__ S, int64_t Tg,
                                              int64_t ILg, int64_t XLg, DcsStencil st) {
-    const int64_t G = Tg * ILg * XLg;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= G) return;
-    const int64_t gx = j % XLg, gi = (j / XLg) % ILg, gt = j / (XLg * ILg);
-    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
-    const float e0 = E[j], e1 = E[G + j], e2 = E[2 * G + j];
-    int Q = 0;
-    for (int k = 0; k < st.q; k++) {
-        const int64_t nt = gt + st.o[k][0], ni = gi + st.o[k][1], nx = gx + st.o[k][2];
-        if (nt < 0 || nt >= Tg || ni < 0 || ni >= ILg || nx < 0 || nx >= XLg) continue;
-        const int64_t jn = (nt * ILg + ni) * XLg + nx;
-        const float w = st.w[k];
-        if (st.literal) {
-            acc0 += fabsf(e0 - w * E[jn]);
-            acc1 += fabsf(e1 - w * E[G + jn]);
-            acc2 += fabsf(e2 - w * E[2 * G + jn]);
-        } else {
-            acc0 += w * fabsf(e0 - E[jn]);
-            acc1 += w * fabsf(e1 - E[G + jn]);
-            acc2 += w * fabsf(e2 - E[2 * G + jn]);
-        }
-        Q++;
-    }
-    S[j] = Q ? acc0 / (float)Q : 0.f;
-    S[G + j] = Q ? acc1 / (float)Q : 0.f;
-    S[2 * G + j] = Q ? acc2 / (float)Q : 0.f;
+    if (j >= Tg * ILg * XLg) return;
+    dcs_point(E, S, Tg, ILg, XLg, st, j);
 }
 
 sal_status launch_dcs(const float* E, float* S, int64_t Tg, int64_t ILg, int64_t XLg, const DcsStencil& st,
@@ -204,60 +181,8 @@ __global__ __launch_bounds__(256) void k_fuse_stats(const float* __restrict__ Sm
                                                     const uint8_t* __restrict__ mask, int64_t G,
                                                     double* __restrict__ part) {
     __shared__ double red[256];
-    double st[kStats];
-    for (int k = 0; k < kStats; k++) st[k] = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < G; j += stride) {
-        if (mask && !mask[j]) continue;
-        const double u0 = Sm[j], u1 = Sm[G + j], u2 = Sm[2 * G + j], d = D[j];
-        st[0] += u0 * u0; st[1] += u0 * u1; st[2] += u0 * u2;
-        st[3] += u1 * u1; st[4] += u1 * u2; st[5] += u2 * u2;
-        st[6] += u0 * d; st[7] += u1 * d; st[8] += u2 * d;
-        st[9] += d * d; st[10] += 1.0;
-    }
-    for (int k = 0; k < kStats; k++) {
-        red[threadIdx.x] = st[k];
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kStats + k] = red[0];
-        __syncthreads();
-    }
-}
-
-__device__ int chol3(const double A[9], const double b[3], double x[3]) {
-    double dmax = 0.0;
-    for (int i = 0; i < 3; i++) {
-        if (!isfinite(A[4 * i])) return 1;
-        dmax = A[4 * i] > dmax ? A[4 * i] : dmax;
-    }
-    if (!(dmax > 0.0)) return 1;
-    double L[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int j = 0; j < 3; j++) {
-        double d = A[3 * j + j];
-        for (int k = 0; k < j; k++) d -= L[3 * j + k] * L[3 * j + k];
-        if (!(d > 1e-12 * dmax) || !isfinite(d)) return 1;
-        L[3 * j + j] = sqrt(d);
-        for (int i = j + 1; i < 3; i++) {
-            double v = A[3 * i + j];
-            for (int k = 0; k < j; k++) v -= L[3 * i + k] * L[3 * j + k];
-            L[3 * i + j] = v / L[3 * j + j];
-        }
-    }
-    double y[3];
-    for (int i = 0; i < 3; i++) {
-        double v = b[i];
-        for (int k = 0; k < i; k++) v -= L[3 * i + k] * y[k];
-        y[i] = v / L[3 * i + i];
-    }
-    for (int i = 2; i >= 0; i--) {
-        double v = y[i];
-        for (int k = i + 1; k < 3; k++) v -= L[3 * k + i] * x[k];
-        x[i] = v / L[3 * i + i];
-    }
-    return 0;
+    fuse_stats_block(Sm, D, mask, G, (int64_t)blockIdx.x * blockDim.x, (int64_t)gridDim.x * blockDim.x,
+                     part + (int64_t)blockIdx.x * kStats, red);
 }
 
 // One block: fixed-order reduction of the partials and the 3x3 solve.  Writes
@@ -266,53 +191,14 @@ __global__ __launch_bounds__(64) void k_fuse_solve(const double* __restrict__ pa
                                                    double w0, double w1, double w2, double delta,
                                                    double* __restrict__ W, double* __restrict__ stats_out) {
     __shared__ double st[kStats];
-    if (threadIdx.x < kStats && mode == SAL_FUSE_ADAPT_LS) {
-        double s = 0.0;
-        for (int b = 0; b < nparts; b++) s += part[(int64_t)b * kStats + threadIdx.x];
-        st[threadIdx.x] = s;
-        if (stats_out) stats_out[threadIdx.x] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    if (mode == SAL_FUSE_EQUAL) {
-        W[0] = W[1] = W[2] = 1.0 / 3.0;
-        W[3] = 0.0;
-        return;
-    }
-    if (mode == SAL_FUSE_FIXED) {
-        W[0] = w0; W[1] = w1; W[2] = w2;
-        W[3] = 0.0;
-        return;
-    }
-    const double A[9] = {st[0] + delta, st[1], st[2], st[1], st[3] + delta, st[4], st[2], st[4], st[5] + delta};
-    const double b[3] = {st[6], st[7], st[8]};
-    double x[3];
-    if (chol3(A, b, x)) {
-        W[0] = W[1] = W[2] = 1.0 / 3.0;
-        W[3] = 1.0;
-    } else {
-        W[0] = x[0]; W[1] = x[1]; W[2] = x[2];
-        W[3] = 0.0;
-    }
+    solve_weights(part, nparts, mode, w0, w1, w2, delta, W, stats_out, st);
 }
 
-__device__ __forceinline__ int64_t cell_of(int64_t v, int s, int64_t Ng) {
-    const int64_t g = (v + (s - 1) / 2) / s;
-    return g < Ng - 1 ? g : Ng - 1;
-}
-
-// S(v) = sum_m W_m S_m(g(v)); one thread per voxel.
+// S(v) = sum_m W_m S_m(g(v)); one block per (t, il) row.
 __global__ __launch_bounds__(256) void k_combine(const float* __restrict__ Sm, const double* __restrict__ W,
                                                  int64_t Tg, int64_t ILg, int64_t XLg, int64_t T, int64_t IL,
                                                  int64_t XL, int s, float* __restrict__ S) {
-    const int64_t NV = T * IL * XL;
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= NV) return;
-    const int64_t x = v % XL, i = (v / XL) % IL, t = v / (XL * IL);
-    const int64_t G = Tg * ILg * XLg;
-    const int64_t j = (cell_of(t, s, Tg) * ILg + cell_of(i, s, ILg)) * XLg + cell_of(x, s, XLg);
-    const double r = W[0] * (double)Sm[j] + W[1] * (double)Sm[G + j] + W[2] * (double)Sm[2 * G + j];
-    S[v] = (float)r;
+    combine_row(Sm, W, Tg, ILg, XLg, IL, XL, s, (int64_t)blockIdx.x, S);
 }
 
 size_t fuse_workspace_bytes() { return sizeof(double) * (kFuseParts * kStats + 16); }
@@ -330,10 +216,10 @@ sal_status launch_fuse(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, co
                        f.w_fixed[2], f.delta, W, f.mode == SAL_FUSE_ADAPT_LS ? ws + kFuseParts * kStats : nullptr);
     sal_status st = check_hip(hipGetLastError(), "launch k_fuse_solve");
     if (st) return st;
-    const int64_t NV = T * IL * XL;
-    if (NV == 0) return SAL_OK;
-    hipLaunchKernelGGL(k_combine, dim3((unsigned)((NV + 255) / 256)), dim3(256), 0, stream, Sm, W, Tg, ILg, XLg, T, IL,
-                       XL, s, S);
+    if (T * IL * XL == 0) return SAL_OK;
+    if (T * IL > INT32_MAX) return fail(SAL_ERR_SHAPE, "volume too large for one launch");
+    hipLaunchKernelGGL(k_combine, dim3((unsigned)(T * IL)), dim3(256), 0, stream, Sm, W, Tg, ILg, XLg, T, IL, XL, s,
+                       S);
     return check_hip(hipGetLastError(), "launch k_combine");
 }
 

@@ -58,7 +58,8 @@ struct AdjGeom {
     static constexpr int RX = 3 * S + N;
     static constexpr int RXp = RX | 1;
     static constexpr int ROWS = (RT * RI + 511) / 512;
-    static constexpr size_t lds_floats = (size_t)RT * RI * RXp + 2 * (size_t)RT * RI * 4 + 2 * (size_t)N * RT * 16 +
+    static constexpr size_t lds_floats = (((size_t)RT * RI * RXp + 3) & ~(size_t)3) + 2 * (size_t)RT * RI * 4 +
+                                         2 * (size_t)N * RT * 16 +
                                          (size_t)KH * N * 2;
     static_assert(lds_floats * sizeof(float) <= 160 * 1024, "adjoint tile exceeds the LDS");
 };
@@ -83,7 +84,7 @@ __global__ __launch_bounds__(512) void k_spectral_adjoint(AdjParams p) {
     const int64_t tt = tile / (p.tilesX * p.tilesI);
 
     float* Vt = lds;                          // [RT][RI][RXp]
-    float* Ab = Vt + (size_t)RT * RI * RXp;   // [2][RT][RI][4]  forward A, then adjoint A'
+    float* Ab = Vt + (((size_t)RT * RI * RXp + 3) & ~(size_t)3);  // [2][RT][RI][4]  forward A, then adjoint A'
     float* Gb = Ab + (size_t)2 * RT * RI * 4; // [2][N][RT][16]  forward G, then adjoint G'
     float* tab = Gb + (size_t)2 * N * RT * 16;  // [KH][N][2] h cos, -h sin
     constexpr int abStride = RT * RI * 4;

@@ -1,0 +1,71 @@
+// sal_batch.hip -- batched center-surround and fusion kernels: one launch covers every
+// volume of a plan, each block looking up the volume it serves in a small table.
+#include "sal_batch.h"
+#include "sal_device.h"
+
+namespace sal {
+
+// last index i with first[i] <= b (first[0] == 0, ascending)
+__device__ __forceinline__ int find_item(const int64_t* __restrict__ first, int n, int64_t b) {
+    int a = 0, z = n - 1;
+    while (a < z) {
+        const int m = (a + z + 1) / 2;
+        if (first[m] <= b) a = m; else z = m - 1;
+    }
+    return a;
+}
+
+__global__ __launch_bounds__(256) void k_dcs_batch(const DcsItem* __restrict__ items,
+                                                   const int64_t* __restrict__ first, int n) {
+    const int a = find_item(first, n, blockIdx.x);
+    const DcsItem& it = items[a];
+    const int64_t j = (int64_t)(blockIdx.x - first[a]) * blockDim.x + threadIdx.x;
+    if (j >= it.Tg * it.ILg * it.XLg) return;
+    dcs_point(it.E, it.S, it.Tg, it.ILg, it.XLg, it.st, j);
+}
+
+__global__ __launch_bounds__(256) void k_fuse_stats_batch(const FuseItem* __restrict__ items,
+                                                          const int* __restrict__ adapt_list) {
+    __shared__ double red[256];
+    const FuseItem& it = items[adapt_list[blockIdx.x / kBatchParts]];
+    const int b = blockIdx.x % kBatchParts;
+    const int64_t G = it.Tg * it.ILg * it.XLg;
+    fuse_stats_block(it.Sm, it.D, it.mask, G, (int64_t)b * blockDim.x, (int64_t)kBatchParts * blockDim.x,
+                     it.part + (int64_t)b * kStats, red);
+}
+
+__global__ __launch_bounds__(64) void k_fuse_solve_batch(const FuseItem* __restrict__ items) {
+    __shared__ double st[kStats];
+    const FuseItem& it = items[blockIdx.x];
+    solve_weights(it.part, kBatchParts, it.mode, it.w0, it.w1, it.w2, it.delta, it.W, nullptr, st);
+}
+
+__global__ __launch_bounds__(256) void k_combine_batch(const FuseItem* __restrict__ items,
+                                                       const int64_t* __restrict__ first, int n) {
+    const int a = find_item(first, n, blockIdx.x);
+    const FuseItem& it = items[a];
+    combine_row(it.Sm, it.W, it.Tg, it.ILg, it.XLg, it.IL, it.XL, it.s, (int64_t)(blockIdx.x - first[a]), it.S);
+}
+
+sal_status launch_dcs_batch(const DcsItem* items, const int64_t* first, int n, int64_t blocks, hipStream_t stream) {
+    if (blocks == 0) return SAL_OK;
+    hipLaunchKernelGGL(k_dcs_batch, dim3((unsigned)blocks), dim3(256), 0, stream, items, first, n);
+    return check_hip(hipGetLastError(), "launch k_dcs_batch");
+}
+
+sal_status launch_fuse_batch(const FuseItem* items, int n, const int* adapt_list, int nadapt, const int64_t* first,
+                             int64_t rows, hipStream_t stream) {
+    sal_status st;
+    if (nadapt > 0) {
+        hipLaunchKernelGGL(k_fuse_stats_batch, dim3((unsigned)(nadapt * kBatchParts)), dim3(256), 0, stream, items,
+                           adapt_list);
+        if ((st = check_hip(hipGetLastError(), "launch k_fuse_stats_batch"))) return st;
+    }
+    hipLaunchKernelGGL(k_fuse_solve_batch, dim3((unsigned)n), dim3(64), 0, stream, items);
+    if ((st = check_hip(hipGetLastError(), "launch k_fuse_solve_batch"))) return st;
+    if (rows == 0) return SAL_OK;
+    hipLaunchKernelGGL(k_combine_batch, dim3((unsigned)rows), dim3(256), 0, stream, items, first, n);
+    return check_hip(hipGetLastError(), "launch k_combine_batch");
+}
+
+}  // namespace sal

@@ -1,0 +1,156 @@
+// sal_device.h -- device helpers shared by the single-volume and batched kernels of the
+// center-surround and fusion steps (not part of the ABI).
+#pragma once
+
+#include "sal_aux.h"
+
+namespace sal {
+
+// S_m at grid point j of one volume (Sec. 2, Eq. 3): (1/Q) sum over in-grid neighbours.
+__device__ __forceinline__ void dcs_point(const float* __restrict__ E, float* __restrict__ S, int64_t Tg,
+                                          int64_t ILg, int64_t XLg, const DcsStencil& st, int64_t j) {
+    const int64_t G = Tg * ILg * XLg;
+    const int64_t gx = j % XLg, gi = (j / XLg) % ILg, gt = j / (XLg * ILg);
+    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
+    const float e0 = E[j], e1 = E[G + j], e2 = E[2 * G + j];
+    int Q = 0;
+    for (int k = 0; k < st.q; k++) {
+        const int64_t nt = gt + st.o[k][0], ni = gi + st.o[k][1], nx = gx + st.o[k][2];
+        if (nt < 0 || nt >= Tg || ni < 0 || ni >= ILg || nx < 0 || nx >= XLg) continue;
+        const int64_t jn = (nt * ILg + ni) * XLg + nx;
+        const float w = st.w[k];
+        if (st.literal) {
+            acc0 += fabsf(e0 - w * E[jn]);
+            acc1 += fabsf(e1 - w * E[G + jn]);
+            acc2 += fabsf(e2 - w * E[2 * G + jn]);
+        } else {
+            acc0 += w * fabsf(e0 - E[jn]);
+            acc1 += w * fabsf(e1 - E[G + jn]);
+            acc2 += w * fabsf(e2 - E[2 * G + jn]);
+        }
+        Q++;
+    }
+    S[j] = Q ? acc0 / (float)Q : 0.f;
+    S[G + j] = Q ? acc1 / (float)Q : 0.f;
+    S[2 * G + j] = Q ? acc2 / (float)Q : 0.f;
+}
+
+// One block's FP64 partial sums of u u^T, u D, D^2 and the count over the masked
+// points j = first, first + stride, ... (fixed order: deterministic).  256 threads.
+__device__ __forceinline__ void fuse_stats_block(const float* __restrict__ Sm, const float* __restrict__ D,
+                                                 const uint8_t* __restrict__ mask, int64_t G, int64_t first,
+                                                 int64_t stride, double* __restrict__ out, double* red) {
+    double st[kStats];
+    for (int k = 0; k < kStats; k++) st[k] = 0.0;
+    for (int64_t j = first + threadIdx.x; j < G; j += stride) {
+        if (mask && !mask[j]) continue;
+        const double u0 = Sm[j], u1 = Sm[G + j], u2 = Sm[2 * G + j], d = D[j];
+        st[0] += u0 * u0; st[1] += u0 * u1; st[2] += u0 * u2;
+        st[3] += u1 * u1; st[4] += u1 * u2; st[5] += u2 * u2;
+        st[6] += u0 * d; st[7] += u1 * d; st[8] += u2 * d;
+        st[9] += d * d; st[10] += 1.0;
+    }
+    for (int k = 0; k < kStats; k++) {
+        red[threadIdx.x] = st[k];
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[k] = red[0];
+        __syncthreads();
+    }
+}
+
+// 3x3 Cholesky solve; 1 if A is not numerically positive definite.
+__device__ __forceinline__ int chol3(const double A[9], const double b[3], double x[3]) {
+    double dmax = 0.0;
+    for (int i = 0; i < 3; i++) {
+        if (!isfinite(A[4 * i])) return 1;
+        dmax = A[4 * i] > dmax ? A[4 * i] : dmax;
+    }
+    if (!(dmax > 0.0)) return 1;
+    double L[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int j = 0; j < 3; j++) {
+        double d = A[3 * j + j];
+        for (int k = 0; k < j; k++) d -= L[3 * j + k] * L[3 * j + k];
+        if (!(d > 1e-12 * dmax) || !isfinite(d)) return 1;
+        L[3 * j + j] = sqrt(d);
+        for (int i = j + 1; i < 3; i++) {
+            double v = A[3 * i + j];
+            for (int k = 0; k < j; k++) v -= L[3 * i + k] * L[3 * j + k];
+            L[3 * i + j] = v / L[3 * j + j];
+        }
+    }
+    double y[3];
+    for (int i = 0; i < 3; i++) {
+        double v = b[i];
+        for (int k = 0; k < i; k++) v -= L[3 * i + k] * y[k];
+        y[i] = v / L[3 * i + i];
+    }
+    for (int i = 2; i >= 0; i--) {
+        double v = y[i];
+        for (int k = i + 1; k < 3; k++) v -= L[3 * k + i] * x[k];
+        x[i] = v / L[3 * i + i];
+    }
+    return 0;
+}
+
+// Weights of one volume from its reduced statistics (block of 64 threads): sums the
+// partials in block order, then solves; writes W[0..2] and the status word W[3].
+__device__ __forceinline__ void solve_weights(const double* __restrict__ part, int nparts, int mode, double w0,
+                                              double w1, double w2, double delta, double* __restrict__ W,
+                                              double* __restrict__ stats_out, double* st) {
+    if (threadIdx.x < kStats && mode == SAL_FUSE_ADAPT_LS) {
+        double s = 0.0;
+        for (int b = 0; b < nparts; b++) s += part[(int64_t)b * kStats + threadIdx.x];
+        st[threadIdx.x] = s;
+        if (stats_out) stats_out[threadIdx.x] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    if (mode == SAL_FUSE_EQUAL) {
+        W[0] = W[1] = W[2] = 1.0 / 3.0;
+        W[3] = 0.0;
+        return;
+    }
+    if (mode == SAL_FUSE_FIXED) {
+        W[0] = w0; W[1] = w1; W[2] = w2;
+        W[3] = 0.0;
+        return;
+    }
+    const double A[9] = {st[0] + delta, st[1], st[2], st[1], st[3] + delta, st[4], st[2], st[4], st[5] + delta};
+    const double b[3] = {st[6], st[7], st[8]};
+    double x[3];
+    if (chol3(A, b, x)) {
+        W[0] = W[1] = W[2] = 1.0 / 3.0;
+        W[3] = 1.0;
+    } else {
+        W[0] = x[0]; W[1] = x[1]; W[2] = x[2];
+        W[3] = 0.0;
+    }
+}
+
+__device__ __forceinline__ int64_t cell_of(int64_t v, int s, int64_t Ng) {
+    const int64_t g = (v + (s - 1) / 2) / s;
+    return g < Ng - 1 ? g : Ng - 1;
+}
+
+// One (t, il) row of S(v) = sum_m W_m S_m(g(v)) (Eq. 4), threads striding along xl.
+__device__ __forceinline__ void combine_row(const float* __restrict__ Sm, const double* __restrict__ W, int64_t Tg,
+                                            int64_t ILg, int64_t XLg, int64_t IL, int64_t XL, int s, int64_t row,
+                                            float* __restrict__ S) {
+    const int64_t t = row / IL, i = row % IL;
+    const int64_t G = Tg * ILg * XLg;
+    const int64_t base = (cell_of(t, s, Tg) * ILg + cell_of(i, s, ILg)) * XLg;
+    const double W0 = W[0], W1 = W[1], W2 = W[2];
+    const int sh = (s - 1) / 2;
+    for (int x = threadIdx.x; x < XL; x += blockDim.x) {
+        int gx = (x + sh) / s;
+        gx = gx < XLg - 1 ? gx : (int)XLg - 1;
+        const int64_t j = base + gx;
+        S[row * XL + x] = (float)(W0 * (double)Sm[j] + W1 * (double)Sm[G + j] + W2 * (double)Sm[2 * G + j]);
+    }
+}
+
+}  // namespace sal

@@ -18,7 +18,11 @@
 // each bin times its per-plane weight mult(kx) alpha_m(k) / n^3, accumulated
 // per window and reduced across lane groups at the end.  Nothing but E
 // leaves the chip.
-#include "sal_internal.h"
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "sal_aux.h"
 
 namespace sal {
 
@@ -47,36 +51,38 @@ __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-template <int N, int CTW>
-__global__ __launch_bounds__(512) void k_project_fp32(ProjParams p) {
+constexpr int kNT = 1024;  // threads per workgroup: 16 waves, 4 per SIMD
+
+// One tile of CT x 4 x 4 centres.  S > 0 fixes the stride at compile time (rows of
+// pass A then live in registers); S == 0 reads it from the parameters.
+template <int N, int S, int CTW>
+__device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int64_t tile, float* lds) {
     constexpr int KH = N / 2 + 1;
     constexpr int NK = N / 4;
-    extern __shared__ float lds[];
+    constexpr int UH = N / 2;  // ki slots per half of the waves
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int col = lane & 15;
     const int grp = lane >> 4;
 
-    // consecutive workgroups land on different XCDs: give each XCD a contiguous run of tiles
-    const int64_t per = (p.ntiles + 7) / 8;
-    const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
-    if (tile >= p.ntiles) return;
     const int64_t tx = tile % p.tilesX;
     const int64_t ti = (tile / p.tilesX) % p.tilesI;
     const int64_t tt = tile / (p.tilesX * p.tilesI);
 
-    const int s = p.s, RT = p.RT, RI = p.RI, RX = p.RX, RXp = p.RXp, CT = p.CT;
-    float* Vt = lds;                                  // [RT][RI][RXp]
-    float* Ab = Vt + (size_t)RT * RI * RXp;           // [2][RT][RI][4]
-    float* Gb = Ab + (size_t)2 * RT * RI * 4;         // [2][N][RT][16]
+    const int s = S > 0 ? S : p.s;
+    const int RT = p.RT, RI = p.RI, RX = p.RX, RXp = p.RXp, CT = p.CT;
+    float* Vt = lds;                                               // [RT][RI][RXp]
+    float* Ab = Vt + (((size_t)RT * RI * RXp + 3) & ~(size_t)3);  // [2][RT][RI][4], 16-byte aligned
+    float* Gb = Ab + (size_t)2 * RT * RI * 4;                      // [2][N][RT][16]
+    float4* Wl = (float4*)(Gb + (size_t)2 * N * RT * 16);          // [N][16] bin weights of the current kx
     const int abStride = RT * RI * 4;
     const int gbStride = N * RT * 16;
 
     // stage the tile and its halo, reflected at the volume borders
     const int64_t t0 = tt * CT * s - N / 2, i0 = ti * 4 * s - N / 2, x0 = tx * 4 * s - N / 2;
     const int nreg = RT * RI * RX;
-    for (int e = tid; e < nreg; e += 512) {
+    for (int e = tid; e < nreg; e += kNT) {
         const int rx = e % RX;
         const int r = e / RX;
         const int ri = r % RI, rt = r / RI;
@@ -90,6 +96,9 @@ __global__ __launch_bounds__(512) void k_project_fp32(ProjParams p) {
 #pragma unroll
     for (int ks = 0; ks < NK; ks++) amat[ks] = p.mat[col * N + 4 * ks + grp];
 
+    // pass C work of this wave: t-centres wave%8 (+8c), ki slots of one half
+    const int wtc = wave & 7;
+    const int u0 = (wave >> 3) * UH;
     float acc[CTW][3];
 #pragma unroll
     for (int c = 0; c < CTW; c++) acc[c][0] = acc[c][1] = acc[c][2] = 0.f;
@@ -105,36 +114,62 @@ __global__ __launch_bounds__(512) void k_project_fp32(ProjParams p) {
                 cA[a] = p.passA[(kx * N + a) * 2];
                 sA[a] = p.passA[(kx * N + a) * 2 + 1];
             }
-            for (int r = tid; r < RT * RI; r += 512) {
+            for (int r = tid; r < RT * RI; r += kNT) {
                 const float* row = Vt + r * RXp;
                 float o[8];
+                if constexpr (S > 0) {
+                    constexpr int RXc = 3 * S + N;
+                    float v[RXc];
 #pragma unroll
-                for (int xc = 0; xc < 4; xc++) {
-                    float ar = 0.f, ai = 0.f;
+                    for (int k = 0; k < RXc; k++) v[k] = row[k];
 #pragma unroll
-                    for (int a = 0; a < N; a++) {
-                        const float v = row[xc * s + a];
-                        ar = fmaf(cA[a], v, ar);
-                        ai = fmaf(sA[a], v, ai);
+                    for (int xc = 0; xc < 4; xc++) {
+                        float ar = 0.f, ai = 0.f;
+#pragma unroll
+                        for (int a = 0; a < N; a++) {
+                            ar = fmaf(cA[a], v[xc * S + a], ar);
+                            ai = fmaf(sA[a], v[xc * S + a], ai);
+                        }
+                        o[xc] = ar;
+                        o[4 + xc] = ai;
                     }
-                    o[xc] = ar;
-                    o[4 + xc] = ai;
+                } else {
+#pragma unroll
+                    for (int xc = 0; xc < 4; xc++) {
+                        float ar = 0.f, ai = 0.f;
+#pragma unroll
+                        for (int a = 0; a < N; a++) {
+                            const float v = row[xc * s + a];
+                            ar = fmaf(cA[a], v, ar);
+                            ai = fmaf(sA[a], v, ai);
+                        }
+                        o[xc] = ar;
+                        o[4 + xc] = ai;
+                    }
                 }
                 *(float4*)&Ab[r * 4] = make_float4(o[0], o[1], o[2], o[3]);
                 *(float4*)&Ab[abStride + r * 4] = make_float4(o[4], o[5], o[6], o[7]);
             }
         }
         __syncthreads();
+        // bin weights of this kx (their previous readers all passed the barrier above)
+        for (int e = tid; e < N * 16; e += kNT) Wl[e] = p.wts[(size_t)kx * N * 16 + e];
         // ---- pass B: complex DFT along il on the matrix cores, combined into signed ki slots
         {
             const int ilc = col >> 2, xc = col & 3;
-            for (int rt = wave; rt < RT; rt += 8) {
+            for (int rt = wave; rt < RT; rt += kNT / 64) {
                 f4 dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};
+                float xr[NK], xi[NK];
 #pragma unroll
                 for (int ks = 0; ks < NK; ks++) {
                     const int idx = (rt * RI + ilc * s + 4 * ks + grp) * 4 + xc;
-                    dr = mfma4(amat[ks], Ab[idx], dr);
-                    di = mfma4(amat[ks], Ab[abStride + idx], di);
+                    xr[ks] = Ab[idx];
+                    xi[ks] = Ab[abStride + idx];
+                }
+#pragma unroll
+                for (int ks = 0; ks < NK; ks++) {
+                    dr = mfma4(amat[ks], xr[ks], dr);
+                    di = mfma4(amat[ks], xi[ks], di);
                 }
 #pragma unroll
                 for (int pr = 0; pr < 2; pr++) {
@@ -160,21 +195,39 @@ __global__ __launch_bounds__(512) void k_project_fp32(ProjParams p) {
             }
         }
         __syncthreads();
-        // ---- pass C along t on the matrix cores, then |F| * weights into the window sums
-        for (int u = 0; u < N; u++) {
-            const float4* wrow = p.wts + ((size_t)(kx * N + u) * 16 + 4 * grp);
-            const float4 w0 = wrow[0], w1 = wrow[1], w2 = wrow[2], w3 = wrow[3];
+        // ---- pass C along t on the matrix cores, then |F| * weights into the window sums.
+        // The contraction of slot u+1 is issued before the epilogue of slot u, so the
+        // matrix cores and the VALU work on different slots at the same time.
 #pragma unroll
-            for (int c = 0; c < CTW; c++) {
-                const int tc = wave + 8 * c;
-                if (tc >= CT) continue;
-                f4 dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};
-                const float* gr = Gb + (u * RT + tc * s + grp) * 16 + col;
+        for (int c = 0; c < CTW; c++) {
+            const int tc = wtc + 8 * c;
+            if (tc >= CT) break;
+            const float* gbase = Gb + (tc * s + grp) * 16 + col;
+            auto contract = [&](int u, f4& dr, f4& di) {
+                const float* gr = gbase + u * RT * 16;
+                float br[NK], bi[NK];
 #pragma unroll
                 for (int ks = 0; ks < NK; ks++) {
-                    dr = mfma4(amat[ks], gr[ks * 64], dr);
-                    di = mfma4(amat[ks], gr[gbStride + ks * 64], di);
+                    br[ks] = gr[ks * 64];
+                    bi[ks] = gr[gbStride + ks * 64];
                 }
+                dr = f4{0.f, 0.f, 0.f, 0.f};
+                di = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < NK; ks++) {
+                    dr = mfma4(amat[ks], br[ks], dr);
+                    di = mfma4(amat[ks], bi[ks], di);
+                }
+            };
+            f4 dr, di;
+            contract(u0, dr, di);
+#pragma unroll
+            for (int uu = 0; uu < UH; uu++) {
+                const int u = u0 + uu;
+                const float4* wrow = Wl + u * 16 + 4 * grp;
+                const float4 w0 = wrow[0], w1 = wrow[1], w2 = wrow[2], w3 = wrow[3];
+                f4 nr, ni;
+                if (uu + 1 < UH) contract(u + 1, nr, ni);
 #pragma unroll
                 for (int pr = 0; pr < 2; pr++) {
                     const bool sp = (grp == 0) && (pr == 0);
@@ -188,30 +241,82 @@ __global__ __launch_bounds__(512) void k_project_fp32(ProjParams p) {
                     acc[c][1] = fmaf(wa.y, m1, fmaf(wb.y, m2, acc[c][1]));
                     acc[c][2] = fmaf(wa.z, m1, fmaf(wb.z, m2, acc[c][2]));
                 }
+                if (uu + 1 < UH) {
+                    dr = nr;
+                    di = ni;
+                }
             }
         }
         // the next pass A writes only Ab, whose readers (pass B) all passed the barrier above
     }
 
-    // reduce the four lane groups that hold partial sums of the same window
-    const int64_t G = p.Tg * p.ILg * p.XLg;
+    // reduce the lane groups holding partial sums of the same window, then the two
+    // halves of the ki slots (waves w and w + 8) through LDS
+    __syncthreads();  // every wave is done with Gb; reuse it for the partial sums
+    float* red = Gb;  // [CTW][8][16][3]
+    float v[CTW][3];
 #pragma unroll
-    for (int c = 0; c < CTW; c++) {
-        const int tc = wave + 8 * c;
-        float v[3];
+    for (int c = 0; c < CTW; c++)
 #pragma unroll
         for (int m = 0; m < 3; m++) {
             float x = acc[c][m];
             x += __shfl_xor(x, 16);
             x += __shfl_xor(x, 32);
-            v[m] = x;
+            v[c][m] = x;
         }
-        const int64_t gt = tt * CT + tc, gi = ti * 4 + (col >> 2), gx = tx * 4 + (col & 3);
-        if (grp == 0 && tc < CT && gt < p.Tg && gi < p.ILg && gx < p.XLg) {
-            const int64_t j = (gt * p.ILg + gi) * p.XLg + gx;
+    if (wave >= 8 && grp == 0) {
 #pragma unroll
-            for (int m = 0; m < 3; m++) p.E[m * G + j] = v[m];
+        for (int c = 0; c < CTW; c++)
+#pragma unroll
+            for (int m = 0; m < 3; m++) red[((c * 8 + wtc) * 16 + col) * 3 + m] = v[c][m];
+    }
+    __syncthreads();
+    const int64_t G = p.Tg * p.ILg * p.XLg;
+    if (wave < 8 && grp == 0) {
+#pragma unroll
+        for (int c = 0; c < CTW; c++) {
+            const int tc = wtc + 8 * c;
+            const int64_t gt = tt * CT + tc, gi = ti * 4 + (col >> 2), gx = tx * 4 + (col & 3);
+            if (tc < CT && gt < p.Tg && gi < p.ILg && gx < p.XLg) {
+                const int64_t j = (gt * p.ILg + gi) * p.XLg + gx;
+#pragma unroll
+                for (int m = 0; m < 3; m++) p.E[m * G + j] = v[c][m] + red[((c * 8 + wtc) * 16 + col) * 3 + m];
+            }
         }
+    }
+}
+
+// One tile per workgroup; consecutive workgroups land on different XCDs, so
+// each XCD gets a contiguous run of tiles (neighbouring halos share its L2).
+template <int N, int S, int CTW>
+__global__ __launch_bounds__(kNT) void k_project_fp32(ProjParams p) {
+    extern __shared__ float lds[];
+    const int64_t per = (p.ntiles + 7) / 8;
+    const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (tile >= p.ntiles) return;
+    project_tile_fp32<N, S, CTW>(p, tile, lds);
+}
+
+// Persistent form over the concatenated tiles of many volumes of one window
+// class: workgroup b of XCD b % 8 walks that XCD's contiguous share of the
+// global tile range with a static stride (every tile is independent, so the
+// result does not depend on which workgroup computes it).
+template <int N, int S, int CTW>
+__global__ __launch_bounds__(kNT) void k_project_fp32_batch(const ProjParams* __restrict__ items,
+                                                            const int64_t* __restrict__ prefix, int nitems,
+                                                            int64_t total) {
+    extern __shared__ float lds[];
+    const int64_t per = (total + 7) / 8;
+    const int64_t xcd = blockIdx.x % 8, local = blockIdx.x / 8, stride = gridDim.x / 8;
+    const int64_t lo = xcd * per, hi = lo + per < total ? lo + per : total;
+    for (int64_t g = lo + local; g < hi; g += stride) {
+        int a = 0, b = nitems - 1;  // last item with prefix[item] <= g
+        while (a < b) {
+            const int m = (a + b + 1) / 2;
+            if (prefix[m] <= g) a = m; else b = m - 1;
+        }
+        __syncthreads();
+        project_tile_fp32<N, S, CTW>(items[a], g - prefix[a], lds);
     }
 }
 
@@ -220,26 +325,42 @@ static size_t proj_lds_bytes(int n, int s, int CT, int* RT, int* RI, int* RX, in
     *RI = 3 * s + n;
     *RX = 3 * s + n;
     *RXp = *RX | 1;  // odd row pitch: conflict-free row reads in pass A
-    return sizeof(float) * ((size_t)(*RT) * (*RI) * (*RXp) + 2 * (size_t)(*RT) * (*RI) * 4 + 2 * (size_t)n * (*RT) * 16);
+    const size_t gb = std::max<size_t>(2 * (size_t)n * (*RT) * 16, 8 * 16 * 3 * 4);  // also holds the final sums
+    return sizeof(float) * ((((size_t)(*RT) * (*RI) * (*RXp) + 3) & ~(size_t)3) + 2 * (size_t)(*RT) * (*RI) * 4 + gb +
+                            (size_t)n * 16 * 4);
 }
 
 static constexpr size_t kLdsMax = 160 * 1024;
 
-template <int N, int CTW>
-static sal_status launch_project(const float* V, int64_t T, int64_t IL, int64_t XL, int s, const Tables* tb,
-                                 float* E, hipStream_t stream) {
+static int fp32_ctw(int n) { return n == 4 ? 2 : 1; }
+
+// Tile depths (t-centres per tile) that fit the LDS, deepest first.
+void project_fp32_ct_candidates(int n, int s, std::vector<int>* out) {
+    out->clear();
+    const int mx = 8 * fp32_ctw(n);
+    int RT, RI, RX, RXp;
+    for (int CT = mx; CT >= 1; CT--) {
+        if (proj_lds_bytes(n, s, CT, &RT, &RI, &RX, &RXp) > kLdsMax) continue;
+        if (out->empty() || CT == mx / 2 || CT == (3 * mx) / 4 || CT == mx / 4) out->push_back(CT);
+    }
+}
+
+sal_status project_fp32_params(int n, int s, int CT, const float* V, int64_t T, int64_t IL, int64_t XL,
+                               const Tables* tb, float* E, void* out, int64_t* ntiles, size_t* lds) {
     ProjParams p;
     p.V = V;
     p.T = T; p.IL = IL; p.XL = XL;
     p.Tg = ceil_div(T, s); p.ILg = ceil_div(IL, s); p.XLg = ceil_div(XL, s);
     p.s = s;
-    int CT = 8 * CTW;
-    size_t lds = 0;
-    for (; CT >= 1; CT--) {
-        lds = proj_lds_bytes(N, s, CT, &p.RT, &p.RI, &p.RX, &p.RXp);
-        if (lds <= kLdsMax) break;
+    if (CT <= 0) {
+        std::vector<int> c;
+        project_fp32_ct_candidates(n, s, &c);
+        if (c.empty()) return fail(SAL_ERR_UNSUPPORTED, "stride too large for the LDS tile");
+        CT = c[0];
     }
-    if (CT < 1) return fail(SAL_ERR_UNSUPPORTED, "stride too large for the LDS tile");
+    if (CT > 8 * fp32_ctw(n)) return fail(SAL_ERR_ARG, "tile depth too large");
+    *lds = proj_lds_bytes(n, s, CT, &p.RT, &p.RI, &p.RX, &p.RXp);
+    if (*lds > kLdsMax) return fail(SAL_ERR_UNSUPPORTED, "tile does not fit the LDS");
     p.CT = CT;
     p.tilesT = ceil_div(p.Tg, CT);
     p.tilesI = ceil_div(p.ILg, 4);
@@ -249,30 +370,98 @@ static sal_status launch_project(const float* V, int64_t T, int64_t IL, int64_t 
     p.mat = tb->mat;
     p.wts = (const float4*)tb->wts;
     p.E = E;
-    if (p.ntiles == 0) return SAL_OK;
+    *ntiles = p.ntiles;
+    if (out) memcpy(out, &p, sizeof(p));
+    return SAL_OK;
+}
+
+size_t project_fp32_param_bytes() { return sizeof(ProjParams); }
+
+template <typename K>
+static sal_status set_lds_attr(K kernel, const char* what) {
+    return check_hip(hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax),
+                     what);
+}
+
+// (n, s) -> the compiled kernel: strides 1..3 have their own instances, larger ones
+// take the run-time-stride form.
+#define SAL_FP32_DISPATCH(CALL)                                            \
+    switch (n) {                                                           \
+        case 4: return CALL(4, 1, 2);                                      \
+        case 8:                                                            \
+            if (s == 1) return CALL(8, 1, 1);                              \
+            if (s == 2) return CALL(8, 2, 1);                              \
+            if (s == 3) return CALL(8, 3, 1);                              \
+            return CALL(8, 0, 1);                                          \
+        case 12:                                                           \
+            if (s == 1) return CALL(12, 1, 1);                             \
+            if (s == 2) return CALL(12, 2, 1);                             \
+            if (s == 3) return CALL(12, 3, 1);                             \
+            return CALL(12, 0, 1);                                         \
+        case 16:                                                           \
+            if (s == 1) return CALL(16, 1, 1);                             \
+            if (s == 2) return CALL(16, 2, 1);                             \
+            if (s == 3) return CALL(16, 3, 1);                             \
+            return CALL(16, 0, 1);                                         \
+        default: return fail(SAL_ERR_UNSUPPORTED, "window side not built"); \
+    }
+
+template <int N, int S, int CTW>
+static sal_status launch_project(const ProjParams& p, size_t lds, hipStream_t stream) {
     static bool attr_set = false;
     if (!attr_set) {
-        sal_status st = check_hip(hipFuncSetAttribute((const void*)k_project_fp32<N, CTW>,
-                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax),
-                                  "hipFuncSetAttribute(project)");
+        sal_status st = set_lds_attr(k_project_fp32<N, S, CTW>, "hipFuncSetAttribute(project)");
         if (st) return st;
         attr_set = true;
     }
     const int64_t grid = 8 * ((p.ntiles + 7) / 8);
     if (grid > INT32_MAX) return fail(SAL_ERR_SHAPE, "volume too large for one launch");
-    hipLaunchKernelGGL((k_project_fp32<N, CTW>), dim3((unsigned)grid), dim3(512), lds, stream, p);
+    hipLaunchKernelGGL((k_project_fp32<N, S, CTW>), dim3((unsigned)grid), dim3(kNT), lds, stream, p);
     return check_hip(hipGetLastError(), "launch k_project_fp32");
 }
 
 sal_status launch_project_fp32(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s, const Tables* tb,
                                float* E, hipStream_t stream) {
-    switch (n) {
-        case 4: return launch_project<4, 4>(V, T, IL, XL, s, tb, E, stream);
-        case 8: return launch_project<8, 2>(V, T, IL, XL, s, tb, E, stream);
-        case 12: return launch_project<12, 1>(V, T, IL, XL, s, tb, E, stream);
-        case 16: return launch_project<16, 1>(V, T, IL, XL, s, tb, E, stream);
-        default: return fail(SAL_ERR_UNSUPPORTED, "window side not built");
-    }
+    ProjParams p;
+    int64_t nt = 0;
+    size_t lds = 0;
+    sal_status st = project_fp32_params(n, s, 0, V, T, IL, XL, tb, E, &p, &nt, &lds);
+    if (st) return st;
+    if (nt == 0) return SAL_OK;
+#define CALL(NN, SS, CC) launch_project<NN, SS, CC>(p, lds, stream)
+    SAL_FP32_DISPATCH(CALL)
+#undef CALL
+}
+
+template <int N, int S, int CTW>
+static sal_status launch_batch(const void* items, const int64_t* prefix, int nitems, int64_t total, size_t lds,
+                               int grid, hipStream_t stream) {
+    // the LDS attribute was set by project_fp32_batch_occupancy(), outside any stream capture
+    hipLaunchKernelGGL((k_project_fp32_batch<N, S, CTW>), dim3((unsigned)grid), dim3(kNT), lds, stream,
+                       (const ProjParams*)items, prefix, nitems, total);
+    return check_hip(hipGetLastError(), "launch k_project_fp32_batch");
+}
+
+template <int N, int S, int CTW>
+static sal_status batch_occupancy(size_t lds, int* per_cu) {
+    sal_status st = set_lds_attr(k_project_fp32_batch<N, S, CTW>, "hipFuncSetAttribute(project batch)");
+    if (st) return st;
+    return check_hip(
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_project_fp32_batch<N, S, CTW>, kNT, lds),
+        "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+}
+
+sal_status project_fp32_batch(int n, int s, const void* items, const int64_t* prefix, int nitems, int64_t total,
+                              size_t lds, int grid, hipStream_t stream) {
+#define CALL(NN, SS, CC) launch_batch<NN, SS, CC>(items, prefix, nitems, total, lds, grid, stream)
+    SAL_FP32_DISPATCH(CALL)
+#undef CALL
+}
+
+sal_status project_fp32_batch_occupancy(int n, int s, size_t lds, int* per_cu) {
+#define CALL(NN, SS, CC) batch_occupancy<NN, SS, CC>(lds, per_cu)
+    SAL_FP32_DISPATCH(CALL)
+#undef CALL
 }
 
 }  // namespace sal
