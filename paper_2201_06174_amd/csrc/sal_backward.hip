@@ -16,6 +16,7 @@
 // it directly or through the border reflection, in a fixed order (no atomics,
 // bitwise reproducible).
 #include "sal_aux.h"
+#include "sal_stage.h"
 
 namespace sal {
 
@@ -91,14 +92,7 @@ __global__ __launch_bounds__(512) void k_spectral_adjoint(AdjParams p) {
     constexpr int gbStride = N * RT * 16;
 
     const int64_t t0 = tt * CT * S - N / 2, i0 = ti * 4 * S - N / 2, x0 = tx * 4 * S - N / 2;
-    for (int e = tid; e < RT * RI * RX; e += 512) {
-        const int rx = e % RX;
-        const int r = e / RX;
-        const int ri = r % RI, rt = r / RI;
-        const int64_t gt = reflect_clamp_b(t0 + rt, p.T), gi = reflect_clamp_b(i0 + ri, p.IL),
-                      gx = reflect_clamp_b(x0 + rx, p.XL);
-        Vt[(rt * RI + ri) * RXp + rx] = p.V[(gt * p.IL + gi) * p.XL + gx];
-    }
+    stage_tile<512>(p.V, p.T, p.IL, p.XL, t0, i0, x0, RT, RI, RX, RXp, Vt);
     for (int e = tid; e < KH * N * 2; e += 512) tab[e] = p.passA[e];
 
     float amat[NK], ainvB[NK], ainvC[4];

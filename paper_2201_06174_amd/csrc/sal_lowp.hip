@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "sal_aux.h"
+#include "sal_stage.h"
 
 namespace sal {
 
@@ -128,7 +129,8 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
     using L = Lp<PREC>;
     typedef typename L::vec vec;
     constexpr int KH = N / 2 + 1;
-    constexpr int UH = N / 2;
+    constexpr int NW = kNTL / 64;
+    constexpr int UH = N * 8 / NW;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -140,7 +142,8 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
     const int64_t tt = tile / (p.tilesX * p.tilesI);
 
     const int s = S > 0 ? S : p.s;
-    const int RT = p.RT, RTp = p.RTp, RI = p.RI, RX = p.RX, RXp = p.RXp, CT = p.CT;
+    const int RT = p.RT, RTp = p.RTp, CT = p.CT;
+    const int RI = S > 0 ? 3 * S + N : p.RI, RX = RI, RXp = S > 0 ? ((3 * S + N) | 1) : p.RXp;
     float* Vt = lds;                                               // [RT][RI][RXp]
     float* Ab = Vt + (((size_t)RT * RI * RXp + 3) & ~(size_t)3);  // [2][RT][RI][4], 16-byte aligned
     uint16_t* Gh = (uint16_t*)(Ab + (size_t)2 * RT * RI * 4);     // [2][N][16][RTp]
@@ -151,14 +154,7 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
     const int gStrideRi = N * 16 * RTp;
 
     const int64_t t0 = tt * CT * s - N / 2, i0 = ti * 4 * s - N / 2, x0 = tx * 4 * s - N / 2;
-    for (int e = tid; e < RT * RI * RX; e += kNTL) {
-        const int rx = e % RX;
-        const int r = e / RX;
-        const int ri = r % RI, rt = r / RI;
-        const int64_t gt = reflect_clamp_l(t0 + rt, p.T), gi = reflect_clamp_l(i0 + ri, p.IL),
-                      gx = reflect_clamp_l(x0 + rx, p.XL);
-        Vt[(rt * RI + ri) * RXp + rx] = p.V[(gt * p.IL + gi) * p.XL + gx];
-    }
+    stage_tile<kNTL>(p.V, p.T, p.IL, p.XL, t0, i0, x0, RT, RI, RX, RXp, Vt);
     // the samples past the last staged row only meet zero coefficients; keep them finite
     for (int e = tid; e < 2 * N * 16 * (RTp - RT); e += kNTL) {
         const int pad = RTp - RT;
@@ -341,7 +337,7 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
             x += __shfl_xor(x, 32);
             v[c][m] = x;
         }
-    if (wave >= 8 && grp == 0) {
+    if (NW > 8 && wave >= 8 && grp == 0) {
 #pragma unroll
         for (int c = 0; c < CTW; c++)
 #pragma unroll
@@ -357,7 +353,7 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
             if (tc < CT && gt < p.Tg && gi < p.ILg && gx < p.XLg) {
                 const int64_t j = (gt * p.ILg + gi) * p.XLg + gx;
 #pragma unroll
-                for (int m = 0; m < 3; m++) p.E[m * G + j] = v[c][m] + red[((c * 8 + wtc) * 16 + col) * 3 + m];
+                for (int m = 0; m < 3; m++) p.E[m * G + j] = v[c][m] + (NW > 8 ? red[((c * 8 + wtc) * 16 + col) * 3 + m] : 0.f);
             }
         }
     }
@@ -393,7 +389,12 @@ __global__ __launch_bounds__(kNTL) void k_project_lowp_batch(const LowpParams* _
 
 static size_t lowp_lds_bytes(int n, int s, int CT, bool split, LowpParams* p) {
     p->RT = (CT - 1) * s + n;
-    p->RTp = ((CT - 1) * s + 17 + 1) & ~1;  // even, one sample of slack for realigned odd starts
+    // row pitch in 16-bit samples: even (dword-aligned rows), one sample of slack for realigned
+    // odd starts, and an odd-times-4-plus-3 dword pitch so the 16 columns of a wave's reads
+    // and writes fall into distinct LDS banks
+    int R = ((CT - 1) * s + 18) / 2;
+    while ((R & 3) != 3) R++;
+    p->RTp = 2 * R;
     p->RI = 3 * s + n;
     p->RX = 3 * s + n;
     p->RXp = p->RX | 1;

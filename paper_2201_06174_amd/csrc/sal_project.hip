@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "sal_aux.h"
+#include "sal_stage.h"
 
 namespace sal {
 
@@ -59,7 +60,8 @@ template <int N, int S, int CTW>
 __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int64_t tile, float* lds) {
     constexpr int KH = N / 2 + 1;
     constexpr int NK = N / 4;
-    constexpr int UH = N / 2;  // ki slots per half of the waves
+    constexpr int NW = kNT / 64;           // waves per workgroup (8 or 16)
+    constexpr int UH = N * 8 / NW;        // ki slots per wave
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -71,7 +73,8 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
     const int64_t tt = tile / (p.tilesX * p.tilesI);
 
     const int s = S > 0 ? S : p.s;
-    const int RT = p.RT, RI = p.RI, RX = p.RX, RXp = p.RXp, CT = p.CT;
+    const int RT = p.RT, CT = p.CT;
+    const int RI = S > 0 ? 3 * S + N : p.RI, RX = RI, RXp = S > 0 ? ((3 * S + N) | 1) : p.RXp;
     float* Vt = lds;                                               // [RT][RI][RXp]
     float* Ab = Vt + (((size_t)RT * RI * RXp + 3) & ~(size_t)3);  // [2][RT][RI][4], 16-byte aligned
     float* Gb = Ab + (size_t)2 * RT * RI * 4;                      // [2][N][RT][16]
@@ -81,15 +84,7 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
 
     // stage the tile and its halo, reflected at the volume borders
     const int64_t t0 = tt * CT * s - N / 2, i0 = ti * 4 * s - N / 2, x0 = tx * 4 * s - N / 2;
-    const int nreg = RT * RI * RX;
-    for (int e = tid; e < nreg; e += kNT) {
-        const int rx = e % RX;
-        const int r = e / RX;
-        const int ri = r % RI, rt = r / RI;
-        const int64_t gt = reflect_clamp(t0 + rt, p.T), gi = reflect_clamp(i0 + ri, p.IL),
-                      gx = reflect_clamp(x0 + rx, p.XL);
-        Vt[(rt * RI + ri) * RXp + rx] = p.V[(gt * p.IL + gi) * p.XL + gx];
-    }
+    stage_tile<kNT>(p.V, p.T, p.IL, p.XL, t0, i0, x0, RT, RI, RX, RXp, Vt);
 
     // A operand of both MFMA passes: packed taper*DFT rows
     float amat[NK];
@@ -264,7 +259,7 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
             x += __shfl_xor(x, 32);
             v[c][m] = x;
         }
-    if (wave >= 8 && grp == 0) {
+    if (NW > 8 && wave >= 8 && grp == 0) {
 #pragma unroll
         for (int c = 0; c < CTW; c++)
 #pragma unroll
@@ -280,7 +275,7 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
             if (tc < CT && gt < p.Tg && gi < p.ILg && gx < p.XLg) {
                 const int64_t j = (gt * p.ILg + gi) * p.XLg + gx;
 #pragma unroll
-                for (int m = 0; m < 3; m++) p.E[m * G + j] = v[c][m] + red[((c * 8 + wtc) * 16 + col) * 3 + m];
+                for (int m = 0; m < 3; m++) p.E[m * G + j] = v[c][m] + (NW > 8 ? red[((c * 8 + wtc) * 16 + col) * 3 + m] : 0.f);
             }
         }
     }
