@@ -22,13 +22,15 @@ namespace sal {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 
 struct LowpParams {
     const float* V;
     int64_t T, IL, XL;
     int64_t Tg, ILg, XLg;
     int s;
-    int CT, RT, RTp, RI, RX, RXp;
+    int CT, RT, RTp, RI, RX, RXp, IQ2;
     int64_t tilesT, tilesI, tilesX, ntiles;
     const float* passA;
     const uint16_t* cpx_a;  // hi (bf16) or fp16 operand table [2][16][32]
@@ -61,6 +63,15 @@ struct Lp<SAL_PREC_SPLIT_BF16> {
         for (int i = 0; i < 8; i++) v[i] = __builtin_bit_cast(__bf16, b[i]);
         return v;
     }
+    // a in the low half, b in the high half, each rounded to nearest even
+    __device__ static __forceinline__ uint32_t pack_hi(float a, float b) {
+        const bf2 v = {(__bf16)a, (__bf16)b};
+        return __builtin_bit_cast(uint32_t, v);
+    }
+    // the rounded residuals x - hi (exact in fp32) of the pair packed by pack_hi
+    __device__ static __forceinline__ uint32_t pack_lo(float a, float b, uint32_t h) {
+        return pack_hi(a - __uint_as_float(h << 16), b - __uint_as_float(h & 0xffff0000u));
+    }
     __device__ static __forceinline__ f4 mma(vec a, vec b, f4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
     }
@@ -78,6 +89,11 @@ struct Lp<SAL_PREC_FP16> {
         for (int i = 0; i < 8; i++) v[i] = __builtin_bit_cast(_Float16, b[i]);
         return v;
     }
+    __device__ static __forceinline__ uint32_t pack_hi(float a, float b) {
+        const h2 v = {(_Float16)a, (_Float16)b};
+        return __builtin_bit_cast(uint32_t, v);
+    }
+    __device__ static __forceinline__ uint32_t pack_lo(float, float, uint32_t) { return 0; }
     __device__ static __forceinline__ f4 mma(vec a, vec b, f4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
     }
@@ -124,6 +140,30 @@ __device__ __forceinline__ typename Lp<PREC>::vec vec_from_words(const uint32_t 
     return __builtin_bit_cast(typename Lp<PREC>::vec, v);
 }
 
+// Eight consecutive il samples of one (plane, rt, xc) from an Ab row laid out as
+// [il/2][xc][il&1] (dword k*4 + xc holds il = 2k, 2k+1).  `rowx` points at dword xc of
+// il/2 = 0.  An even stride keeps every lane's start even; otherwise each lane realigns
+// by its own start parity.
+template <int S>
+__device__ __forceinline__ void load8_ab(const uint32_t* rowx, int il0, uint32_t (&w)[4]) {
+    const uint32_t* q = rowx + (il0 >> 1) * 4;
+    if constexpr (S > 0 && (S & 1) == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) w[k] = q[4 * k];
+    } else {
+        uint32_t a[5];
+#pragma unroll
+        for (int k = 0; k < 5; k++) a[k] = q[4 * k];
+        const uint32_t sh = (il0 & 1) * 2;
+#pragma unroll
+        for (int k = 0; k < 4; k++) w[k] = __builtin_amdgcn_alignbyte(a[k + 1], a[k], sh);
+    }
+}
+
+// dwords per Ab row plane: covers the furthest 5-dword read of pass B, starting at
+// il = 3s + 8 for the last window column and the upper K half
+__host__ __device__ constexpr int ab_iq2(int s) { return (3 * s + 8) / 2 + 5; }
+
 template <int N, int S, int PREC, int CTW>
 __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int64_t tile, float* lds) {
     using L = Lp<PREC>;
@@ -131,6 +171,7 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
     constexpr int KH = N / 2 + 1;
     constexpr int NW = kNTL / 64;
     constexpr int UH = N * 8 / NW;
+    constexpr int NPL = L::split ? 4 : 2;  // Ab planes: (hi, lo) x (real, imaginary)
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -142,14 +183,15 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
     const int64_t tt = tile / (p.tilesX * p.tilesI);
 
     const int s = S > 0 ? S : p.s;
-    const int RT = p.RT, RTp = p.RTp, CT = p.CT;
+    const int RT = p.RT, RTe = (p.RT + 1) & ~1, RTp = p.RTp, CT = p.CT;
     const int RI = S > 0 ? 3 * S + N : p.RI, RX = RI, RXp = S > 0 ? ((3 * S + N) | 1) : p.RXp;
-    float* Vt = lds;                                               // [RT][RI][RXp]
-    float* Ab = Vt + (((size_t)RT * RI * RXp + 3) & ~(size_t)3);  // [2][RT][RI][4], 16-byte aligned
-    uint16_t* Gh = (uint16_t*)(Ab + (size_t)2 * RT * RI * 4);     // [2][N][16][RTp]
-    uint16_t* Gl = Gh + (size_t)2 * N * 16 * RTp;                 // same, lo parts (split only)
+    const int IQ2 = S > 0 ? ab_iq2(S) : p.IQ2;
+    float* Vt = lds;                                                     // [RT][RI][RXp] fp32
+    uint16_t* Ab = (uint16_t*)(Vt + (((size_t)RT * RI * RXp + 3) & ~(size_t)3));  // [NPL][RTe][IQ2][4][2]
+    const int abPlane = RTe * IQ2 * 8;
+    uint16_t* Gh = Ab + (size_t)NPL * abPlane;                          // [2][N][16][RTp]
+    uint16_t* Gl = Gh + (size_t)2 * N * 16 * RTp;                        // same, lo parts (split only)
     float4* Wl = (float4*)(Gl + (L::split ? (size_t)2 * N * 16 * RTp : 0));  // [N][16] weights of this kx
-    const int abStride = RT * RI * 4;
     const int gRow = RTp;  // one (ri, u, col) sample row; RTp is even, rows stay 4-byte aligned
     const int gStrideRi = N * 16 * RTp;
 
@@ -163,7 +205,7 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
         if constexpr (L::split) Gl[r * RTp + k] = 0;
     }
 
-    // A operands: lane supplies row = col, K slots 8*grp .. 8*grp+7
+    // DFT operands: lane supplies bin = col, K slots 8*grp .. 8*grp+7
     vec are_h, are_l, aim_h, aim_l;
     {
         uint16_t b[8];
@@ -188,9 +230,12 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
 
     const int wtc = wave & 7;
     const int u0 = (wave >> 3) * UH;
-    float acc[CTW][3];
+    // acc[c][j][m]: window 4*grp + j of t slot wtc + 8c, plane m, summed over this lane's bins
+    float acc[CTW][4][3];
 #pragma unroll
-    for (int c = 0; c < CTW; c++) acc[c][0] = acc[c][1] = acc[c][2] = 0.f;
+    for (int c = 0; c < CTW; c++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[c][j][0] = acc[c][j][1] = acc[c][j][2] = 0.f;
 
     const int half = grp >> 1;       // 0: real part samples, 1: imaginary part samples
     const int b0 = 8 * (grp & 1);    // first sample of this lane's K slots
@@ -198,87 +243,107 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
     __syncthreads();
 
     for (int kx = 0; kx < KH; kx++) {
-        // ---- pass A (fp32)
-        {
-            float cA[N], sA[N];
+        // ---- pass A (fp32 sums): one thread per (rt, il pair, cos|sin); the two rows'
+        // results are rounded once and stored as packed pairs for pass B
+        for (int e = tid; e < RTe * IQ2 * 2; e += kNTL) {
+            const int h = e & 1;
+            const int q = e >> 1;
+            const int rt = q / IQ2, il2 = q - rt * IQ2;
+            float cf[N];
 #pragma unroll
-            for (int a = 0; a < N; a++) {
-                cA[a] = p.passA[(kx * N + a) * 2];
-                sA[a] = p.passA[(kx * N + a) * 2 + 1];
-            }
-            for (int r = tid; r < RT * RI; r += kNTL) {
-                const float* row = Vt + r * RXp;
-                float o[8];
-                if constexpr (S > 0) {
-                    constexpr int RXc = 3 * S + N;
-                    float v[RXc];
+            for (int a = 0; a < N; a++) cf[a] = p.passA[(kx * N + a) * 2 + h];
+            float o[2][4];
 #pragma unroll
-                    for (int k = 0; k < RXc; k++) v[k] = row[k];
+            for (int r = 0; r < 2; r++) {
+                const int il = 2 * il2 + r;
 #pragma unroll
-                    for (int xc = 0; xc < 4; xc++) {
-                        float ar = 0.f, ai = 0.f;
+                for (int xc = 0; xc < 4; xc++) o[r][xc] = 0.f;
+                if (rt < RT && il < RI) {
+                    const float* row = Vt + (rt * RI + il) * RXp;
+                    if constexpr (S > 0) {
+                        constexpr int RXc = 3 * S + N;
+                        float v[RXc];
 #pragma unroll
-                        for (int a = 0; a < N; a++) {
-                            ar = fmaf(cA[a], v[xc * S + a], ar);
-                            ai = fmaf(sA[a], v[xc * S + a], ai);
+                        for (int k = 0; k < RXc; k++) v[k] = row[k];
+#pragma unroll
+                        for (int xc = 0; xc < 4; xc++) {
+                            float acc_a = 0.f;
+#pragma unroll
+                            for (int a = 0; a < N; a++) acc_a = fmaf(cf[a], v[xc * S + a], acc_a);
+                            o[r][xc] = acc_a;
                         }
-                        o[xc] = ar;
-                        o[4 + xc] = ai;
-                    }
-                } else {
+                    } else {
 #pragma unroll
-                    for (int xc = 0; xc < 4; xc++) {
-                        float ar = 0.f, ai = 0.f;
+                        for (int xc = 0; xc < 4; xc++) {
+                            float acc_a = 0.f;
 #pragma unroll
-                        for (int a = 0; a < N; a++) {
-                            const float v = row[xc * s + a];
-                            ar = fmaf(cA[a], v, ar);
-                            ai = fmaf(sA[a], v, ai);
+                            for (int a = 0; a < N; a++) acc_a = fmaf(cf[a], row[xc * s + a], acc_a);
+                            o[r][xc] = acc_a;
                         }
-                        o[xc] = ar;
-                        o[4 + xc] = ai;
                     }
                 }
-                *(float4*)&Ab[r * 4] = make_float4(o[0], o[1], o[2], o[3]);
-                *(float4*)&Ab[abStride + r * 4] = make_float4(o[4], o[5], o[6], o[7]);
+            }
+            uint4 wh, wl;
+            wh.x = L::pack_hi(o[0][0], o[1][0]);
+            wh.y = L::pack_hi(o[0][1], o[1][1]);
+            wh.z = L::pack_hi(o[0][2], o[1][2]);
+            wh.w = L::pack_hi(o[0][3], o[1][3]);
+            const size_t at = (size_t)(rt * IQ2 + il2) * 8;
+            *(uint4*)(Ab + (size_t)h * abPlane + at) = wh;
+            if constexpr (L::split) {
+                wl.x = L::pack_lo(o[0][0], o[1][0], wh.x);
+                wl.y = L::pack_lo(o[0][1], o[1][1], wh.y);
+                wl.z = L::pack_lo(o[0][2], o[1][2], wh.z);
+                wl.w = L::pack_lo(o[0][3], o[1][3], wh.w);
+                *(uint4*)(Ab + (size_t)(2 + h) * abPlane + at) = wl;
             }
         }
         __syncthreads();
         for (int e = tid; e < N * 16; e += kNTL) Wl[e] = p.wts[(size_t)kx * N * 16 + e];
-        // ---- pass B: complex DFT along il, one contraction per output tile
+        // ---- pass B: complex DFT along il for a pair of rows per wave; the outputs of the
+        // two rows are rounded and written as packed pairs along t
         {
-            const int ilc = col >> 2, xc = col & 3;
-            for (int rt = wave; rt < RT; rt += kNTL / 64) {
-                uint16_t bh[8], bl[8];
+            const int il0 = (col >> 2) * s + b0, xc = col & 3;
+            const uint32_t* abh = (const uint32_t*)(Ab + (size_t)half * abPlane) + xc;
+            const uint32_t* abl = (const uint32_t*)(Ab + (size_t)(2 + half) * abPlane) + xc;
+            for (int pi = wave; pi < RTe / 2; pi += NW) {
+                f4 dre[2], dim[2];
 #pragma unroll
-                for (int i = 0; i < 8; i++) {
-                    const int b = b0 + i;
-                    const float x = b < N ? Ab[half * abStride + (rt * RI + ilc * s + b) * 4 + xc] : 0.f;
-                    bh[i] = L::hi(x);
-                    bl[i] = L::lo(x, bh[i]);
+                for (int r = 0; r < 2; r++) {
+                    const int rowoff = (2 * pi + r) * IQ2 * 4;
+                    uint32_t wh[4], wl[4];
+                    load8_ab<S>(abh + rowoff, il0, wh);
+                    if constexpr (L::split) load8_ab<S>(abl + rowoff, il0, wl);
+                    const vec vh = vec_from_words<PREC>(wh);
+                    const vec vl = L::split ? vec_from_words<PREC>(wl) : vh;
+                    dre[r] = contract<PREC>(are_h, are_l, vh, vl, f4{0.f, 0.f, 0.f, 0.f});
+                    dim[r] = contract<PREC>(aim_h, aim_l, vh, vl, f4{0.f, 0.f, 0.f, 0.f});
                 }
-                const vec vh = L::from_bits(bh), vl = L::from_bits(bl);
-                f4 dre = {0.f, 0.f, 0.f, 0.f}, dim = {0.f, 0.f, 0.f, 0.f};
-                dre = contract<PREC>(are_h, are_l, vh, vl, dre);
-                dim = contract<PREC>(aim_h, aim_l, vh, vl, dim);
 #pragma unroll
                 for (int j = 0; j < 4; j++) {
                     const int u = 4 * grp + j;
                     if (u < N) {
-                        const uint16_t rh = L::hi(dre[j]), ih = L::hi(dim[j]);
-                        Gh[(u * 16 + col) * gRow + rt] = rh;
-                        Gh[gStrideRi + (u * 16 + col) * gRow + rt] = ih;
+                        uint32_t* gre = (uint32_t*)(Gh + (u * 16 + col) * gRow) + pi;
+                        uint32_t* gim = (uint32_t*)(Gh + gStrideRi + (u * 16 + col) * gRow) + pi;
+                        const uint32_t rh = L::pack_hi(dre[0][j], dre[1][j]);
+                        const uint32_t ih = L::pack_hi(dim[0][j], dim[1][j]);
+                        *gre = rh;
+                        *gim = ih;
                         if constexpr (L::split) {
-                            Gl[(u * 16 + col) * gRow + rt] = L::lo(dre[j], rh);
-                            Gl[gStrideRi + (u * 16 + col) * gRow + rt] = L::lo(dim[j], ih);
+                            uint32_t* lre = (uint32_t*)(Gl + (u * 16 + col) * gRow) + pi;
+                            uint32_t* lim = (uint32_t*)(Gl + gStrideRi + (u * 16 + col) * gRow) + pi;
+                            *lre = L::pack_lo(dre[0][j], dre[1][j], rh);
+                            *lim = L::pack_lo(dim[0][j], dim[1][j], ih);
                         }
                     }
                 }
             }
         }
         __syncthreads();
-        // ---- pass C along t and the projection epilogue; slot u+1 is contracted before
-        // the epilogue of slot u so the matrix cores and the VALU overlap
+        // ---- pass C along t and the projection epilogue.  The product is taken transposed
+        // (windows x bins), so a lane holds one bin kt = col of four windows and needs one
+        // weight triple per ki.  Slot u+1 is contracted before the epilogue of slot u so the
+        // matrix cores and the VALU overlap.
 #pragma unroll
         for (int c = 0; c < CTW; c++) {
             const int tc = wtc + 8 * c;
@@ -294,24 +359,24 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
                     if constexpr (L::split) load8_u16<ODD>(glb + u * 16 * gRow, ts, wl);
                     const vec vh = vec_from_words<PREC>(wh);
                     const vec vl = L::split ? vec_from_words<PREC>(wl) : vh;
-                    dre = contract<PREC>(are_h, are_l, vh, vl, f4{0.f, 0.f, 0.f, 0.f});
-                    dim = contract<PREC>(aim_h, aim_l, vh, vl, f4{0.f, 0.f, 0.f, 0.f});
+                    dre = contract<PREC>(vh, vl, are_h, are_l, f4{0.f, 0.f, 0.f, 0.f});
+                    dim = contract<PREC>(vh, vl, aim_h, aim_l, f4{0.f, 0.f, 0.f, 0.f});
                 };
                 f4 dre, dim;
                 contract_c(u0, dre, dim);
 #pragma unroll
                 for (int uu = 0; uu < UH; uu++) {
                     const int u = u0 + uu;
-                    const float4* wrow = Wl + u * 16 + 4 * grp;
-                    const float4 w0 = wrow[0], w1 = wrow[1], w2 = wrow[2], w3 = wrow[3];
+                    const float4 w = Wl[u * 16 + col];
                     f4 nre, nim;
                     if (uu + 1 < UH) contract_c(u + 1, nre, nim);
-                    float m[4];
 #pragma unroll
-                    for (int j = 0; j < 4; j++) m[j] = __builtin_amdgcn_sqrtf(fmaf(dre[j], dre[j], dim[j] * dim[j]));
-                    acc[c][0] = fmaf(w0.x, m[0], fmaf(w1.x, m[1], fmaf(w2.x, m[2], fmaf(w3.x, m[3], acc[c][0]))));
-                    acc[c][1] = fmaf(w0.y, m[0], fmaf(w1.y, m[1], fmaf(w2.y, m[2], fmaf(w3.y, m[3], acc[c][1]))));
-                    acc[c][2] = fmaf(w0.z, m[0], fmaf(w1.z, m[1], fmaf(w2.z, m[2], fmaf(w3.z, m[3], acc[c][2]))));
+                    for (int j = 0; j < 4; j++) {
+                        const float m = __builtin_amdgcn_sqrtf(fmaf(dre[j], dre[j], dim[j] * dim[j]));
+                        acc[c][j][0] = fmaf(w.x, m, acc[c][j][0]);
+                        acc[c][j][1] = fmaf(w.y, m, acc[c][j][1]);
+                        acc[c][j][2] = fmaf(w.z, m, acc[c][j][2]);
+                    }
                     if (uu + 1 < UH) {
                         dre = nre;
                         dim = nim;
@@ -324,36 +389,50 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
         }
     }
 
-    // reduce the lane groups, then the two halves of the ki slots through LDS
+    // reduce over the 16 bins of a lane group, then over the two halves of the ki slots
+    // through LDS
     __syncthreads();
     float* red = (float*)Gh;  // [CTW][8][16][3]
-    float v[CTW][3];
 #pragma unroll
     for (int c = 0; c < CTW; c++)
 #pragma unroll
-        for (int m = 0; m < 3; m++) {
-            float x = acc[c][m];
-            x += __shfl_xor(x, 16);
-            x += __shfl_xor(x, 32);
-            v[c][m] = x;
-        }
-    if (NW > 8 && wave >= 8 && grp == 0) {
+        for (int j = 0; j < 4; j++)
+#pragma unroll
+            for (int m = 0; m < 3; m++) {
+                float x = acc[c][j][m];
+                x += __shfl_xor(x, 1);
+                x += __shfl_xor(x, 2);
+                x += __shfl_xor(x, 4);
+                x += __shfl_xor(x, 8);
+                acc[c][j][m] = x;
+            }
+    if (NW > 8 && wave >= 8 && col == 0) {
 #pragma unroll
         for (int c = 0; c < CTW; c++)
 #pragma unroll
-            for (int m = 0; m < 3; m++) red[((c * 8 + wtc) * 16 + col) * 3 + m] = v[c][m];
+            for (int j = 0; j < 4; j++)
+#pragma unroll
+                for (int m = 0; m < 3; m++) red[((c * 8 + wtc) * 16 + 4 * grp + j) * 3 + m] = acc[c][j][m];
     }
     __syncthreads();
     const int64_t G = p.Tg * p.ILg * p.XLg;
-    if (wave < 8 && grp == 0) {
+    if (wave < 8 && col == 0) {
 #pragma unroll
         for (int c = 0; c < CTW; c++) {
             const int tc = wtc + 8 * c;
-            const int64_t gt = tt * CT + tc, gi = ti * 4 + (col >> 2), gx = tx * 4 + (col & 3);
-            if (tc < CT && gt < p.Tg && gi < p.ILg && gx < p.XLg) {
-                const int64_t j = (gt * p.ILg + gi) * p.XLg + gx;
+            const int64_t gt = tt * CT + tc, gi = ti * 4 + grp;
+            if (tc < CT && gt < p.Tg && gi < p.ILg) {
 #pragma unroll
-                for (int m = 0; m < 3; m++) p.E[m * G + j] = v[c][m] + (NW > 8 ? red[((c * 8 + wtc) * 16 + col) * 3 + m] : 0.f);
+                for (int j = 0; j < 4; j++) {
+                    const int64_t gx = tx * 4 + j;
+                    if (gx < p.XLg) {
+                        const int64_t at = (gt * p.ILg + gi) * p.XLg + gx;
+#pragma unroll
+                        for (int m = 0; m < 3; m++)
+                            p.E[m * G + at] =
+                                acc[c][j][m] + (NW > 8 ? red[((c * 8 + wtc) * 16 + 4 * grp + j) * 3 + m] : 0.f);
+                    }
+                }
             }
         }
     }
@@ -398,9 +477,12 @@ static size_t lowp_lds_bytes(int n, int s, int CT, bool split, LowpParams* p) {
     p->RI = 3 * s + n;
     p->RX = 3 * s + n;
     p->RXp = p->RX | 1;
-    const size_t f32 = (((size_t)p->RT * p->RI * p->RXp + 3) & ~(size_t)3) + 2 * (size_t)p->RT * p->RI * 4;
-    const size_t u16 = std::max<size_t>((size_t)2 * n * 16 * p->RTp * (split ? 2 : 1), 8 * 16 * 3 * 2 * 2);
-    return sizeof(float) * f32 + 2 * u16 + sizeof(float) * 4 * 16 * n;
+    p->IQ2 = ab_iq2(s);
+    const size_t RTe = (size_t)((p->RT + 1) & ~1);
+    const size_t f32 = ((size_t)p->RT * p->RI * p->RXp + 3) & ~(size_t)3;
+    const size_t ab = (split ? 4 : 2) * RTe * p->IQ2 * 8;
+    const size_t g = std::max<size_t>((size_t)2 * n * 16 * p->RTp * (split ? 2 : 1), 8 * 16 * 3 * 2 * 2);
+    return sizeof(float) * f32 + 2 * (ab + g) + sizeof(float) * 4 * 16 * n;
 }
 
 static constexpr size_t kLdsMaxL = 160 * 1024;

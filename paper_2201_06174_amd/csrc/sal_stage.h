@@ -17,26 +17,41 @@ __device__ __forceinline__ int64_t reflect_clamp_s(int64_t p, int64_t N) {
 }
 
 // Copy the region [RT][RI][RX] starting at voxel (t0, i0, x0) into Vt with row pitch RXp.
-// Waves take (t, il) rows, lanes the xl samples of a row (two rows per wave when a row
-// fits in 32 lanes), so each lane's xl index and its reflection are fixed.
+// A lane owns one (il, xl) column of the region, so its reflected in-plane offset is
+// computed once; the lanes split into as many groups as there are whole columns sets in
+// the workgroup, and group g walks the t planes g, g + G, ...  The loads of up to
+// kStageBatch planes are issued before any of them is stored; every address is reflected
+// and clamped into the volume, so the loads are unconditional and only the stores are
+// masked.
+constexpr int kStageBatch = 16;
+
 template <int NT>
 __device__ __forceinline__ void stage_tile(const float* __restrict__ V, int64_t T, int64_t IL, int64_t XL,
                                            int64_t t0, int64_t i0, int64_t x0, int RT, int RI, int RX, int RXp,
                                            float* __restrict__ Vt) {
-    constexpr int NWAVES = NT / 64;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const bool two = RX <= 32;
-    const int sub = two ? (lane >> 5) : 0;
-    const int rx = two ? (lane & 31) : lane;
-    const int step = two ? 2 * NWAVES : NWAVES;
-    const int nrows = RT * RI;
-    const bool act = rx < RX;
-    const int64_t gx = reflect_clamp_s(x0 + rx, XL);
-    for (int r = (two ? 2 * wave : wave) + sub; r < nrows + sub; r += step) {
-        if (r < nrows && act) {
-            const int rt = r / RI, ri = r - rt * RI;
-            const int64_t gt = reflect_clamp_s(t0 + rt, T), gi = reflect_clamp_s(i0 + ri, IL);
-            Vt[r * RXp + rx] = V[(gt * IL + gi) * XL + gx];
+    const int PQ = RI * RX;
+    const int G = PQ >= NT ? 1 : NT / PQ;
+    const int g = (int)threadIdx.x / PQ;
+    if (g >= G) return;
+    const int64_t PS = IL * XL;
+    const int plane = RI * RXp;
+    for (int q = (int)threadIdx.x - g * PQ; q < PQ; q += NT) {
+        const int ri = q / RX, rx = q - ri * RX;
+        const int64_t off = reflect_clamp_s(i0 + ri, IL) * XL + reflect_clamp_s(x0 + rx, XL);
+        const float* src = V + off;
+        float* dst = Vt + ri * RXp + rx;
+        for (int rt0 = g; rt0 < RT; rt0 += G * kStageBatch) {
+            float v[kStageBatch];
+#pragma unroll
+            for (int u = 0; u < kStageBatch; u++) {
+                const int rt = min(rt0 + u * G, RT - 1);
+                v[u] = src[reflect_clamp_s(t0 + rt, T) * PS];
+            }
+#pragma unroll
+            for (int u = 0; u < kStageBatch; u++) {
+                const int rt = rt0 + u * G;
+                if (rt < RT) dst[rt * plane] = v[u];
+            }
         }
     }
 }
