@@ -171,6 +171,7 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
     constexpr int KH = N / 2 + 1;
     constexpr int NW = kNTL / 64;
     constexpr int UH = N * 8 / NW;
+    static_assert(NW == 16, "the ki slots are split between two halves of 8 waves");
     constexpr int NPL = L::split ? 4 : 2;  // Ab planes: (hi, lo) x (real, imaginary)
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -229,7 +230,6 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
     }
 
     const int wtc = wave & 7;
-    const int u0 = (wave >> 3) * UH;
     // acc[c][j][m]: window 4*grp + j of t slot wtc + 8c, plane m, summed over this lane's bins
     float acc[CTW][4][3];
 #pragma unroll
@@ -299,7 +299,16 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
             }
         }
         __syncthreads();
-        for (int e = tid; e < N * 16; e += kNTL) Wl[e] = p.wts[(size_t)kx * N * 16 + e];
+        // bin weights of this kx.  The planes kx = 0 and kx = n/2 are their own Hermitian
+        // mirrors (|F(-k)| = |F(k)|): only the ki slots [0, n/2] are visited there, and a slot
+        // whose mirror is skipped counts twice.
+        const bool mirror = kx == 0 || 2 * kx == N;
+        for (int e = tid; e < N * 16; e += kNTL) {
+            const int u = e >> 4;
+            const float f = mirror && u >= 1 && u < N / 2 ? 2.f : 1.f;
+            const float4 w = p.wts[(size_t)kx * N * 16 + e];
+            Wl[e] = make_float4(f * w.x, f * w.y, f * w.z, f * w.w);
+        }
         // ---- pass B: complex DFT along il for a pair of rows per wave; the outputs of the
         // two rows are rounded and written as packed pairs along t
         {
@@ -343,7 +352,9 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
         // ---- pass C along t and the projection epilogue.  The product is taken transposed
         // (windows x bins), so a lane holds one bin kt = col of four windows and needs one
         // weight triple per ki.  Slot u+1 is contracted before the epilogue of slot u so the
-        // matrix cores and the VALU overlap.
+        // matrix cores and the VALU overlap.  The two wave halves split the ki slots to visit,
+        // [0, n) or [0, n/2] on a mirror plane.
+        const int ua = (wave >> 3) ? (mirror ? (N / 2 + 2) / 2 : UH) : 0;
 #pragma unroll
         for (int c = 0; c < CTW; c++) {
             const int tc = wtc + 8 * c;
@@ -351,8 +362,9 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
             const int ts = tc * s + b0;
             const uint16_t* ghb = Gh + half * gStrideRi + col * gRow;
             const uint16_t* glb = Gl + half * gStrideRi + col * gRow;
-            auto run = [&](auto odd) {
+            auto run = [&](auto odd, auto count) {
                 constexpr bool ODD = decltype(odd)::value;
+                constexpr int CNT = decltype(count)::value;
                 auto contract_c = [&](int u, f4& dre, f4& dim) {
                     uint32_t wh[4], wl[4];
                     load8_u16<ODD>(ghb + u * 16 * gRow, ts, wh);
@@ -363,13 +375,13 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
                     dim = contract<PREC>(vh, vl, aim_h, aim_l, f4{0.f, 0.f, 0.f, 0.f});
                 };
                 f4 dre, dim;
-                contract_c(u0, dre, dim);
+                contract_c(ua, dre, dim);
 #pragma unroll
-                for (int uu = 0; uu < UH; uu++) {
-                    const int u = u0 + uu;
+                for (int uu = 0; uu < CNT; uu++) {
+                    const int u = ua + uu;
                     const float4 w = Wl[u * 16 + col];
                     f4 nre, nim;
-                    if (uu + 1 < UH) contract_c(u + 1, nre, nim);
+                    if (uu + 1 < CNT) contract_c(u + 1, nre, nim);
 #pragma unroll
                     for (int j = 0; j < 4; j++) {
                         const float m = __builtin_amdgcn_sqrtf(fmaf(dre[j], dre[j], dim[j] * dim[j]));
@@ -377,15 +389,21 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
                         acc[c][j][1] = fmaf(w.y, m, acc[c][j][1]);
                         acc[c][j][2] = fmaf(w.z, m, acc[c][j][2]);
                     }
-                    if (uu + 1 < UH) {
+                    if (uu + 1 < CNT) {
                         dre = nre;
                         dim = nim;
                     }
                 }
             };
+            // slot counts are compile-time per case so each loop stays fully unrolled
+            auto run_slots = [&](auto odd) {
+                if (!mirror) run(odd, std::integral_constant<int, UH>{});
+                else if (wave >> 3) run(odd, std::integral_constant<int, (N / 2 + 1) / 2>{});
+                else run(odd, std::integral_constant<int, (N / 2 + 2) / 2>{});
+            };
             // the window start's parity is the same for the whole wave
-            if ((S > 0 && (S & 1) == 0) || (ts & 1) == 0) run(std::false_type{});
-            else run(std::true_type{});
+            if ((S > 0 && (S & 1) == 0) || (ts & 1) == 0) run_slots(std::false_type{});
+            else run_slots(std::true_type{});
         }
     }
 

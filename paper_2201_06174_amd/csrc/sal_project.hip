@@ -20,6 +20,7 @@
 // leaves the chip.
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "sal_aux.h"
@@ -62,6 +63,7 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
     constexpr int NK = N / 4;
     constexpr int NW = kNT / 64;           // waves per workgroup (8 or 16)
     constexpr int UH = N * 8 / NW;        // ki slots per wave
+    static_assert(NW == 16, "the ki slots are split between two halves of 8 waves");
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -93,7 +95,6 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
 
     // pass C work of this wave: t-centres wave%8 (+8c), ki slots of one half
     const int wtc = wave & 7;
-    const int u0 = (wave >> 3) * UH;
     float acc[CTW][3];
 #pragma unroll
     for (int c = 0; c < CTW; c++) acc[c][0] = acc[c][1] = acc[c][2] = 0.f;
@@ -147,8 +148,16 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
             }
         }
         __syncthreads();
-        // bin weights of this kx (their previous readers all passed the barrier above)
-        for (int e = tid; e < N * 16; e += kNT) Wl[e] = p.wts[(size_t)kx * N * 16 + e];
+        // bin weights of this kx (their previous readers all passed the barrier above).  The
+        // planes kx = 0 and kx = n/2 are their own Hermitian mirrors (|F(-k)| = |F(k)|): only
+        // the ki slots [0, n/2] are visited there, and a slot whose mirror is skipped counts twice.
+        const bool mirror = kx == 0 || 2 * kx == N;
+        for (int e = tid; e < N * 16; e += kNT) {
+            const int u = e >> 4;
+            const float f = mirror && u >= 1 && u < N / 2 ? 2.f : 1.f;
+            const float4 w = p.wts[(size_t)kx * N * 16 + e];
+            Wl[e] = make_float4(f * w.x, f * w.y, f * w.z, f * w.w);
+        }
         // ---- pass B: complex DFT along il on the matrix cores, combined into signed ki slots
         {
             const int ilc = col >> 2, xc = col & 3;
@@ -192,7 +201,9 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
         __syncthreads();
         // ---- pass C along t on the matrix cores, then |F| * weights into the window sums.
         // The contraction of slot u+1 is issued before the epilogue of slot u, so the
-        // matrix cores and the VALU work on different slots at the same time.
+        // matrix cores and the VALU work on different slots at the same time.  The two
+        // wave halves split the ki slots to visit, [0, n) or [0, n/2] on a mirror plane.
+        const int ua = (wave >> 3) ? (mirror ? (N / 2 + 2) / 2 : UH) : 0;
 #pragma unroll
         for (int c = 0; c < CTW; c++) {
             const int tc = wtc + 8 * c;
@@ -214,33 +225,41 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
                     di = mfma4(amat[ks], bi[ks], di);
                 }
             };
-            f4 dr, di;
-            contract(u0, dr, di);
+            auto run = [&](auto count) {
+                constexpr int CNT = decltype(count)::value;
+                f4 dr, di;
+                contract(ua, dr, di);
 #pragma unroll
-            for (int uu = 0; uu < UH; uu++) {
-                const int u = u0 + uu;
-                const float4* wrow = Wl + u * 16 + 4 * grp;
-                const float4 w0 = wrow[0], w1 = wrow[1], w2 = wrow[2], w3 = wrow[3];
-                f4 nr, ni;
-                if (uu + 1 < UH) contract(u + 1, nr, ni);
+                for (int uu = 0; uu < CNT; uu++) {
+                    const int u = ua + uu;
+                    const float4* wrow = Wl + u * 16 + 4 * grp;
+                    const float4 w0 = wrow[0], w1 = wrow[1], w2 = wrow[2], w3 = wrow[3];
+                    f4 nr, ni;
+                    const bool more = uu + 1 < CNT;
+                    if (more) contract(u + 1, nr, ni);
 #pragma unroll
-                for (int pr = 0; pr < 2; pr++) {
-                    const bool sp = (grp == 0) && (pr == 0);
-                    const float Ca = dr[2 * pr], Sb = dr[2 * pr + 1], Cai = di[2 * pr], Sbi = di[2 * pr + 1];
-                    const float re1 = sp ? Ca : Ca + Sbi, im1 = sp ? Cai : Cai - Sb;
-                    const float re2 = sp ? Sb : Ca - Sbi, im2 = sp ? Sbi : Cai + Sb;
-                    const float m1 = __builtin_amdgcn_sqrtf(fmaf(re1, re1, im1 * im1));
-                    const float m2 = __builtin_amdgcn_sqrtf(fmaf(re2, re2, im2 * im2));
-                    const float4 wa = pr ? w2 : w0, wb = pr ? w3 : w1;
-                    acc[c][0] = fmaf(wa.x, m1, fmaf(wb.x, m2, acc[c][0]));
-                    acc[c][1] = fmaf(wa.y, m1, fmaf(wb.y, m2, acc[c][1]));
-                    acc[c][2] = fmaf(wa.z, m1, fmaf(wb.z, m2, acc[c][2]));
+                    for (int pr = 0; pr < 2; pr++) {
+                        const bool sp = (grp == 0) && (pr == 0);
+                        const float Ca = dr[2 * pr], Sb = dr[2 * pr + 1], Cai = di[2 * pr], Sbi = di[2 * pr + 1];
+                        const float re1 = sp ? Ca : Ca + Sbi, im1 = sp ? Cai : Cai - Sb;
+                        const float re2 = sp ? Sb : Ca - Sbi, im2 = sp ? Sbi : Cai + Sb;
+                        const float m1 = __builtin_amdgcn_sqrtf(fmaf(re1, re1, im1 * im1));
+                        const float m2 = __builtin_amdgcn_sqrtf(fmaf(re2, re2, im2 * im2));
+                        const float4 wa = pr ? w2 : w0, wb = pr ? w3 : w1;
+                        acc[c][0] = fmaf(wa.x, m1, fmaf(wb.x, m2, acc[c][0]));
+                        acc[c][1] = fmaf(wa.y, m1, fmaf(wb.y, m2, acc[c][1]));
+                        acc[c][2] = fmaf(wa.z, m1, fmaf(wb.z, m2, acc[c][2]));
+                    }
+                    if (more) {
+                        dr = nr;
+                        di = ni;
+                    }
                 }
-                if (uu + 1 < UH) {
-                    dr = nr;
-                    di = ni;
-                }
-            }
+            };
+            // slot counts are compile-time per case so each loop stays fully unrolled
+            if (!mirror) run(std::integral_constant<int, UH>{});
+            else if (wave >> 3) run(std::integral_constant<int, (N / 2 + 1) / 2>{});
+            else run(std::integral_constant<int, (N / 2 + 2) / 2>{});
         }
         // the next pass A writes only Ab, whose readers (pass B) all passed the barrier above
     }
