@@ -53,9 +53,9 @@ sal_status project_lowp_params(int n, int s, int precision, int CT, const float*
                                int64_t XL, const Tables* tb, float* E, void* out, int64_t* ntiles, size_t* lds);
 sal_status project_fp32_batch(int n, int s, const void* items, const int64_t* prefix, int nitems, int64_t total,
                               size_t lds, int grid, hipStream_t stream);
-sal_status project_lowp_batch(int n, int s, int precision, const void* items, const int64_t* prefix, int nitems,
-                              int64_t total, size_t lds, int grid, hipStream_t stream);
+sal_status project_lowp_batch(int n, int s, int precision, int CT, const void* items, const int64_t* prefix,
+                              int nitems, int64_t total, size_t lds, int grid, hipStream_t stream);
 sal_status project_fp32_batch_occupancy(int n, int s, size_t lds, int* per_cu);
-sal_status project_lowp_batch_occupancy(int n, int s, int precision, size_t lds, int* per_cu);
+sal_status project_lowp_batch_occupancy(int n, int s, int precision, int CT, size_t lds, int* per_cu);
 
 }  // namespace sal

@@ -160,11 +160,32 @@ __device__ __forceinline__ void load8_ab(const uint32_t* rowx, int il0, uint32_t
     }
 }
 
+// Row pitch of the pass-B output rows in 16-bit samples for a tile of CT t-centres: even
+// (dword-aligned rows), room for the furthest realigned read, and an odd-times-4-plus-3
+// dword pitch so the 16 columns of a wave's reads and writes fall into distinct LDS banks.
+__host__ __device__ constexpr int lowp_rtp(int CT, int s) {
+    int R = ((CT - 1) * s + 18) / 2;
+    while ((R & 3) != 3) R++;
+    return 2 * R;
+}
+
+// Sum over the 16 lanes of a DPP row (the bins kt of one lane group): rotations by 8, 4, 2
+// and 1 within the row leave the total in every lane, without a trip through LDS.
+__device__ __forceinline__ float row_sum16(float x) {
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xf, 0xf, false));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x124, 0xf, 0xf, false));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x122, 0xf, 0xf, false));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x121, 0xf, 0xf, false));
+    return x;
+}
+
 // dwords per Ab row plane: covers the furthest 5-dword read of pass B, starting at
 // il = 3s + 8 for the last window column and the upper K half
 __host__ __device__ constexpr int ab_iq2(int s) { return (3 * s + 8) / 2 + 5; }
 
-template <int N, int S, int PREC, int CTW>
+// FIX: the tile has its full depth 8*CTW and a compile-time stride, so every LDS extent
+// and pitch is a compile-time constant (addresses fold into instruction offsets).
+template <int N, int S, int PREC, int CTW, bool FIX>
 __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int64_t tile, float* lds) {
     using L = Lp<PREC>;
     typedef typename L::vec vec;
@@ -184,7 +205,12 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
     const int64_t tt = tile / (p.tilesX * p.tilesI);
 
     const int s = S > 0 ? S : p.s;
-    const int RT = p.RT, RTe = (p.RT + 1) & ~1, RTp = p.RTp, CT = p.CT;
+    static_assert(!FIX || S > 0, "a fixed tile needs a compile-time stride");
+    constexpr int CTF = 8 * CTW;
+    const int CT = FIX ? CTF : p.CT;
+    const int RT = FIX ? (CTF - 1) * S + N : p.RT;
+    const int RTe = (RT + 1) & ~1;
+    const int RTp = FIX ? lowp_rtp(CTF, S > 0 ? S : 1) : p.RTp;
     const int RI = S > 0 ? 3 * S + N : p.RI, RX = RI, RXp = S > 0 ? ((3 * S + N) | 1) : p.RXp;
     const int IQ2 = S > 0 ? ab_iq2(S) : p.IQ2;
     float* Vt = lds;                                                     // [RT][RI][RXp] fp32
@@ -417,12 +443,7 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
         for (int j = 0; j < 4; j++)
 #pragma unroll
             for (int m = 0; m < 3; m++) {
-                float x = acc[c][j][m];
-                x += __shfl_xor(x, 1);
-                x += __shfl_xor(x, 2);
-                x += __shfl_xor(x, 4);
-                x += __shfl_xor(x, 8);
-                acc[c][j][m] = x;
+                acc[c][j][m] = row_sum16(acc[c][j][m]);
             }
     if (NW > 8 && wave >= 8 && col == 0) {
 #pragma unroll
@@ -456,16 +477,16 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
     }
 }
 
-template <int N, int S, int PREC, int CTW>
+template <int N, int S, int PREC, int CTW, bool FIX>
 __global__ __launch_bounds__(kNTL) void k_project_lowp(LowpParams p) {
     extern __shared__ float lds[];
     const int64_t per = (p.ntiles + 7) / 8;
     const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (tile >= p.ntiles) return;
-    project_tile_lowp<N, S, PREC, CTW>(p, tile, lds);
+    project_tile_lowp<N, S, PREC, CTW, FIX>(p, tile, lds);
 }
 
-template <int N, int S, int PREC, int CTW>
+template <int N, int S, int PREC, int CTW, bool FIX>
 __global__ __launch_bounds__(kNTL) void k_project_lowp_batch(const LowpParams* __restrict__ items,
                                                              const int64_t* __restrict__ prefix, int nitems,
                                                              int64_t total) {
@@ -480,18 +501,13 @@ __global__ __launch_bounds__(kNTL) void k_project_lowp_batch(const LowpParams* _
             if (prefix[m] <= g) a = m; else b = m - 1;
         }
         __syncthreads();
-        project_tile_lowp<N, S, PREC, CTW>(items[a], g - prefix[a], lds);
+        project_tile_lowp<N, S, PREC, CTW, FIX>(items[a], g - prefix[a], lds);
     }
 }
 
 static size_t lowp_lds_bytes(int n, int s, int CT, bool split, LowpParams* p) {
     p->RT = (CT - 1) * s + n;
-    // row pitch in 16-bit samples: even (dword-aligned rows), one sample of slack for realigned
-    // odd starts, and an odd-times-4-plus-3 dword pitch so the 16 columns of a wave's reads
-    // and writes fall into distinct LDS banks
-    int R = ((CT - 1) * s + 18) / 2;
-    while ((R & 3) != 3) R++;
-    p->RTp = 2 * R;
+    p->RTp = lowp_rtp(CT, s);
     p->RI = 3 * s + n;
     p->RX = 3 * s + n;
     p->RXp = p->RX | 1;
@@ -557,36 +573,61 @@ static sal_status set_lds_attr_l(K kernel, const char* what) {
                                          (int)kLdsMaxL), what);
 }
 
-template <int N, int S, int PREC, int CTW>
-static sal_status launch_lowp(const LowpParams& p, size_t lds, hipStream_t stream) {
+template <int N, int S, int PREC, int CTW, bool FIX>
+static sal_status launch_lowp_k(const LowpParams& p, size_t lds, hipStream_t stream) {
     static bool attr = false;
     if (!attr) {
-        sal_status st = set_lds_attr_l(k_project_lowp<N, S, PREC, CTW>, "hipFuncSetAttribute(project lowp)");
+        sal_status st = set_lds_attr_l(k_project_lowp<N, S, PREC, CTW, FIX>, "hipFuncSetAttribute(project lowp)");
         if (st) return st;
         attr = true;
     }
     const int64_t grid = 8 * ((p.ntiles + 7) / 8);
     if (grid > INT32_MAX) return fail(SAL_ERR_SHAPE, "volume too large for one launch");
-    hipLaunchKernelGGL((k_project_lowp<N, S, PREC, CTW>), dim3((unsigned)grid), dim3(kNTL), lds, stream, p);
+    hipLaunchKernelGGL((k_project_lowp<N, S, PREC, CTW, FIX>), dim3((unsigned)grid), dim3(kNTL), lds, stream, p);
     return check_hip(hipGetLastError(), "launch k_project_lowp");
 }
 
+// the full-depth tile of a compile-time stride takes the kernel with fixed extents
 template <int N, int S, int PREC, int CTW>
-static sal_status launch_lowp_batch(const void* items, const int64_t* prefix, int nitems, int64_t total, size_t lds,
-                                   int grid, hipStream_t stream) {
+static constexpr bool fixed_tile(int CT) { return S > 0 && CT == 8 * CTW; }
+
+template <int N, int S, int PREC, int CTW>
+static sal_status launch_lowp(const LowpParams& p, size_t lds, hipStream_t stream) {
+    if constexpr (S > 0)
+        if (fixed_tile<N, S, PREC, CTW>(p.CT)) return launch_lowp_k<N, S, PREC, CTW, true>(p, lds, stream);
+    return launch_lowp_k<N, S, PREC, CTW, false>(p, lds, stream);
+}
+
+template <int N, int S, int PREC, int CTW>
+static sal_status launch_lowp_batch(int CT, const void* items, const int64_t* prefix, int nitems, int64_t total,
+                                   size_t lds, int grid, hipStream_t stream) {
     // the LDS attribute was set by project_lowp_batch_occupancy(), outside any stream capture
-    hipLaunchKernelGGL((k_project_lowp_batch<N, S, PREC, CTW>), dim3((unsigned)grid), dim3(kNTL), lds, stream,
+    if constexpr (S > 0)
+        if (fixed_tile<N, S, PREC, CTW>(CT)) {
+            hipLaunchKernelGGL((k_project_lowp_batch<N, S, PREC, CTW, true>), dim3((unsigned)grid), dim3(kNTL), lds,
+                               stream, (const LowpParams*)items, prefix, nitems, total);
+            return check_hip(hipGetLastError(), "launch k_project_lowp_batch");
+        }
+    hipLaunchKernelGGL((k_project_lowp_batch<N, S, PREC, CTW, false>), dim3((unsigned)grid), dim3(kNTL), lds, stream,
                        (const LowpParams*)items, prefix, nitems, total);
     return check_hip(hipGetLastError(), "launch k_project_lowp_batch");
 }
 
-template <int N, int S, int PREC, int CTW>
-static sal_status lowp_occupancy(size_t lds, int* per_cu) {
-    sal_status st = set_lds_attr_l(k_project_lowp_batch<N, S, PREC, CTW>, "hipFuncSetAttribute(project lowp batch)");
+template <int N, int S, int PREC, int CTW, bool FIX>
+static sal_status lowp_occupancy_k(size_t lds, int* per_cu) {
+    sal_status st =
+        set_lds_attr_l(k_project_lowp_batch<N, S, PREC, CTW, FIX>, "hipFuncSetAttribute(project lowp batch)");
     if (st) return st;
     return check_hip(
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_project_lowp_batch<N, S, PREC, CTW>, kNTL, lds),
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_project_lowp_batch<N, S, PREC, CTW, FIX>, kNTL, lds),
         "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+}
+
+template <int N, int S, int PREC, int CTW>
+static sal_status lowp_occupancy(int CT, size_t lds, int* per_cu) {
+    if constexpr (S > 0)
+        if (fixed_tile<N, S, PREC, CTW>(CT)) return lowp_occupancy_k<N, S, PREC, CTW, true>(lds, per_cu);
+    return lowp_occupancy_k<N, S, PREC, CTW, false>(lds, per_cu);
 }
 
 #define SAL_LP_S(NN, CC, PP)                       \
@@ -619,15 +660,15 @@ sal_status launch_project_lowp(const float* V, int64_t T, int64_t IL, int64_t XL
 #undef CALL
 }
 
-sal_status project_lowp_batch(int n, int s, int precision, const void* items, const int64_t* prefix, int nitems,
-                              int64_t total, size_t lds, int grid, hipStream_t stream) {
-#define CALL(NN, SS, PP, CC) launch_lowp_batch<NN, SS, PP, CC>(items, prefix, nitems, total, lds, grid, stream)
+sal_status project_lowp_batch(int n, int s, int precision, int CT, const void* items, const int64_t* prefix,
+                              int nitems, int64_t total, size_t lds, int grid, hipStream_t stream) {
+#define CALL(NN, SS, PP, CC) launch_lowp_batch<NN, SS, PP, CC>(CT, items, prefix, nitems, total, lds, grid, stream)
     SAL_LP_DISPATCH
 #undef CALL
 }
 
-sal_status project_lowp_batch_occupancy(int n, int s, int precision, size_t lds, int* per_cu) {
-#define CALL(NN, SS, PP, CC) lowp_occupancy<NN, SS, PP, CC>(lds, per_cu)
+sal_status project_lowp_batch_occupancy(int n, int s, int precision, int CT, size_t lds, int* per_cu) {
+#define CALL(NN, SS, PP, CC) lowp_occupancy<NN, SS, PP, CC>(CT, lds, per_cu)
     SAL_LP_DISPATCH
 #undef CALL
 }

@@ -99,8 +99,8 @@ sal_status build_class_params(sal_plan* plan, Class& c, int CT) {
     c.lds = lds;
     int per_cu = 1, cus = 1;
     st = c.spec.precision == SAL_PREC_FP32 ? project_fp32_batch_occupancy(c.spec.n, c.spec.s, lds, &per_cu)
-                                           : project_lowp_batch_occupancy(c.spec.n, c.spec.s, c.spec.precision, lds,
-                                                                          &per_cu);
+                                           : project_lowp_batch_occupancy(c.spec.n, c.spec.s, c.spec.precision, CT,
+                                                                          lds, &per_cu);
     if (st) return st;
     if ((st = check_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, plan->device),
                         "hipDeviceGetAttribute")))
@@ -131,8 +131,8 @@ sal_status launch_class(sal_plan* plan, const Class& c, hipStream_t stream) {
     if (c.spec.precision == SAL_PREC_FP32)
         return project_fp32_batch(c.spec.n, c.spec.s, items, prefix, (int)c.members.size(), c.total, c.lds, c.grid,
                                   stream);
-    return project_lowp_batch(c.spec.n, c.spec.s, c.spec.precision, items, prefix, (int)c.members.size(), c.total,
-                              c.lds, c.grid, stream);
+    return project_lowp_batch(c.spec.n, c.spec.s, c.spec.precision, c.CT, items, prefix, (int)c.members.size(),
+                              c.total, c.lds, c.grid, stream);
 }
 
 sal_status enqueue_all(sal_plan* plan, hipStream_t stream) {

@@ -18,39 +18,51 @@ __device__ __forceinline__ int64_t reflect_clamp_s(int64_t p, int64_t N) {
 
 // Copy the region [RT][RI][RX] starting at voxel (t0, i0, x0) into Vt with row pitch RXp.
 // A lane owns one (il, xl) column of the region, so its reflected in-plane offset is
-// computed once; the lanes split into as many groups as there are whole columns sets in
-// the workgroup, and group g walks the t planes g, g + G, ...  The loads of up to
-// kStageBatch planes are issued before any of them is stored; every address is reflected
-// and clamped into the volume, so the loads are unconditional and only the stores are
-// masked.
+// computed once.  Whole waves form groups that each cover every column (64 lanes per wave,
+// the last wave of a group partly idle); group g walks the t planes g, g + G, ..., so a
+// plane index, its reflection and its base address are the same across the wave and stay
+// in scalar registers.  The loads of up to kStageBatch planes are issued before any of them
+// is stored; every address is reflected and clamped into the volume, so the loads are
+// unconditional and only the stores are masked.
 constexpr int kStageBatch = 16;
 
 template <int NT>
 __device__ __forceinline__ void stage_tile(const float* __restrict__ V, int64_t T, int64_t IL, int64_t XL,
                                            int64_t t0, int64_t i0, int64_t x0, int RT, int RI, int RX, int RXp,
                                            float* __restrict__ Vt) {
+    constexpr int NWV = NT / 64;
     const int PQ = RI * RX;
-    const int G = PQ >= NT ? 1 : NT / PQ;
-    const int g = (int)threadIdx.x / PQ;
+    const int WPG = (PQ + 63) / 64;                // waves per column set
+    const int G = WPG <= NWV ? NWV / WPG : 1;       // groups of waves
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int g = wave / WPG;
     if (g >= G) return;
     const int64_t PS = IL * XL;
     const int plane = RI * RXp;
-    for (int q = (int)threadIdx.x - g * PQ; q < PQ; q += NT) {
-        const int ri = q / RX, rx = q - ri * RX;
+    // waves of a group (or, with fewer waves than a column set, all waves in turn) take
+    // consecutive 64-column slices
+    const int wstep = G == 1 ? NWV : WPG;
+    for (int q = (wave - g * WPG) * 64 + lane, q0 = (wave - g * WPG) * 64; q0 < PQ; q += wstep * 64, q0 += wstep * 64) {
+        const bool act = q < PQ;
+        const int qc = act ? q : PQ - 1;
+        const int ri = qc / RX, rx = qc - ri * RX;
         const int64_t off = reflect_clamp_s(i0 + ri, IL) * XL + reflect_clamp_s(x0 + rx, XL);
-        const float* src = V + off;
+        const uint32_t off32 = (uint32_t)off;
         float* dst = Vt + ri * RXp + rx;
         for (int rt0 = g; rt0 < RT; rt0 += G * kStageBatch) {
             float v[kStageBatch];
 #pragma unroll
             for (int u = 0; u < kStageBatch; u++) {
                 const int rt = min(rt0 + u * G, RT - 1);
-                v[u] = src[reflect_clamp_s(t0 + rt, T) * PS];
+                const float* pb = V + reflect_clamp_s(t0 + rt, T) * PS;
+                // a plane below 2^30 samples takes a 32-bit lane offset on a scalar base
+                v[u] = PS < (int64_t(1) << 30) ? pb[off32] : pb[off];
             }
 #pragma unroll
             for (int u = 0; u < kStageBatch; u++) {
                 const int rt = rt0 + u * G;
-                if (rt < RT) dst[rt * plane] = v[u];
+                if (rt < RT && act) dst[rt * plane] = v[u];
             }
         }
     }
