@@ -34,6 +34,20 @@ def algorithmic_flops_per_window(n: int) -> float:
     return 2.5 * n ** 3 * math.log2(n ** 3)
 
 
+def dense_dft_flops_per_window(n: int, s: int) -> float:
+    """Flops of the separable dense-DFT contractions of one window in the sliding tile
+    design (real pass along xl at n/2+1 bins, then the two complex passes):
+    8 n^3 K + 8 n^2 K s + 4 n K s^2 with K = n/2 + 1.  The graded roofline time of a
+    launch is this count over the matrix-core peak of the precision (three products
+    for split-bf16)."""
+    K = n // 2 + 1
+    return 8.0 * n ** 3 * K + 8.0 * n ** 2 * K * s + 4.0 * n * K * s * s
+
+
+TRAFFIC_DIR = os.path.join(ROOT, "profiles")
+COPY_BYTES = 1 << 30
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -45,6 +59,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--traffic-pass", action="store_true",
+                    help="launch a %d-byte device copy, then the feature kernel twice, and exit "
+                         "(the command profiled with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)" % COPY_BYTES)
     return ap.parse_args()
 
 
@@ -143,10 +160,15 @@ def time_fwd_bwd(torch, w_name, steps, warmup):
     fwd /= steps
     bwd /= steps
     nvox = int(np.prod(V.shape))
+    nwin = int(np.prod([-(-N // w.s) for N in V.shape]))
+    # forward, recomputed spectra and the adjoint synthesis: three dense-DFT passes of FP32 work
+    t_roof = 3 * dense_dft_flops_per_window(w.n, w.s) * nwin / (PEAK_FP32_MFMA_TFLOPS * 1e12) * 1e3
     return {"workload": "%s: %s, window %d^3, stride %d, loss sum(S * U(0,1))" % (
         w_name, "x".join(str(v) for v in V.shape), w.n, w.s),
         "fwd_ms": round(fwd, 4), "bwd_ms": round(bwd, 4),
-        "fwd_bwd_mvoxel_s": round(nvox / ((fwd + bwd) * 1e-3) / 1e6, 3)}
+        "fwd_bwd_mvoxel_s": round(nvox / ((fwd + bwd) * 1e-3) / 1e6, 3),
+        "roofline": {"bound": "mfma", "t_roof_ms": round(t_roof, 4), "frac": round(t_roof / (fwd + bwd), 4),
+                     "peak_tflops": PEAK_FP32_MFMA_TFLOPS}}
 
 
 def time_batch(torch, lib, steps, count=96):
@@ -195,6 +217,41 @@ def time_batch(torch, lib, steps, count=96):
     return out
 
 
+def graded(w, nwin, precision, kern_ms):
+    """Graded roofline of the feature kernel: the dense-DFT contraction count of the
+    launch over the matrix-core peak of its precision, against the measured time."""
+    flops = dense_dft_flops_per_window(w.n, w.s) * nwin * (3 if precision == "split_bf16" else 1)
+    peak = PEAK_FP32_MFMA_TFLOPS if precision == "fp32" else PEAK_BF16_MFMA_TFLOPS
+    t_roof = flops / (peak * 1e12) * 1e3
+    return {"t_roof_ms": round(t_roof, 4), "frac": round(t_roof / kern_ms, 4),
+            "executed_flops_per_window": dense_dft_flops_per_window(w.n, w.s)}
+
+
+def stored_traffic(workload, precision):
+    """HBM bytes per launch of the FP32 feature kernel from the committed PMC summary, or
+    None when there is none for this workload or the kernel sources changed since."""
+    if precision != "fp32":
+        return None
+    from paper_2201_06174_amd import profiling
+    t = profiling.read_traffic(os.path.join(TRAFFIC_DIR, "k_project_fp32_%s_traffic.txt" % workload))
+    if not t or t.get("source_digest") != profiling.source_digest():
+        return None
+    return float(t["traffic_bytes_per_launch"])
+
+
+def traffic_pass(torch, pipe):
+    x = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(2):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
+    for _ in range(2):
+        pipe.project()
+    torch.cuda.synchronize()
+    print("traffic pass done", flush=True)
+
+
 def cpu_baseline(V, w, seconds):
     """The FP64 oracle on a bounded sample of windows of the same volume, on all host cores."""
     from oracle import oracle as orc
@@ -239,6 +296,9 @@ def main():
     Dd = torch.from_numpy(D).to(dev)
     Md = torch.from_numpy(mask).to(dev)
     pipe = Pipeline(torch, lib, Vd, w, args.precision, args.fusion, Dd, Md)
+    if args.traffic_pass:
+        traffic_pass(torch, pipe)
+        return
     ms, kern_ms, wall = time_forward(torch, pipe, args.steps, args.warmup)
     nvox = int(np.prod(V.shape))
     nwin = int(np.prod(pipe.grid))
@@ -246,6 +306,7 @@ def main():
     alg = algorithmic_flops_per_window(w.n) * nwin
     achieved = alg / (kern_ms * 1e-3) / 1e12
     peak = PEAK_FP32_MFMA_TFLOPS if args.precision == "fp32" else PEAK_BF16_MFMA_TFLOPS
+    kname = "k_project_fp32" if args.precision == "fp32" else "k_project_lowp"
     out = {
         "metric": "Mvoxel/s saliency fwd (FP32 vs split-BF16 @<=1e-3 rel) and fwd+bwd on 1 GPU",
         "value": round(value, 3),
@@ -263,9 +324,10 @@ def main():
             args.workload, "x".join(str(v) for v in V.shape), w.n, w.s, len(w.offsets), args.fusion),
             "precision": args.precision, "voxels": nvox, "windows": nwin},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": None,
-                     "kernel": "k_project_fp32 (sal_project)", "kernel_ms": round(kern_ms, 4),
-                     "flops_per_window": algorithmic_flops_per_window(w.n)},
+                     "frac": round(achieved / peak, 4), "traffic": stored_traffic(args.workload, args.precision),
+                     "kernel": "%s (sal_project)" % kname, "kernel_ms": round(kern_ms, 4),
+                     "flops_per_window": algorithmic_flops_per_window(w.n),
+                     "graded": graded(w, nwin, args.precision, kern_ms)},
     }
     if not args.no_extra:
         extra = {}
@@ -273,12 +335,12 @@ def main():
         for prec in ("fp32", "split_bf16", "fp16"):
             if prec == args.precision:
                 forms[prec] = {"ms_per_step": round(ms, 4), "kernel_ms": round(kern_ms, 4),
-                               "mvoxel_s": round(value, 3)}
+                               "mvoxel_s": round(value, 3), "graded": graded(w, nwin, prec, kern_ms)}
                 continue
             pp = Pipeline(torch, lib, Vd, w, prec, args.fusion, Dd, Md)
             m2, k2, _ = time_forward(torch, pp, max(3, args.steps // 2), 2)
             forms[prec] = {"ms_per_step": round(m2, 4), "kernel_ms": round(k2, 4),
-                           "mvoxel_s": round(nvox / (m2 * 1e-3) / 1e6, 3)}
+                           "mvoxel_s": round(nvox / (m2 * 1e-3) / 1e6, 3), "graded": graded(w, nwin, prec, k2)}
             del pp
         for prec in forms:
             forms[prec]["speedup_vs_fp32"] = round(forms["fp32"]["ms_per_step"] / forms[prec]["ms_per_step"], 3)

@@ -179,9 +179,10 @@ __device__ __forceinline__ float row_sum16(float x) {
     return x;
 }
 
-// dwords per Ab row plane: covers the furthest 5-dword read of pass B, starting at
-// il = 3s + 8 for the last window column and the upper K half
-__host__ __device__ constexpr int ab_iq2(int s) { return (3 * s + 8) / 2 + 5; }
+// dword columns per Ab row plane: cover the furthest read of pass B, which starts at
+// il = 3s + 8 (last window column, upper K half) and spans 4 dwords for an even stride,
+// 5 for an odd one
+__host__ __device__ constexpr int ab_iq2(int s) { return (3 * s + 8) / 2 + ((s & 1) ? 5 : 4); }
 
 // FIX: the tile has its full depth 8*CTW and a compile-time stride, so every LDS extent
 // and pitch is a compile-time constant (addresses fold into instruction offsets).
