@@ -167,6 +167,17 @@ sal_status get_tables(int n, int window, const Tables** out) {
             }
         }
     }
+    // the same with the Hermitian mirror folded in: on the planes kx = 0 and kx = n/2 only the ki
+    // slots [0, n/2] are visited, and a slot whose mirror n - u is skipped counts twice
+    std::vector<float> wnat_h(wnat);
+    for (int kx = 0; kx < KH; kx++) {
+        if (kx != 0 && 2 * kx != n) continue;
+        for (int u = 1; u < n; u++)
+            for (int c = 0; c < 16 * 4; c++) {
+                float& w = wnat_h[(size_t(kx) * n + u) * 64 + c];
+                w = u < n / 2 ? 2.f * w : (u == n / 2 ? w : 0.f);
+            }
+    }
     std::vector<uint16_t> chi(2 * 16 * 32, 0), clo(2 * 16 * 32, 0), ch16(2 * 16 * 32, 0);
     for (int c = 0; c < 2; c++)
         for (int r = 0; r < 16; r++)
@@ -186,7 +197,7 @@ sal_status get_tables(int n, int window, const Tables** out) {
                 clo[(c * 16 + r) * 32 + k] = to_bf16(f - from_bf16(bh));
                 ch16[(c * 16 + r) * 32 + k] = to_f16(f);
             }
-    size_t bytes = (passA.size() + mat.size() + wts.size() + inv.size() + wnat.size()) * 4 + 3 * 1024 * 2 + 10 * 256;
+    size_t bytes = (passA.size() + mat.size() + wts.size() + inv.size() + 2 * wnat.size()) * 4 + 3 * 1024 * 2 + 11 * 256;
     void* base = nullptr;
     st = check_hip(hipMalloc(&base, bytes), "hipMalloc(tables)");
     if (st) return st;
@@ -205,16 +216,58 @@ sal_status get_tables(int n, int window, const Tables** out) {
     dt.t.wts = (const float*)put(wts.data(), wts.size() * 4);
     dt.t.inv = (const float*)put(inv.data(), inv.size() * 4);
     dt.t.wts_nat = (const float*)put(wnat.data(), wnat.size() * 4);
+    dt.t.wts_nat_h = (const float*)put(wnat_h.data(), wnat_h.size() * 4);
     dt.t.cpx_hi = (const uint16_t*)put(chi.data(), chi.size() * 2);
     dt.t.cpx_lo = (const uint16_t*)put(clo.data(), clo.size() * 2);
     dt.t.cpx_h16 = (const uint16_t*)put(ch16.data(), ch16.size() * 2);
-    if (!dt.t.passA || !dt.t.mat || !dt.t.wts || !dt.t.inv || !dt.t.wts_nat || !dt.t.cpx_hi || !dt.t.cpx_lo ||
-        !dt.t.cpx_h16) {
+    if (!dt.t.passA || !dt.t.mat || !dt.t.wts || !dt.t.inv || !dt.t.wts_nat || !dt.t.wts_nat_h || !dt.t.cpx_hi ||
+        !dt.t.cpx_lo || !dt.t.cpx_h16) {
         hipFree(base);
         return fail(SAL_ERR_DEVICE, "uploading constant tables failed");
     }
     auto res = g_tables.emplace(key, dt);
     *out = &res.first->second.t;
+    return SAL_OK;
+}
+
+static std::map<std::tuple<int, int, int, int>, void*> g_pa_ops;
+
+sal_status get_pass_a_ops(int n, int s, int window, const uint16_t** out) {
+    int dev = 0;
+    sal_status st = check_hip(hipGetDevice(&dev), "hipGetDevice");
+    if (st) return st;
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto key = std::make_tuple(dev, n, s, window);
+    auto it = g_pa_ops.find(key);
+    if (it != g_pa_ops.end()) {
+        *out = (const uint16_t*)it->second;
+        return SAL_OK;
+    }
+    const int KH = n / 2 + 1;
+    std::vector<uint16_t> ops(size_t(KH) * 3 * 16 * 32, 0);
+    for (int kx = 0; kx < KH; kx++)
+        for (int c = 0; c < 8; c++) {
+            const int h = c >> 2, xc = c & 3;
+            for (int x = 0; x < 32; x++) {
+                const int a = x - xc * s;
+                if (a < 0 || a >= n) continue;
+                const double t = taper(a, n, window);
+                const float f = float(h == 0 ? t * cos_k(kx, a, n) : -t * sin_k(kx, a, n));
+                const uint16_t bh = to_bf16(f);
+                uint16_t* o = &ops[(size_t(kx) * 3 * 16 + c) * 32 + x];
+                o[0] = bh;
+                o[16 * 32] = to_bf16(f - from_bf16(bh));
+                o[2 * 16 * 32] = to_f16(f);
+            }
+        }
+    void* d = nullptr;
+    if ((st = check_hip(hipMalloc(&d, ops.size() * 2), "hipMalloc(pass A operands)"))) return st;
+    if ((st = check_hip(hipMemcpy(d, ops.data(), ops.size() * 2, hipMemcpyHostToDevice), "hipMemcpy(pass A operands)"))) {
+        hipFree(d);
+        return st;
+    }
+    g_pa_ops.emplace(key, d);
+    *out = (const uint16_t*)d;
     return SAL_OK;
 }
 

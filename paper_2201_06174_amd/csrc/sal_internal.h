@@ -36,6 +36,8 @@ struct Tables {
     const float* wts = nullptr;     // [KH][n][16][4]: bin weights mult(kx) alpha_m / n^3 per packed row
     const float* inv = nullptr;     // [16 a][16 r]: h(a) * trig row r at sample a (transpose of `mat`), zero padded
     const float* wts_nat = nullptr; // [KH][n][16][4]: bin weights for natural-order rows (row r = bin r)
+    const float* wts_nat_h = nullptr; // the same, with ki slots (n/2, n) of the planes kx = 0, n/2 folded into
+                                      // their Hermitian mirrors (doubled slots 1 .. n/2-1, zero beyond n/2)
     // complex DFT operands of the reduced-precision passes, [2 (re, im)][16 rows][32 K]:
     // row r is bin r (signed frequency), K = [real part samples 0..15 | imaginary part samples 0..15],
     // re rows h cos | h sin, im rows -h sin | h cos; bf16 hi and lo parts and fp16
@@ -45,6 +47,12 @@ struct Tables {
 };
 
 sal_status get_tables(int n, int window, const Tables** out);
+
+// Per (device, n, s, window) B operands of the reduced-precision pass A, [KH][3][16 cols][32 K]:
+// planes bf16 hi, bf16 lo, fp16; column c < 8 is (c >> 2: h cos | -h sin, c & 3: window column
+// xc), K = sample x of a staged row, holding the taper*twiddle of tap x - xc*s (zero outside
+// the window and for columns 8..15).
+sal_status get_pass_a_ops(int n, int s, int window, const uint16_t** out);
 
 // Packed row r of an n-point transform: its frequency q and whether it is a sine row.
 // Rows: 0 -> cos 0, 1 -> cos n/2, 2q -> cos q, 2q+1 -> sin q (1 <= q < n/2), r >= n -> zero.

@@ -35,7 +35,8 @@ struct LowpParams {
     const float* passA;
     const uint16_t* cpx_a;  // hi (bf16) or fp16 operand table [2][16][32]
     const uint16_t* cpx_b;  // lo (bf16) table, unused for fp16
-    const float4* wts;      // natural-order weights
+    const float4* wts;      // natural-order weights, Hermitian mirror folded in (wts_nat_h)
+    const uint16_t* pa_ops; // pass-A operands of this stride (fixed tiles)
     float* E;
 };
 
@@ -184,8 +185,33 @@ __device__ __forceinline__ float row_sum16(float x) {
 // 5 for an odd one
 __host__ __device__ constexpr int ab_iq2(int s) { return (3 * s + 8) / 2 + ((s & 1) ? 5 : 4); }
 
+// Extents of the fixed-tile LDS layout, where the staged volume is held as 16-bit planes
+// for pass A on the matrix cores: rows r = rt * RIE + il of XP samples (RIE = RI rounded up
+// to even so that rows r, r + 1 with r even are il pairs of one rt; XP = RX rounded up to 8
+// for 16-byte operand reads), MT tiles of 16 rows, plus the rows that the 32-sample operand
+// reads of the last tile run past.
+struct FixGeom {
+    int RT, RTe, RI, RIE, RX, XP, MROWS, MT, VROWS, VP;
+};
+__host__ __device__ constexpr FixGeom fix_geom(int n, int s, int CT) {
+    FixGeom g{};
+    g.RT = (CT - 1) * s + n;
+    g.RTe = (g.RT + 1) & ~1;
+    g.RI = 3 * s + n;
+    g.RIE = (g.RI + 1) & ~1;
+    g.RX = 3 * s + n;
+    g.XP = (g.RX + 7) & ~7;
+    g.MROWS = g.RTe * g.RIE;
+    g.MT = (g.MROWS + 15) / 16;
+    g.VROWS = g.MT * 16 + (32 - g.XP + g.XP - 1) / g.XP;
+    g.VP = g.VROWS * g.XP;
+    return g;
+}
+
 // FIX: the tile has its full depth 8*CTW and a compile-time stride, so every LDS extent
-// and pitch is a compile-time constant (addresses fold into instruction offsets).
+// and pitch is a compile-time constant (addresses fold into instruction offsets), and the
+// volume is staged once per tile as 16-bit operands: pass A then also runs on the matrix
+// cores, and the bin weights are read from the (cached) global table.
 template <int N, int S, int PREC, int CTW, bool FIX>
 __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int64_t tile, float* lds) {
     using L = Lp<PREC>;
@@ -208,14 +234,19 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
     const int s = S > 0 ? S : p.s;
     static_assert(!FIX || S > 0, "a fixed tile needs a compile-time stride");
     constexpr int CTF = 8 * CTW;
+    constexpr FixGeom FG = fix_geom(N, S > 0 ? S : 1, CTF);
     const int CT = FIX ? CTF : p.CT;
-    const int RT = FIX ? (CTF - 1) * S + N : p.RT;
+    const int RT = FIX ? FG.RT : p.RT;
     const int RTe = (RT + 1) & ~1;
     const int RTp = FIX ? lowp_rtp(CTF, S > 0 ? S : 1) : p.RTp;
     const int RI = S > 0 ? 3 * S + N : p.RI, RX = RI, RXp = S > 0 ? ((3 * S + N) | 1) : p.RXp;
     const int IQ2 = S > 0 ? ab_iq2(S) : p.IQ2;
-    float* Vt = lds;                                                     // [RT][RI][RXp] fp32
-    uint16_t* Ab = (uint16_t*)(Vt + (((size_t)RT * RI * RXp + 3) & ~(size_t)3));  // [NPL][RTe][IQ2][4][2]
+    // fixed tile: Vb [hi, lo][VROWS][XP] 16-bit; otherwise Vt [RT][RI][RXp] fp32
+    float* Vt = lds;
+    uint16_t* Vb = (uint16_t*)lds;
+    constexpr int NVP = L::split ? 2 : 1;
+    const size_t vbytes = FIX ? (size_t)NVP * FG.VP * 2 : (((size_t)RT * RI * RXp + 3) & ~(size_t)3) * 4;
+    uint16_t* Ab = (uint16_t*)((char*)lds + vbytes);                      // [NPL][RTe][IQ2][4][2]
     const int abPlane = RTe * IQ2 * 8;
     uint16_t* Gh = Ab + (size_t)NPL * abPlane;                          // [2][N][16][RTp]
     uint16_t* Gl = Gh + (size_t)2 * N * 16 * RTp;                        // same, lo parts (split only)
@@ -224,7 +255,44 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
     const int gStrideRi = N * 16 * RTp;
 
     const int64_t t0 = tt * CT * s - N / 2, i0 = ti * 4 * s - N / 2, x0 = tx * 4 * s - N / 2;
-    stage_tile<kNTL>(p.V, p.T, p.IL, p.XL, t0, i0, x0, RT, RI, RX, RXp, Vt);
+    if constexpr (FIX) {
+        stage_tile_with<kNTL>(p.V, p.T, p.IL, p.XL, t0, i0, x0, RT, RI, RX, [&](int rt, int ri, int rx, float v) {
+            const int at = (rt * FG.RIE + ri) * FG.XP + rx;
+            const uint16_t h = L::hi(v);
+            Vb[at] = h;
+            if constexpr (L::split) Vb[FG.VP + at] = L::lo(v, h);
+        });
+        // zero the pads the operand reads cover (disjoint from the staged samples): columns
+        // [RX, XP) of every row, the odd il row of each rt, and the rows from rt = RT on
+        constexpr int XPAD = FG.XP - FG.RX;
+        if constexpr (XPAD > 0)
+            for (int e = tid; e < FG.VROWS * XPAD; e += kNTL) {
+                const int at = (e / XPAD) * FG.XP + FG.RX + e % XPAD;
+                Vb[at] = 0;
+                if constexpr (L::split) Vb[FG.VP + at] = 0;
+            }
+        if constexpr (FG.RIE > FG.RI)
+            for (int e = tid; e < FG.RT * FG.RX; e += kNTL) {
+                const int at = ((e / FG.RX) * FG.RIE + FG.RI) * FG.XP + e % FG.RX;
+                Vb[at] = 0;
+                if constexpr (L::split) Vb[FG.VP + at] = 0;
+            }
+        for (int e = tid; e < (FG.VROWS - FG.RT * FG.RIE) * FG.RX; e += kNTL) {
+            const int at = (FG.RT * FG.RIE + e / FG.RX) * FG.XP + e % FG.RX;
+            Vb[at] = 0;
+            if constexpr (L::split) Vb[FG.VP + at] = 0;
+        }
+        // Ab columns il/2 in [RIE/2, IQ2) are read by pass B but never written by pass A
+        constexpr int CPAD = ab_iq2(S > 0 ? S : 1) - FG.RIE / 2;
+        if constexpr (CPAD > 0)
+            for (int e = tid; e < NPL * FG.RTe * CPAD * 4; e += kNTL) {
+                const int pl = e / (FG.RTe * CPAD * 4), r = e % (FG.RTe * CPAD * 4);
+                const int rt = r / (CPAD * 4), k = r % (CPAD * 4);
+                ((uint32_t*)(Ab + (size_t)pl * abPlane))[(rt * IQ2 + FG.RIE / 2) * 4 + k] = 0u;
+            }
+    } else {
+        stage_tile<kNTL>(p.V, p.T, p.IL, p.XL, t0, i0, x0, RT, RI, RX, RXp, Vt);
+    }
     // the samples past the last staged row only meet zero coefficients; keep them finite
     for (int e = tid; e < 2 * N * 16 * (RTp - RT); e += kNTL) {
         const int pad = RTp - RT;
@@ -255,6 +323,15 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
             aim_l = aim_h;
         }
     }
+    // pass-A operands of a bin kx (fixed tile): lane supplies column col (cos|sin x window
+    // column), K slots = staged samples 8*grp .. 8*grp+7
+    auto pass_a_ops = [&](int kx, vec& bh, vec& bl) {
+        const uint16_t* o = p.pa_ops + ((size_t)(kx * 3 + (L::split ? 0 : 2)) * 16 + col) * 32 + 8 * grp;
+        bh = __builtin_bit_cast(vec, *(const uint4*)o);
+        bl = L::split ? __builtin_bit_cast(vec, *(const uint4*)(o + 16 * 32)) : bh;
+    };
+    vec pbh, pbl;
+    if constexpr (FIX) pass_a_ops(0, pbh, pbl);
 
     const int wtc = wave & 7;
     // acc[c][j][m]: window 4*grp + j of t slot wtc + 8c, plane m, summed over this lane's bins
@@ -270,72 +347,97 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
     __syncthreads();
 
     for (int kx = 0; kx < KH; kx++) {
-        // ---- pass A (fp32 sums): one thread per (rt, il pair, cos|sin); the two rows'
-        // results are rounded once and stored as packed pairs for pass B
-        for (int e = tid; e < RTe * IQ2 * 2; e += kNTL) {
-            const int h = e & 1;
-            const int q = e >> 1;
-            const int rt = q / IQ2, il2 = q - rt * IQ2;
-            float cf[N];
+        if constexpr (FIX) {
+            // ---- pass A on the matrix cores: 16 staged rows x 32 samples times the 32 x 16
+            // operand of this kx (columns cos|sin x window column); the il pairs of the result
+            // are rounded once and stored packed for pass B
+            for (int mt = wave; mt < FG.MT; mt += NW) {
+                const uint16_t* ra = Vb + (size_t)(mt * 16 + col) * FG.XP + 8 * grp;
+                const vec ah = __builtin_bit_cast(vec, *(const uint4*)ra);
+                const vec al = L::split ? __builtin_bit_cast(vec, *(const uint4*)(ra + FG.VP)) : ah;
+                const f4 d = contract<PREC>(ah, al, pbh, pbl, f4{0.f, 0.f, 0.f, 0.f});
+                if (col < 8) {
+                    const int h = col >> 2, xc = col & 3;
 #pragma unroll
-            for (int a = 0; a < N; a++) cf[a] = p.passA[(kx * N + a) * 2 + h];
-            float o[2][4];
-#pragma unroll
-            for (int r = 0; r < 2; r++) {
-                const int il = 2 * il2 + r;
-#pragma unroll
-                for (int xc = 0; xc < 4; xc++) o[r][xc] = 0.f;
-                if (rt < RT && il < RI) {
-                    const float* row = Vt + (rt * RI + il) * RXp;
-                    if constexpr (S > 0) {
-                        constexpr int RXc = 3 * S + N;
-                        float v[RXc];
-#pragma unroll
-                        for (int k = 0; k < RXc; k++) v[k] = row[k];
-#pragma unroll
-                        for (int xc = 0; xc < 4; xc++) {
-                            float acc_a = 0.f;
-#pragma unroll
-                            for (int a = 0; a < N; a++) acc_a = fmaf(cf[a], v[xc * S + a], acc_a);
-                            o[r][xc] = acc_a;
-                        }
-                    } else {
-#pragma unroll
-                        for (int xc = 0; xc < 4; xc++) {
-                            float acc_a = 0.f;
-#pragma unroll
-                            for (int a = 0; a < N; a++) acc_a = fmaf(cf[a], row[xc * s + a], acc_a);
-                            o[r][xc] = acc_a;
+                    for (int pr = 0; pr < 2; pr++) {
+                        const int r = mt * 16 + 4 * grp + 2 * pr;
+                        if (r < FG.MROWS) {
+                            const int rt = r / FG.RIE, il2 = (r - rt * FG.RIE) >> 1;
+                            const int at = (rt * IQ2 + il2) * 4 + xc;
+                            const uint32_t hw = L::pack_hi(d[2 * pr], d[2 * pr + 1]);
+                            ((uint32_t*)(Ab + (size_t)h * abPlane))[at] = hw;
+                            if constexpr (L::split)
+                                ((uint32_t*)(Ab + (size_t)(2 + h) * abPlane))[at] = L::pack_lo(d[2 * pr], d[2 * pr + 1], hw);
                         }
                     }
                 }
             }
-            uint4 wh, wl;
-            wh.x = L::pack_hi(o[0][0], o[1][0]);
-            wh.y = L::pack_hi(o[0][1], o[1][1]);
-            wh.z = L::pack_hi(o[0][2], o[1][2]);
-            wh.w = L::pack_hi(o[0][3], o[1][3]);
-            const size_t at = (size_t)(rt * IQ2 + il2) * 8;
-            *(uint4*)(Ab + (size_t)h * abPlane + at) = wh;
-            if constexpr (L::split) {
-                wl.x = L::pack_lo(o[0][0], o[1][0], wh.x);
-                wl.y = L::pack_lo(o[0][1], o[1][1], wh.y);
-                wl.z = L::pack_lo(o[0][2], o[1][2], wh.z);
-                wl.w = L::pack_lo(o[0][3], o[1][3], wh.w);
-                *(uint4*)(Ab + (size_t)(2 + h) * abPlane + at) = wl;
+            if (kx + 1 < KH) pass_a_ops(kx + 1, pbh, pbl);
+        } else {
+            // ---- pass A (fp32 sums): one thread per (rt, il pair, cos|sin); the two rows'
+            // results are rounded once and stored as packed pairs for pass B
+            for (int e = tid; e < RTe * IQ2 * 2; e += kNTL) {
+                const int h = e & 1;
+                const int q = e >> 1;
+                const int rt = q / IQ2, il2 = q - rt * IQ2;
+                float cf[N];
+#pragma unroll
+                for (int a = 0; a < N; a++) cf[a] = p.passA[(kx * N + a) * 2 + h];
+                float o[2][4];
+#pragma unroll
+                for (int r = 0; r < 2; r++) {
+                    const int il = 2 * il2 + r;
+#pragma unroll
+                    for (int xc = 0; xc < 4; xc++) o[r][xc] = 0.f;
+                    if (rt < RT && il < RI) {
+                        const float* row = Vt + (rt * RI + il) * RXp;
+                        if constexpr (S > 0) {
+                            constexpr int RXc = 3 * S + N;
+                            float v[RXc];
+#pragma unroll
+                            for (int k = 0; k < RXc; k++) v[k] = row[k];
+#pragma unroll
+                            for (int xc = 0; xc < 4; xc++) {
+                                float acc_a = 0.f;
+#pragma unroll
+                                for (int a = 0; a < N; a++) acc_a = fmaf(cf[a], v[xc * S + a], acc_a);
+                                o[r][xc] = acc_a;
+                            }
+                        } else {
+#pragma unroll
+                            for (int xc = 0; xc < 4; xc++) {
+                                float acc_a = 0.f;
+#pragma unroll
+                                for (int a = 0; a < N; a++) acc_a = fmaf(cf[a], row[xc * s + a], acc_a);
+                                o[r][xc] = acc_a;
+                            }
+                        }
+                    }
+                }
+                uint4 wh, wl;
+                wh.x = L::pack_hi(o[0][0], o[1][0]);
+                wh.y = L::pack_hi(o[0][1], o[1][1]);
+                wh.z = L::pack_hi(o[0][2], o[1][2]);
+                wh.w = L::pack_hi(o[0][3], o[1][3]);
+                const size_t at = (size_t)(rt * IQ2 + il2) * 8;
+                *(uint4*)(Ab + (size_t)h * abPlane + at) = wh;
+                if constexpr (L::split) {
+                    wl.x = L::pack_lo(o[0][0], o[1][0], wh.x);
+                    wl.y = L::pack_lo(o[0][1], o[1][1], wh.y);
+                    wl.z = L::pack_lo(o[0][2], o[1][2], wh.z);
+                    wl.w = L::pack_lo(o[0][3], o[1][3], wh.w);
+                    *(uint4*)(Ab + (size_t)(2 + h) * abPlane + at) = wl;
+                }
             }
         }
         __syncthreads();
         // bin weights of this kx.  The planes kx = 0 and kx = n/2 are their own Hermitian
-        // mirrors (|F(-k)| = |F(k)|): only the ki slots [0, n/2] are visited there, and a slot
-        // whose mirror is skipped counts twice.
+        // mirrors (|F(-k)| = |F(k)|): only the ki slots [0, n/2] are visited there, with the
+        // skipped mirrors folded into the table's weights.
         const bool mirror = kx == 0 || 2 * kx == N;
-        for (int e = tid; e < N * 16; e += kNTL) {
-            const int u = e >> 4;
-            const float f = mirror && u >= 1 && u < N / 2 ? 2.f : 1.f;
-            const float4 w = p.wts[(size_t)kx * N * 16 + e];
-            Wl[e] = make_float4(f * w.x, f * w.y, f * w.z, f * w.w);
-        }
+        const float4* wk = p.wts + (size_t)kx * N * 16;
+        if constexpr (!FIX)
+            for (int e = tid; e < N * 16; e += kNTL) Wl[e] = wk[e];
         // ---- pass B: complex DFT along il for a pair of rows per wave; the outputs of the
         // two rows are rounded and written as packed pairs along t
         {
@@ -401,14 +503,21 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
                     dre = contract<PREC>(vh, vl, are_h, are_l, f4{0.f, 0.f, 0.f, 0.f});
                     dim = contract<PREC>(vh, vl, aim_h, aim_l, f4{0.f, 0.f, 0.f, 0.f});
                 };
+                // weights of bin (kt = col, ki = u): from LDS, or on the fixed tile straight
+                // from the global table, fetched one slot ahead
+                auto weight = [&](int u) { return FIX ? wk[u * 16 + col] : Wl[u * 16 + col]; };
                 f4 dre, dim;
+                float4 w = weight(ua);
                 contract_c(ua, dre, dim);
 #pragma unroll
                 for (int uu = 0; uu < CNT; uu++) {
                     const int u = ua + uu;
-                    const float4 w = Wl[u * 16 + col];
                     f4 nre, nim;
-                    if (uu + 1 < CNT) contract_c(u + 1, nre, nim);
+                    float4 wn;
+                    if (uu + 1 < CNT) {
+                        wn = weight(u + 1);
+                        contract_c(u + 1, nre, nim);
+                    }
 #pragma unroll
                     for (int j = 0; j < 4; j++) {
                         const float m = __builtin_amdgcn_sqrtf(fmaf(dre[j], dre[j], dim[j] * dim[j]));
@@ -419,6 +528,7 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
                     if (uu + 1 < CNT) {
                         dre = nre;
                         dim = nim;
+                        w = wn;
                     }
                 }
             };
@@ -506,6 +616,15 @@ __global__ __launch_bounds__(kNTL) void k_project_lowp_batch(const LowpParams* _
     }
 }
 
+static int lowp_ctw(int n) { return n == 4 ? 2 : 1; }
+
+// Whether a launch takes the fixed-tile kernel: a stride built at compile time for this n
+// (the dispatch below) and the full tile depth.
+static bool lowp_fixed(int n, int s, int CT) {
+    const bool compiled = s == 1 || (s == 2 && n > 4) || (s == 3 && n > 6);
+    return compiled && CT == 8 * lowp_ctw(n);
+}
+
 static size_t lowp_lds_bytes(int n, int s, int CT, bool split, LowpParams* p) {
     p->RT = (CT - 1) * s + n;
     p->RTp = lowp_rtp(CT, s);
@@ -514,15 +633,18 @@ static size_t lowp_lds_bytes(int n, int s, int CT, bool split, LowpParams* p) {
     p->RXp = p->RX | 1;
     p->IQ2 = ab_iq2(s);
     const size_t RTe = (size_t)((p->RT + 1) & ~1);
-    const size_t f32 = ((size_t)p->RT * p->RI * p->RXp + 3) & ~(size_t)3;
     const size_t ab = (split ? 4 : 2) * RTe * p->IQ2 * 8;
     const size_t g = std::max<size_t>((size_t)2 * n * 16 * p->RTp * (split ? 2 : 1), 8 * 16 * 3 * 2 * 2);
+    if (lowp_fixed(n, s, CT)) {
+        // 16-bit staged planes, no weight staging
+        const FixGeom fg = fix_geom(n, s, CT);
+        return 2 * ((split ? 2 : 1) * (size_t)fg.VP + ab + g);
+    }
+    const size_t f32 = ((size_t)p->RT * p->RI * p->RXp + 3) & ~(size_t)3;
     return sizeof(float) * f32 + 2 * (ab + g) + sizeof(float) * 4 * 16 * n;
 }
 
 static constexpr size_t kLdsMaxL = 160 * 1024;
-
-static int lowp_ctw(int n) { return n == 4 ? 2 : 1; }
 
 void project_lowp_ct_candidates(int n, int s, int precision, std::vector<int>* out) {
     out->clear();
@@ -559,7 +681,12 @@ sal_status project_lowp_params(int n, int s, int precision, int CT, const float*
     p.passA = tb->passA;
     p.cpx_a = split ? tb->cpx_hi : tb->cpx_h16;
     p.cpx_b = tb->cpx_lo;
-    p.wts = (const float4*)tb->wts_nat;
+    p.wts = (const float4*)tb->wts_nat_h;
+    p.pa_ops = nullptr;
+    if (lowp_fixed(n, s, CT)) {
+        sal_status st = get_pass_a_ops(n, s, tb->window, &p.pa_ops);
+        if (st) return st;
+    }
     p.E = E;
     *ntiles = p.ntiles;
     if (out) memcpy(out, &p, sizeof(p));

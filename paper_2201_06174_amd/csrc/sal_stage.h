@@ -16,7 +16,8 @@ __device__ __forceinline__ int64_t reflect_clamp_s(int64_t p, int64_t N) {
     return p < 0 ? 0 : (p >= N ? N - 1 : p);
 }
 
-// Copy the region [RT][RI][RX] starting at voxel (t0, i0, x0) into Vt with row pitch RXp.
+// Hand every sample of the region [RT][RI][RX] starting at voxel (t0, i0, x0) to
+// store(rt, ri, rx, value).
 // A lane owns one (il, xl) column of the region, so its reflected in-plane offset is
 // computed once.  Whole waves form groups that each cover every column (64 lanes per wave,
 // the last wave of a group partly idle); group g walks the t planes g, g + G, ..., so a
@@ -26,10 +27,10 @@ __device__ __forceinline__ int64_t reflect_clamp_s(int64_t p, int64_t N) {
 // unconditional and only the stores are masked.
 constexpr int kStageBatch = 16;
 
-template <int NT>
-__device__ __forceinline__ void stage_tile(const float* __restrict__ V, int64_t T, int64_t IL, int64_t XL,
-                                           int64_t t0, int64_t i0, int64_t x0, int RT, int RI, int RX, int RXp,
-                                           float* __restrict__ Vt) {
+template <int NT, typename Store>
+__device__ __forceinline__ void stage_tile_with(const float* __restrict__ V, int64_t T, int64_t IL, int64_t XL,
+                                                int64_t t0, int64_t i0, int64_t x0, int RT, int RI, int RX,
+                                                Store store) {
     constexpr int NWV = NT / 64;
     const int PQ = RI * RX;
     const int WPG = (PQ + 63) / 64;                // waves per column set
@@ -39,7 +40,6 @@ __device__ __forceinline__ void stage_tile(const float* __restrict__ V, int64_t 
     const int g = wave / WPG;
     if (g >= G) return;
     const int64_t PS = IL * XL;
-    const int plane = RI * RXp;
     // waves of a group (or, with fewer waves than a column set, all waves in turn) take
     // consecutive 64-column slices
     const int wstep = G == 1 ? NWV : WPG;
@@ -49,7 +49,6 @@ __device__ __forceinline__ void stage_tile(const float* __restrict__ V, int64_t 
         const int ri = qc / RX, rx = qc - ri * RX;
         const int64_t off = reflect_clamp_s(i0 + ri, IL) * XL + reflect_clamp_s(x0 + rx, XL);
         const uint32_t off32 = (uint32_t)off;
-        float* dst = Vt + ri * RXp + rx;
         for (int rt0 = g; rt0 < RT; rt0 += G * kStageBatch) {
             float v[kStageBatch];
 #pragma unroll
@@ -62,10 +61,19 @@ __device__ __forceinline__ void stage_tile(const float* __restrict__ V, int64_t 
 #pragma unroll
             for (int u = 0; u < kStageBatch; u++) {
                 const int rt = rt0 + u * G;
-                if (rt < RT && act) dst[rt * plane] = v[u];
+                if (rt < RT && act) store(rt, ri, rx, v[u]);
             }
         }
     }
+}
+
+// fp32 rows of pitch RXp: Vt[(rt * RI + ri) * RXp + rx]
+template <int NT>
+__device__ __forceinline__ void stage_tile(const float* __restrict__ V, int64_t T, int64_t IL, int64_t XL,
+                                           int64_t t0, int64_t i0, int64_t x0, int RT, int RI, int RX, int RXp,
+                                           float* __restrict__ Vt) {
+    stage_tile_with<NT>(V, T, IL, XL, t0, i0, x0, RT, RI, RX,
+                        [&](int rt, int ri, int rx, float v) { Vt[(rt * RI + ri) * RXp + rx] = v; });
 }
 
 }  // namespace sal
