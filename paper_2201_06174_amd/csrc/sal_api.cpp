@@ -1,6 +1,7 @@
 // sal_api.cpp -- the C ABI of libsal: argument validation on the host, then launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <string>
@@ -25,6 +26,7 @@ sal_status make_stencil(const sal_stencil* st, int s, DcsStencil* out) {
     if (s < 1) return fail(SAL_ERR_ARG, "stride must be >= 1");
     out->q = st->q;
     out->literal = st->literal ? 1 : 0;
+    out->reach[0] = out->reach[1] = out->reach[2] = 0;
     int d = 0;
     for (int k = 0; k < st->q; k++) {
         for (int a = 0; a < 3; a++) {
@@ -32,6 +34,7 @@ sal_status make_stencil(const sal_stencil* st, int s, DcsStencil* out) {
             if (v % s != 0) return fail(SAL_ERR_ARG, "stencil offsets must be multiples of the stride");
             if (std::abs(v) > (1 << 24)) return fail(SAL_ERR_ARG, "stencil offset too large");
             out->o[k][a] = v / s;
+            out->reach[a] = std::max(out->reach[a], std::abs(v / s));
             d = std::abs(v) > d ? std::abs(v) : d;
         }
     }

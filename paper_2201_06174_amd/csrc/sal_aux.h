@@ -14,6 +14,7 @@ constexpr int kFuseParts = 256;  // fixed number of partial-sum blocks (determin
 struct DcsStencil {
     int q;
     int literal;
+    int reach[3];  // largest |offset| per axis, in grid units
     int o[SAL_MAX_STENCIL][3];
     float w[SAL_MAX_STENCIL];
 };

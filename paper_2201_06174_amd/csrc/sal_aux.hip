@@ -117,51 +117,72 @@ sal_status launch_dcs(const float* E, float* S, int64_t Tg, int64_t ILg, int64_t
 }
 
 // Adjoint of Eq. 3 as a gather: each grid point collects its own terms and the
-// terms in which it is the neighbour of g - o.  sgn(0) = 0.
+// terms in which it is the neighbour of g - o.  sgn(0) = 0.  Neighbour counts do not
+// depend on the plane and are found once; a point at least twice the stencil reach away
+// from every border (so its neighbours' stencils stay inside too) has all of them equal
+// to q.  The terms of each plane are summed in the same order as a per-plane loop would.
+template <typename I>
+__device__ __forceinline__ void dcs_adjoint_point(const float* __restrict__ E, const float* __restrict__ gSm,
+                                                  float* __restrict__ gE, I Tg, I ILg, I XLg, const DcsStencil& st,
+                                                  I j) {
+    const I G = Tg * ILg * XLg;
+    const I gx = j % XLg, gi = (j / XLg) % ILg, gt = j / (XLg * ILg);
+    auto inside = [&](I a, I b, I c) { return a >= 0 && a < Tg && b >= 0 && b < ILg && c >= 0 && c < XLg; };
+    auto count = [&](I a, I b, I c) {
+        int Q = 0;
+        for (int k = 0; k < st.q; k++) Q += inside(a + st.o[k][0], b + st.o[k][1], c + st.o[k][2]);
+        return Q;
+    };
+    const bool inner = gt >= 2 * st.reach[0] && gt + 2 * st.reach[0] < Tg && gi >= 2 * st.reach[1] &&
+                       gi + 2 * st.reach[1] < ILg && gx >= 2 * st.reach[2] && gx + 2 * st.reach[2] < XLg;
+    float e0[3], cg[3], acc[3] = {0.f, 0.f, 0.f};
+    const int Qg = inner ? st.q : count(gt, gi, gx);
+#pragma unroll
+    for (int m = 0; m < 3; m++) {
+        e0[m] = E[m * G + j];
+        cg[m] = Qg ? gSm[m * G + j] / (float)Qg : 0.f;
+    }
+    if (Qg) {
+        for (int k = 0; k < st.q; k++) {
+            const I nt = gt + st.o[k][0], ni = gi + st.o[k][1], nx = gx + st.o[k][2];
+            if (!inner && !inside(nt, ni, nx)) continue;
+            const I jn = (nt * ILg + ni) * XLg + nx;
+#pragma unroll
+            for (int m = 0; m < 3; m++) {
+                const float e1 = E[m * G + jn];
+                const float d = st.literal ? e0[m] - st.w[k] * e1 : e0[m] - e1;
+                const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
+                acc[m] += cg[m] * (st.literal ? 1.f : st.w[k]) * sg;
+            }
+        }
+    }
+    for (int k = 0; k < st.q; k++) {
+        const I pt = gt - st.o[k][0], pi = gi - st.o[k][1], px = gx - st.o[k][2];
+        if (!inner && !inside(pt, pi, px)) continue;
+        const I jp = (pt * ILg + pi) * XLg + px;
+        const int Qp = inner ? st.q : count(pt, pi, px);
+#pragma unroll
+        for (int m = 0; m < 3; m++) {
+            const float ep = E[m * G + jp];
+            const float d = st.literal ? ep - st.w[k] * e0[m] : ep - e0[m];
+            const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
+            acc[m] -= gSm[m * G + jp] / (float)Qp * st.w[k] * sg;
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < 3; m++) gE[m * G + j] = acc[m];
+}
+
 __global__ __launch_bounds__(256) void k_dcs_adjoint(const float* __restrict__ E, const float* __restrict__ gSm,
                                                      float* __restrict__ gE, int64_t Tg, int64_t ILg, int64_t XLg,
                                                      DcsStencil st) {
     const int64_t G = Tg * ILg * XLg;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= G) return;
-    const int64_t gx = j % XLg, gi = (j / XLg) % ILg, gt = j / (XLg * ILg);
-    auto inside = [&](int64_t a, int64_t b, int64_t c) {
-        return a >= 0 && a < Tg && b >= 0 && b < ILg && c >= 0 && c < XLg;
-    };
-    auto count = [&](int64_t a, int64_t b, int64_t c) {
-        int Q = 0;
-        for (int k = 0; k < st.q; k++) Q += inside(a + st.o[k][0], b + st.o[k][1], c + st.o[k][2]);
-        return Q;
-    };
-    for (int m = 0; m < 3; m++) {
-        const float* Em = E + m * G;
-        const float* gm = gSm + m * G;
-        const float e0 = Em[j];
-        float acc = 0.f;
-        const int Qg = count(gt, gi, gx);
-        if (Qg) {
-            const float cg = gm[j] / (float)Qg;
-            for (int k = 0; k < st.q; k++) {
-                const int64_t nt = gt + st.o[k][0], ni = gi + st.o[k][1], nx = gx + st.o[k][2];
-                if (!inside(nt, ni, nx)) continue;
-                const float e1 = Em[(nt * ILg + ni) * XLg + nx];
-                const float d = st.literal ? e0 - st.w[k] * e1 : e0 - e1;
-                const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
-                acc += cg * (st.literal ? 1.f : st.w[k]) * sg;
-            }
-        }
-        for (int k = 0; k < st.q; k++) {
-            const int64_t pt = gt - st.o[k][0], pi = gi - st.o[k][1], px = gx - st.o[k][2];
-            if (!inside(pt, pi, px)) continue;
-            const int64_t jp = (pt * ILg + pi) * XLg + px;
-            const int Qp = count(pt, pi, px);
-            const float ep = Em[jp];
-            const float d = st.literal ? ep - st.w[k] * e0 : ep - e0;
-            const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
-            acc -= gm[jp] / (float)Qp * st.w[k] * sg;
-        }
-        gE[m * G + j] = acc;
-    }
+    if (3 * G < (int64_t(1) << 31))
+        dcs_adjoint_point<int32_t>(E, gSm, gE, (int32_t)Tg, (int32_t)ILg, (int32_t)XLg, st, (int32_t)j);
+    else
+        dcs_adjoint_point<int64_t>(E, gSm, gE, Tg, ILg, XLg, st, j);
 }
 
 sal_status launch_dcs_adjoint(const float* E, const float* gSm, float* gE, int64_t Tg, int64_t ILg, int64_t XLg,

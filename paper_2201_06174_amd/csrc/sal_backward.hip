@@ -33,6 +33,10 @@ __device__ __forceinline__ f4 mfma4b(float a, float b, f4 c) {
 }
 
 __device__ __forceinline__ void lds_fence() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+// Keeps the compiler from moving LDS accesses across this point.  The LDS itself executes a
+// wave's accesses in issue order, so a read issued after another lane's write of the same
+// wave sees that write without waiting for it first.
+__device__ __forceinline__ void lds_order() { asm volatile("" ::: "memory"); }
 
 constexpr int kAdjCT = 8;  // t-centres per adjoint tile (one per wave in the t-slot loops)
 
@@ -59,14 +63,20 @@ struct AdjGeom {
     static constexpr int RX = 3 * S + N;
     static constexpr int RXp = RX | 1;
     static constexpr int ROWS = (RT * RI + 511) / 512;
-    static constexpr size_t lds_floats = (((size_t)RT * RI * RXp + 3) & ~(size_t)3) + 2 * (size_t)RT * RI * 4 +
-                                         2 * (size_t)N * RT * 16 +
-                                         (size_t)KH * N * 2;
+    static constexpr size_t base_floats = (((size_t)RT * RI * RXp + 3) & ~(size_t)3) + 2 * (size_t)RT * RI * 4 +
+                                          2 * (size_t)N * RT * 16 +
+                                          (size_t)KH * N * 2 + (size_t)CT * 16 * 3;
+    // SEP: the inverse pass C accumulates into a buffer of its own, so each t-centre's
+    // forward contraction, Y and inverse contraction run back to back (few live registers)
+    static constexpr bool SEP = (base_floats + 2 * (size_t)N * RT * 16) * sizeof(float) <= 160 * 1024;
+    static constexpr size_t lds_floats = base_floats + (SEP ? 2 * (size_t)N * RT * 16 : 0);
     static_assert(lds_floats * sizeof(float) <= 160 * 1024, "adjoint tile exceeds the LDS");
 };
 
+// With a separate inverse buffer two tiles share a CU (4 waves per SIMD, at most 128
+// registers each); otherwise the t-centres' Y values stay live and one tile takes the CU.
 template <int N, int S>
-__global__ __launch_bounds__(512) void k_spectral_adjoint(AdjParams p) {
+__global__ __launch_bounds__(512, (AdjGeom<N, S>::SEP ? 4 : 2)) void k_spectral_adjoint(AdjParams p) {
     using Gm = AdjGeom<N, S>;
     constexpr int CT = Gm::CT, KH = Gm::KH, NK = Gm::NK, RT = Gm::RT, RI = Gm::RI, RX = Gm::RX, RXp = Gm::RXp,
                   ROWS = Gm::ROWS;
@@ -88,6 +98,8 @@ __global__ __launch_bounds__(512) void k_spectral_adjoint(AdjParams p) {
     float* Ab = Vt + (((size_t)RT * RI * RXp + 3) & ~(size_t)3);  // [2][RT][RI][4]  forward A, then adjoint A'
     float* Gb = Ab + (size_t)2 * RT * RI * 4; // [2][N][RT][16]  forward G, then adjoint G'
     float* tab = Gb + (size_t)2 * N * RT * 16;  // [KH][N][2] h cos, -h sin
+    float* gel = tab + (size_t)KH * N * 2;        // [CT][16][3] upstream gradient of the tile's features
+    float* Gi = Gm::SEP ? gel + CT * 16 * 3 : Gb;  // [2][N][RT][16] inverse pass C output
     constexpr int abStride = RT * RI * 4;
     constexpr int gbStride = N * RT * 16;
 
@@ -104,16 +116,13 @@ __global__ __launch_bounds__(512) void k_spectral_adjoint(AdjParams p) {
 #pragma unroll
     for (int j = 0; j < 4; j++) ainvC[j] = p.inv[col * 16 + 4 * grp + j];
 
-    // upstream gradient of the features of this lane's windows (zero outside the grid)
+    // upstream gradient of the tile's features (zero outside the grid)
     const int64_t G = p.Tg * p.ILg * p.XLg;
-    float ge[CT][3];
-#pragma unroll
-    for (int tc = 0; tc < CT; tc++) {
-        const int64_t gt = tt * CT + tc, gi = ti * 4 + (col >> 2), gx = tx * 4 + (col & 3);
+    for (int e = tid; e < CT * 16 * 3; e += 512) {
+        const int m = e % 3, w = (e / 3) % 16, tc = e / 48;
+        const int64_t gt = tt * CT + tc, gi = ti * 4 + (w >> 2), gx = tx * 4 + (w & 3);
         const bool ok = gt < p.Tg && gi < p.ILg && gx < p.XLg;
-        const int64_t j = ok ? (gt * p.ILg + gi) * p.XLg + gx : 0;
-#pragma unroll
-        for (int m = 0; m < 3; m++) ge[tc][m] = ok ? p.gE[m * G + j] : 0.f;
+        gel[e] = ok ? p.gE[m * G + (gt * p.ILg + gi) * p.XLg + gx] : 0.f;
     }
 
     float acc[ROWS][RX];
@@ -182,13 +191,12 @@ __global__ __launch_bounds__(512) void k_spectral_adjoint(AdjParams p) {
         }
         __syncthreads();
         // ---- pass C, Y = c F/|F|, and the transposed pass C with overlap-add over the t-centres.
-        // One wave owns each ki slot u, so its rows of Gb are read and then rewritten by it alone.
+        // One wave owns each ki slot u, so its rows of the inverse buffer are written by it alone.
         for (int u = wave; u < N; u += 8) {
             const float4* wrow = p.wts + ((size_t)(kx * N + u) * 16 + 4 * grp);
             const float4 w0 = wrow[0], w1 = wrow[1], w2 = wrow[2], w3 = wrow[3];
-            float y[CT][8];
-#pragma unroll
-            for (int tc = 0; tc < CT; tc++) {
+            // forward contraction of t-centre tc and Y = c F/|F| as packed inverse-DFT inputs
+            auto fwd_y = [&](int tc, float (&y)[8]) {
                 f4 dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};
                 const float* gr = Gb + (u * RT + tc * S + grp) * 16 + col;
 #pragma unroll
@@ -196,6 +204,7 @@ __global__ __launch_bounds__(512) void k_spectral_adjoint(AdjParams p) {
                     dr = mfma4b(amat[ks], gr[ks * 64], dr);
                     di = mfma4b(amat[ks], gr[gbStride + ks * 64], di);
                 }
+                const float* ge = gel + (tc * 16 + col) * 3;
 #pragma unroll
                 for (int pr = 0; pr < 2; pr++) {
                     const bool sp = (grp == 0) && (pr == 0);
@@ -203,47 +212,66 @@ __global__ __launch_bounds__(512) void k_spectral_adjoint(AdjParams p) {
                     const float re1 = sp ? Ca : Ca + Sbi, im1 = sp ? Cai : Cai - Sb;
                     const float re2 = sp ? Sb : Ca - Sbi, im2 = sp ? Sbi : Cai + Sb;
                     const float4 wa = pr ? w2 : w0, wb = pr ? w3 : w1;
-                    const float c1 = fmaf(ge[tc][0], wa.x, fmaf(ge[tc][1], wa.y, ge[tc][2] * wa.z));
-                    const float c2 = fmaf(ge[tc][0], wb.x, fmaf(ge[tc][1], wb.y, ge[tc][2] * wb.z));
+                    const float c1 = fmaf(ge[0], wa.x, fmaf(ge[1], wa.y, ge[2] * wa.z));
+                    const float c2 = fmaf(ge[0], wb.x, fmaf(ge[1], wb.y, ge[2] * wb.z));
                     const float q1 = fmaf(re1, re1, im1 * im1), q2 = fmaf(re2, re2, im2 * im2);
                     const float s1 = q1 > 0.f ? c1 * __builtin_amdgcn_rsqf(q1) : 0.f;
                     const float s2 = q2 > 0.f ? c2 * __builtin_amdgcn_rsqf(q2) : 0.f;
                     const float y1r = s1 * re1, y1i = s1 * im1, y2r = s2 * re2, y2i = s2 * im2;
                     // packed inverse-DFT inputs: cos row gets Y(+q) + Y(-q), sin row i (Y(+q) - Y(-q))
-                    y[tc][4 * pr + 0] = sp ? y1r : y1r + y2r;   // real chain, cos row
-                    y[tc][4 * pr + 1] = sp ? y2r : y2i - y1i;   // real chain, sin row
-                    y[tc][4 * pr + 2] = sp ? y1i : y1i + y2i;   // imaginary chain, cos row
-                    y[tc][4 * pr + 3] = sp ? y2i : y1r - y2r;   // imaginary chain, sin row
+                    y[4 * pr + 0] = sp ? y1r : y1r + y2r;   // real chain, cos row
+                    y[4 * pr + 1] = sp ? y2r : y2i - y1i;   // real chain, sin row
+                    y[4 * pr + 2] = sp ? y1i : y1i + y2i;   // imaginary chain, cos row
+                    y[4 * pr + 3] = sp ? y2i : y1r - y2r;   // imaginary chain, sin row
                 }
-            }
-            lds_fence();
-            for (int e = lane; e < RT * 16; e += 64) {
-                Gb[u * RT * 16 + e] = 0.f;
-                Gb[gbStride + u * RT * 16 + e] = 0.f;
-            }
-            lds_fence();
-#pragma unroll
-            for (int tc = 0; tc < CT; tc++) {
+            };
+            // inverse contraction of t-centre tc, overlap-added into rows tc*S + a of slot u;
+            // the rows of slot u belong to this wave alone, whose LDS accesses run in order
+            auto inv_add = [&](int tc, const float (&y)[8]) {
                 f4 zr = {0.f, 0.f, 0.f, 0.f}, zi = {0.f, 0.f, 0.f, 0.f};
                 // K-permuted contraction: step j takes packed row 4*grp + j from this lane's registers
-                zr = mfma4b(ainvC[0], y[tc][0], zr);
-                zi = mfma4b(ainvC[0], y[tc][2], zi);
-                zr = mfma4b(ainvC[1], y[tc][1], zr);
-                zi = mfma4b(ainvC[1], y[tc][3], zi);
-                zr = mfma4b(ainvC[2], y[tc][4], zr);
-                zi = mfma4b(ainvC[2], y[tc][6], zi);
-                zr = mfma4b(ainvC[3], y[tc][5], zr);
-                zi = mfma4b(ainvC[3], y[tc][7], zi);
+                zr = mfma4b(ainvC[0], y[0], zr);
+                zi = mfma4b(ainvC[0], y[2], zi);
+                zr = mfma4b(ainvC[1], y[1], zr);
+                zi = mfma4b(ainvC[1], y[3], zi);
+                zr = mfma4b(ainvC[2], y[4], zr);
+                zi = mfma4b(ainvC[2], y[6], zi);
+                zr = mfma4b(ainvC[3], y[5], zr);
+                zi = mfma4b(ainvC[3], y[7], zi);
 #pragma unroll
                 for (int j = 0; j < 4; j++) {
                     const int a = 4 * grp + j;
                     if (a < N) {
-                        float* dst = Gb + (u * RT + tc * S + a) * 16 + col;
+                        float* dst = Gi + (u * RT + tc * S + a) * 16 + col;
                         dst[0] += zr[j];
                         dst[gbStride] += zi[j];
                     }
                 }
+                lds_order();
+            };
+            if constexpr (Gm::SEP) {
+                for (int e = lane; e < RT * 16; e += 64) {
+                    Gi[u * RT * 16 + e] = 0.f;
+                    Gi[gbStride + u * RT * 16 + e] = 0.f;
+                }
+#pragma unroll 1
+                for (int tc = 0; tc < CT; tc++) {
+                    float y[8];
+                    fwd_y(tc, y);
+                    inv_add(tc, y);
+                }
+            } else {
+                // the inverse overwrites the rows the forward reads: every t-centre's Y first
+                float y[CT][8];
+#pragma unroll
+                for (int tc = 0; tc < CT; tc++) fwd_y(tc, y[tc]);
                 lds_fence();
+                for (int e = lane; e < RT * 16; e += 64) {
+                    Gi[u * RT * 16 + e] = 0.f;
+                    Gi[gbStride + u * RT * 16 + e] = 0.f;
+                }
+#pragma unroll
+                for (int tc = 0; tc < CT; tc++) inv_add(tc, y[tc]);
             }
         }
         for (int e = tid; e < 2 * abStride; e += 512) Ab[e] = 0.f;
@@ -259,13 +287,13 @@ __global__ __launch_bounds__(512) void k_spectral_adjoint(AdjParams p) {
                     float xr, xi;
                     if (r == 0 || r == 1) {
                         const int u = r == 0 ? 0 : N / 2;
-                        xr = Gb[(u * RT + rt) * 16 + col];
-                        xi = Gb[gbStride + (u * RT + rt) * 16 + col];
+                        xr = Gi[(u * RT + rt) * 16 + col];
+                        xi = Gi[gbStride + (u * RT + rt) * 16 + col];
                     } else {
                         const int q = r >> 1;
-                        const float pr_ = Gb[(q * RT + rt) * 16 + col], pi_ = Gb[gbStride + (q * RT + rt) * 16 + col];
-                        const float mr_ = Gb[((N - q) * RT + rt) * 16 + col],
-                                    mi_ = Gb[gbStride + ((N - q) * RT + rt) * 16 + col];
+                        const float pr_ = Gi[(q * RT + rt) * 16 + col], pi_ = Gi[gbStride + (q * RT + rt) * 16 + col];
+                        const float mr_ = Gi[((N - q) * RT + rt) * 16 + col],
+                                    mi_ = Gi[gbStride + ((N - q) * RT + rt) * 16 + col];
                         if (r & 1) {  // sin row: i (G(+q) - G(-q))
                             xr = mi_ - pi_;
                             xi = pr_ - mr_;
@@ -277,7 +305,8 @@ __global__ __launch_bounds__(512) void k_spectral_adjoint(AdjParams p) {
                     zr = mfma4b(ainvB[ks], xr, zr);
                     zi = mfma4b(ainvB[ks], xi, zi);
                 }
-                // rows b = 4 grp + j of column (ilc, xc): add into il row ilc*S + b, one ilc at a time
+                // rows b = 4 grp + j of column (ilc, xc) add into il row ilc*S + b, one ilc at a
+                // time; the rows of rt belong to this wave alone, whose LDS accesses run in order
 #pragma unroll
                 for (int k = 0; k < 4; k++) {
                     if (ilc == k) {
@@ -291,7 +320,7 @@ __global__ __launch_bounds__(512) void k_spectral_adjoint(AdjParams p) {
                             }
                         }
                     }
-                    lds_fence();
+                    lds_order();
                 }
             }
         }
@@ -341,45 +370,55 @@ struct GatherParams {
     int n, s;
 };
 
-__global__ __launch_bounds__(256) void k_gather(GatherParams p) {
-    const int64_t NV = p.N3[0] * p.N3[1] * p.N3[2];
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= NV) return;
-    const int64_t c3[3] = {v / (p.N3[1] * p.N3[2]), (v / p.N3[2]) % p.N3[1], v % p.N3[2]};
-    int64_t tl[3][16];
+template <typename I>
+__device__ __forceinline__ void gather_point(const GatherParams& p, I v) {
+    const I N1 = (I)p.N3[1], N2 = (I)p.N3[2];
+    const I c3[3] = {v / (N1 * N2), (v / N2) % N1, v % N2};
+    I tl[3][16];
     int off[3][16];
     int cnt[3] = {0, 0, 0};
     const int half = p.n / 2;
     for (int a = 0; a < 3; a++) {
-        const int64_t Na = p.N3[a], pa = c3[a];
-        int64_t qs[3];
+        const I Na = (I)p.N3[a], pa = c3[a];
+        I qs[3];
         int nq = 0;
         qs[nq++] = pa;
         if (-1 - pa >= -half) qs[nq++] = -1 - pa;
         if (2 * Na - 1 - pa < Na + half) qs[nq++] = 2 * Na - 1 - pa;
-        const int64_t step = (int64_t)p.C[a] * p.s;
+        const I step = (I)p.C[a] * p.s;
         for (int k = 0; k < nq; k++) {
-            const int64_t q = qs[k] + half;  // position relative to the start of tile 0's region
-            int64_t lo = q - p.R[a] + 1;
+            const I q = qs[k] + half;  // position relative to the start of tile 0's region
+            I lo = q - p.R[a] + 1;
             lo = lo <= 0 ? 0 : (lo + step - 1) / step;
-            int64_t hi = q / step;
-            if (hi > p.tiles[a] - 1) hi = p.tiles[a] - 1;
-            for (int64_t tix = lo; tix <= hi && cnt[a] < 16; tix++) {
+            I hi = q / step;
+            if (hi > (I)p.tiles[a] - 1) hi = (I)p.tiles[a] - 1;
+            for (I tix = lo; tix <= hi && cnt[a] < 16; tix++) {
                 tl[a][cnt[a]] = tix;
                 off[a][cnt[a]] = (int)(q - tix * step);
                 cnt[a]++;
             }
         }
     }
-    const int64_t regsz = (int64_t)p.R[0] * p.R[1] * p.R[2];
+    const I regsz = (I)p.R[0] * p.R[1] * p.R[2];
+    const I T1 = (I)p.tiles[1], T2 = (I)p.tiles[2];
     float acc = 0.f;
     for (int i = 0; i < cnt[0]; i++)
         for (int j = 0; j < cnt[1]; j++)
             for (int k = 0; k < cnt[2]; k++) {
-                const int64_t tile = (tl[0][i] * p.tiles[1] + tl[1][j]) * p.tiles[2] + tl[2][k];
-                acc += p.part[tile * regsz + ((int64_t)off[0][i] * p.R[1] + off[1][j]) * p.R[2] + off[2][k]];
+                const I tile = (tl[0][i] * T1 + tl[1][j]) * T2 + tl[2][k];
+                acc += p.part[tile * regsz + ((I)off[0][i] * p.R[1] + off[1][j]) * p.R[2] + off[2][k]];
             }
     p.gV[v] = acc;
+}
+
+// 32-bit index arithmetic whenever the workspace and the volume fit it
+__global__ __launch_bounds__(256) void k_gather(GatherParams p) {
+    const int64_t NV = p.N3[0] * p.N3[1] * p.N3[2];
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= NV) return;
+    const int64_t parts = p.tiles[0] * p.tiles[1] * p.tiles[2] * (int64_t)p.R[0] * p.R[1] * p.R[2];
+    if (parts < (int64_t(1) << 31) && NV < (int64_t(1) << 31)) gather_point<int32_t>(p, (int32_t)v);
+    else gather_point<int64_t>(p, v);
 }
 
 struct AdjLayout {

@@ -7,17 +7,22 @@
 namespace sal {
 
 // S_m at grid point j of one volume (Sec. 2, Eq. 3): (1/Q) sum over in-grid neighbours.
-__device__ __forceinline__ void dcs_point(const float* __restrict__ E, float* __restrict__ S, int64_t Tg,
-                                          int64_t ILg, int64_t XLg, const DcsStencil& st, int64_t j) {
-    const int64_t G = Tg * ILg * XLg;
-    const int64_t gx = j % XLg, gi = (j / XLg) % ILg, gt = j / (XLg * ILg);
+// A point at least the stencil reach away from every border has all q neighbours in the
+// grid and skips the bounds tests (same terms, same order).
+template <typename I>
+__device__ __forceinline__ void dcs_point_t(const float* __restrict__ E, float* __restrict__ S, I Tg, I ILg, I XLg,
+                                            const DcsStencil& st, I j) {
+    const I G = Tg * ILg * XLg;
+    const I gx = j % XLg, gi = (j / XLg) % ILg, gt = j / (XLg * ILg);
+    const bool inner = gt >= st.reach[0] && gt + st.reach[0] < Tg && gi >= st.reach[1] && gi + st.reach[1] < ILg &&
+                       gx >= st.reach[2] && gx + st.reach[2] < XLg;
     float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
     const float e0 = E[j], e1 = E[G + j], e2 = E[2 * G + j];
     int Q = 0;
     for (int k = 0; k < st.q; k++) {
-        const int64_t nt = gt + st.o[k][0], ni = gi + st.o[k][1], nx = gx + st.o[k][2];
-        if (nt < 0 || nt >= Tg || ni < 0 || ni >= ILg || nx < 0 || nx >= XLg) continue;
-        const int64_t jn = (nt * ILg + ni) * XLg + nx;
+        const I nt = gt + st.o[k][0], ni = gi + st.o[k][1], nx = gx + st.o[k][2];
+        if (!inner && (nt < 0 || nt >= Tg || ni < 0 || ni >= ILg || nx < 0 || nx >= XLg)) continue;
+        const I jn = (nt * ILg + ni) * XLg + nx;
         const float w = st.w[k];
         if (st.literal) {
             acc0 += fabsf(e0 - w * E[jn]);
@@ -33,6 +38,15 @@ __device__ __forceinline__ void dcs_point(const float* __restrict__ E, float* __
     S[j] = Q ? acc0 / (float)Q : 0.f;
     S[G + j] = Q ? acc1 / (float)Q : 0.f;
     S[2 * G + j] = Q ? acc2 / (float)Q : 0.f;
+}
+
+// 32-bit index arithmetic whenever the grid's three planes fit it
+__device__ __forceinline__ void dcs_point(const float* __restrict__ E, float* __restrict__ S, int64_t Tg,
+                                          int64_t ILg, int64_t XLg, const DcsStencil& st, int64_t j) {
+    if (3 * Tg * ILg * XLg < (int64_t(1) << 31))
+        dcs_point_t<int32_t>(E, S, (int32_t)Tg, (int32_t)ILg, (int32_t)XLg, st, (int32_t)j);
+    else
+        dcs_point_t<int64_t>(E, S, Tg, ILg, XLg, st, j);
 }
 
 // One block's FP64 partial sums of u u^T, u D, D^2 and the count over the masked
