@@ -74,9 +74,15 @@ struct AdjGeom {
 };
 
 // With a separate inverse buffer two tiles share a CU (4 waves per SIMD, at most 128
-// registers each); otherwise the t-centres' Y values stay live and one tile takes the CU.
+// registers each), three for n = 8 at s <= 2 (6 waves, at most 85 registers; its LDS tile
+// is 45 KB); otherwise the t-centres' Y values stay live and one tile takes the CU.
 template <int N, int S>
-__global__ __launch_bounds__(512, (AdjGeom<N, S>::SEP ? 4 : 2)) void k_spectral_adjoint(AdjParams p) {
+constexpr int adj_waves_per_simd() {
+    return AdjGeom<N, S>::SEP ? (N <= 8 && S <= 2 ? 6 : 4) : 2;
+}
+
+template <int N, int S>
+__global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_adjoint(AdjParams p) {
     using Gm = AdjGeom<N, S>;
     constexpr int CT = Gm::CT, KH = Gm::KH, NK = Gm::NK, RT = Gm::RT, RI = Gm::RI, RX = Gm::RX, RXp = Gm::RXp,
                   ROWS = Gm::ROWS;

@@ -302,8 +302,14 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
 
 // One tile per workgroup; consecutive workgroups land on different XCDs, so
 // each XCD gets a contiguous run of tiles (neighbouring halos share its L2).
+// An n = 8 tile is small enough (about 30 KB of LDS) for two workgroups per CU when each
+// wave stays within 64 registers; the second workgroup covers the first one's barriers and
+// staging.
+template <int N>
+constexpr int fp32_waves_per_simd() { return N == 8 ? 8 : 4; }
+
 template <int N, int S, int CTW>
-__global__ __launch_bounds__(kNT) void k_project_fp32(ProjParams p) {
+__global__ __launch_bounds__(kNT, (fp32_waves_per_simd<N>())) void k_project_fp32(ProjParams p) {
     extern __shared__ float lds[];
     const int64_t per = (p.ntiles + 7) / 8;
     const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
@@ -316,7 +322,7 @@ __global__ __launch_bounds__(kNT) void k_project_fp32(ProjParams p) {
 // global tile range with a static stride (every tile is independent, so the
 // result does not depend on which workgroup computes it).
 template <int N, int S, int CTW>
-__global__ __launch_bounds__(kNT) void k_project_fp32_batch(const ProjParams* __restrict__ items,
+__global__ __launch_bounds__(kNT, (fp32_waves_per_simd<N>())) void k_project_fp32_batch(const ProjParams* __restrict__ items,
                                                             const int64_t* __restrict__ prefix, int nitems,
                                                             int64_t total) {
     extern __shared__ float lds[];
