@@ -70,6 +70,10 @@ struct AdjGeom {
     // forward contraction, Y and inverse contraction run back to back (few live registers)
     static constexpr bool SEP = (base_floats + 2 * (size_t)N * RT * 16) * sizeof(float) <= 160 * 1024;
     static constexpr size_t lds_floats = base_floats + (SEP ? 2 * (size_t)N * RT * 16 : 0);
+    // PAIR (n = 8): the 8 packed rows of an n = 8 transform fill half of a 16-row matrix
+    // operand, so pass C takes two t-centres per contraction: rows 8..15 hold the second
+    // centre's (banded, K = n + s samples; block-diagonal for the inverse)
+    static constexpr bool PAIR = N == 8 && SEP && CT % 2 == 0;
     static_assert(lds_floats * sizeof(float) <= 160 * 1024, "adjoint tile exceeds the LDS");
 };
 
@@ -121,6 +125,16 @@ __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_
     }
 #pragma unroll
     for (int j = 0; j < 4; j++) ainvC[j] = p.inv[col * 16 + 4 * grp + j];
+    // paired operands: forward row col of centre col >> 3 at K slot 4 ks + grp (its sample
+    // k - (col >> 3) S), inverse block-diagonal in (output centre, packed-row centre)
+    float amatP[3], ainvP[4];
+#pragma unroll
+    for (int ks = 0; ks < 3; ks++) {
+        const int a = 4 * ks + grp - (col >> 3) * S;
+        amatP[ks] = a >= 0 && a < N ? p.mat[(col & 7) * N + a] : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++) ainvP[j] = (col >> 3) == (grp >> 1) ? p.inv[(col & 7) * 16 + ((4 * grp + j) & 7)] : 0.f;
 
     // upstream gradient of the tile's features (zero outside the grid)
     const int64_t G = p.Tg * p.ILg * p.XLg;
@@ -255,7 +269,70 @@ __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_
                 }
                 lds_order();
             };
-            if constexpr (Gm::SEP) {
+            if constexpr (Gm::PAIR) {
+                for (int e = lane; e < RT * 16; e += 64) {
+                    Gi[u * RT * 16 + e] = 0.f;
+                    Gi[gbStride + u * RT * 16 + e] = 0.f;
+                }
+                // a lane's rows belong to centre tc0 + (grp >> 1), packed rows 4 (grp & 1) + j
+                const float4* wp = p.wts + ((size_t)(kx * N + u) * 16 + 4 * (grp & 1));
+                const float4 v0 = wp[0], v1 = wp[1], v2 = wp[2], v3 = wp[3];
+#pragma unroll 1
+                for (int tc0 = 0; tc0 < CT; tc0 += 2) {
+                    f4 dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};
+                    // samples tc0*S + k, k < 12 (past the last row only zero coefficients meet
+                    // the finite LDS that follows)
+                    const float* gr = Gb + (u * RT + tc0 * S + grp) * 16 + col;
+#pragma unroll
+                    for (int ks = 0; ks < 3; ks++) {
+                        dr = mfma4b(amatP[ks], gr[ks * 64], dr);
+                        di = mfma4b(amatP[ks], gr[gbStride + ks * 64], di);
+                    }
+                    const float* ge = gel + ((tc0 + (grp >> 1)) * 16 + col) * 3;
+                    float y[8];
+#pragma unroll
+                    for (int pr = 0; pr < 2; pr++) {
+                        const bool sp = ((grp & 1) == 0) && (pr == 0);
+                        const float Ca = dr[2 * pr], Sb = dr[2 * pr + 1], Cai = di[2 * pr], Sbi = di[2 * pr + 1];
+                        const float re1 = sp ? Ca : Ca + Sbi, im1 = sp ? Cai : Cai - Sb;
+                        const float re2 = sp ? Sb : Ca - Sbi, im2 = sp ? Sbi : Cai + Sb;
+                        const float4 wa = pr ? v2 : v0, wb = pr ? v3 : v1;
+                        const float c1 = fmaf(ge[0], wa.x, fmaf(ge[1], wa.y, ge[2] * wa.z));
+                        const float c2 = fmaf(ge[0], wb.x, fmaf(ge[1], wb.y, ge[2] * wb.z));
+                        const float q1 = fmaf(re1, re1, im1 * im1), q2 = fmaf(re2, re2, im2 * im2);
+                        const float s1 = q1 > 0.f ? c1 * __builtin_amdgcn_rsqf(q1) : 0.f;
+                        const float s2 = q2 > 0.f ? c2 * __builtin_amdgcn_rsqf(q2) : 0.f;
+                        const float y1r = s1 * re1, y1i = s1 * im1, y2r = s2 * re2, y2i = s2 * im2;
+                        y[4 * pr + 0] = sp ? y1r : y1r + y2r;
+                        y[4 * pr + 1] = sp ? y2r : y2i - y1i;
+                        y[4 * pr + 2] = sp ? y1i : y1i + y2i;
+                        y[4 * pr + 3] = sp ? y2i : y1r - y2r;
+                    }
+                    f4 zr = {0.f, 0.f, 0.f, 0.f}, zi = {0.f, 0.f, 0.f, 0.f};
+                    zr = mfma4b(ainvP[0], y[0], zr);
+                    zi = mfma4b(ainvP[0], y[2], zi);
+                    zr = mfma4b(ainvP[1], y[1], zr);
+                    zi = mfma4b(ainvP[1], y[3], zi);
+                    zr = mfma4b(ainvP[2], y[4], zr);
+                    zi = mfma4b(ainvP[2], y[6], zi);
+                    zr = mfma4b(ainvP[3], y[5], zr);
+                    zi = mfma4b(ainvP[3], y[7], zi);
+                    // output rows 4 grp + j: sample (4 grp + j) & 7 of centre tc0 + (grp >> 1); the
+                    // two centres' rows overlap, so they are added one centre after the other
+#pragma unroll
+                    for (int blk = 0; blk < 2; blk++) {
+                        if ((grp >> 1) == blk) {
+#pragma unroll
+                            for (int j = 0; j < 4; j++) {
+                                float* dst = Gi + (u * RT + (tc0 + blk) * S + 4 * (grp & 1) + j) * 16 + col;
+                                dst[0] += zr[j];
+                                dst[gbStride] += zi[j];
+                            }
+                        }
+                        lds_order();
+                    }
+                }
+            } else if constexpr (Gm::SEP) {
                 for (int e = lane; e < RT * 16; e += 64) {
                     Gi[u * RT * 16 + e] = 0.f;
                     Gi[gbStride + u * RT * 16 + e] = 0.f;
