@@ -92,6 +92,16 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
     float amat[NK];
 #pragma unroll
     for (int ks = 0; ks < NK; ks++) amat[ks] = p.mat[col * N + 4 * ks + grp];
+    // PAIR (n = 8): the 8 packed rows fill half of the 16-row operand, so pass C stacks two
+    // t-centres: row col of centre col >> 3 at K slot 4 ks + grp (its sample k - (col >> 3) s);
+    // 12 samples in 3 K steps instead of 2 x 2
+    constexpr bool PAIR = N == 8 && CTW == 1;
+    float amatP[3];
+#pragma unroll
+    for (int ks = 0; ks < 3; ks++) {
+        const int a = 4 * ks + grp - (col >> 3) * s;
+        amatP[ks] = PAIR && a >= 0 && a < N ? p.mat[(col & 7) * N + a] : 0.f;
+    }
 
     // pass C work of this wave: t-centres wave%8 (+8c), ki slots of one half
     const int wtc = wave & 7;
@@ -203,6 +213,61 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
         // The contraction of slot u+1 is issued before the epilogue of slot u, so the
         // matrix cores and the VALU work on different slots at the same time.  The two
         // wave halves split the ki slots to visit, [0, n) or [0, n/2] on a mirror plane.
+        if constexpr (PAIR) {
+            // wave: centre pair wave & 3 (lanes grp >> 1 pick the centre), ki slots
+            // [2q, 2q + 2) of quarter q = wave >> 2, cut to [0, n/2] on a mirror plane
+            const int tc0 = 2 * (wave & 3), ua = 2 * (wave >> 2);
+            const int nu = mirror ? N / 2 + 1 : N;
+            const int cnt = nu - ua >= 2 ? 2 : (nu - ua > 0 ? nu - ua : 0);
+            // samples tc0*s + k, k < 12; past the tile's last row only zero coefficients meet
+            // the finite LDS that follows
+            const float* gbase = Gb + (tc0 * s + grp) * 16 + col;
+            auto contractP = [&](int u, f4& dr, f4& di) {
+                const float* gr = gbase + u * RT * 16;
+                float br[3], bi[3];
+#pragma unroll
+                for (int ks = 0; ks < 3; ks++) {
+                    br[ks] = gr[ks * 64];
+                    bi[ks] = gr[gbStride + ks * 64];
+                }
+                dr = f4{0.f, 0.f, 0.f, 0.f};
+                di = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < 3; ks++) {
+                    dr = mfma4(amatP[ks], br[ks], dr);
+                    di = mfma4(amatP[ks], bi[ks], di);
+                }
+            };
+            auto epilogue = [&](int u, const f4& dr, const f4& di) {
+                const float4* wrow = Wl + u * 16 + 4 * (grp & 1);
+                const float4 w0 = wrow[0], w1 = wrow[1], w2 = wrow[2], w3 = wrow[3];
+#pragma unroll
+                for (int pr = 0; pr < 2; pr++) {
+                    const bool sp = ((grp & 1) == 0) && (pr == 0);
+                    const float Ca = dr[2 * pr], Sb = dr[2 * pr + 1], Cai = di[2 * pr], Sbi = di[2 * pr + 1];
+                    const float re1 = sp ? Ca : Ca + Sbi, im1 = sp ? Cai : Cai - Sb;
+                    const float re2 = sp ? Sb : Ca - Sbi, im2 = sp ? Sbi : Cai + Sb;
+                    const float m1 = __builtin_amdgcn_sqrtf(fmaf(re1, re1, im1 * im1));
+                    const float m2 = __builtin_amdgcn_sqrtf(fmaf(re2, re2, im2 * im2));
+                    const float4 wa = pr ? w2 : w0, wb = pr ? w3 : w1;
+                    acc[0][0] = fmaf(wa.x, m1, fmaf(wb.x, m2, acc[0][0]));
+                    acc[0][1] = fmaf(wa.y, m1, fmaf(wb.y, m2, acc[0][1]));
+                    acc[0][2] = fmaf(wa.z, m1, fmaf(wb.z, m2, acc[0][2]));
+                }
+            };
+            if (cnt == 2) {
+                f4 d0r, d0i, d1r, d1i;
+                contractP(ua, d0r, d0i);
+                contractP(ua + 1, d1r, d1i);
+                epilogue(ua, d0r, d0i);
+                epilogue(ua + 1, d1r, d1i);
+            } else if (cnt == 1) {
+                f4 d0r, d0i;
+                contractP(ua, d0r, d0i);
+                epilogue(ua, d0r, d0i);
+            }
+            continue;
+        }
         const int ua = (wave >> 3) ? (mirror ? (N / 2 + 2) / 2 : UH) : 0;
 #pragma unroll
         for (int c = 0; c < CTW; c++) {
@@ -264,6 +329,37 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
         // the next pass A writes only Ab, whose readers (pass B) all passed the barrier above
     }
 
+    const int64_t G = p.Tg * p.ILg * p.XLg;
+    if constexpr (PAIR) {
+        // lane groups 0|1 and 2|3 hold the two centres of a pair; the four ki quarters
+        // (waves w, w + 4, w + 8, w + 12) are summed through LDS in a fixed order
+        __syncthreads();
+        float* red = Gb;  // [3 quarters][4 pairs][2 centres][16][3]
+        const int tp = wave & 3, q = wave >> 2, blk = grp >> 1;
+        float v[3];
+#pragma unroll
+        for (int m = 0; m < 3; m++) v[m] = acc[0][m] + __shfl_xor(acc[0][m], 16);
+        if (q > 0 && (grp & 1) == 0) {
+#pragma unroll
+            for (int m = 0; m < 3; m++) red[((((q - 1) * 4 + tp) * 2 + blk) * 16 + col) * 3 + m] = v[m];
+        }
+        __syncthreads();
+        if (q == 0 && (grp & 1) == 0) {
+            const int tc = 2 * tp + blk;
+            const int64_t gt = tt * CT + tc, gi = ti * 4 + (col >> 2), gx = tx * 4 + (col & 3);
+            if (tc < CT && gt < p.Tg && gi < p.ILg && gx < p.XLg) {
+                const int64_t j = (gt * p.ILg + gi) * p.XLg + gx;
+#pragma unroll
+                for (int m = 0; m < 3; m++) {
+                    float x = v[m];
+#pragma unroll
+                    for (int qq = 0; qq < 3; qq++) x += red[(((qq * 4 + tp) * 2 + blk) * 16 + col) * 3 + m];
+                    p.E[m * G + j] = x;
+                }
+            }
+        }
+        return;
+    }
     // reduce the lane groups holding partial sums of the same window, then the two
     // halves of the ki slots (waves w and w + 8) through LDS
     __syncthreads();  // every wave is done with Gb; reuse it for the partial sums
@@ -285,7 +381,6 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
             for (int m = 0; m < 3; m++) red[((c * 8 + wtc) * 16 + col) * 3 + m] = v[c][m];
     }
     __syncthreads();
-    const int64_t G = p.Tg * p.ILg * p.XLg;
     if (wave < 8 && grp == 0) {
 #pragma unroll
         for (int c = 0; c < CTW; c++) {
