@@ -74,6 +74,9 @@ struct AdjGeom {
     // operand, so pass C takes two t-centres per contraction: rows 8..15 hold the second
     // centre's (banded, K = n + s samples; block-diagonal for the inverse)
     static constexpr bool PAIR = N == 8 && SEP && CT % 2 == 0;
+    // BANDB (n = 8, RI <= 16): the transposed pass B is one banded contraction per four t
+    // rows, with the il rows of a whole tile as the 16 matrix rows
+    static constexpr bool BANDB = PAIR && RI <= 16;
     static_assert(lds_floats * sizeof(float) <= 160 * 1024, "adjoint tile exceeds the LDS");
 };
 
@@ -127,6 +130,14 @@ __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_
     for (int j = 0; j < 4; j++) ainvC[j] = p.inv[col * 16 + 4 * grp + j];
     // paired operands: forward row col of centre col >> 3 at K slot 4 ks + grp (its sample
     // k - (col >> 3) S), inverse block-diagonal in (output centre, packed-row centre)
+    // banded transposed pass B: row il, K slot 4 k + grp = (il-centre (4k+grp) >> 3, packed row
+    // (4k+grp) & 7), the adjoint coefficient of sample il - centre*S
+    float abandB[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        const int K = 4 * k + grp, a = col - (K >> 3) * S;
+        abandB[k] = Gm::BANDB && a >= 0 && a < N ? p.inv[a * 16 + (K & 7)] : 0.f;
+    }
     float amatP[3], ainvP[4];
 #pragma unroll
     for (int ks = 0; ks < 3; ks++) {
@@ -357,10 +368,46 @@ __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_
                 for (int tc = 0; tc < CT; tc++) inv_add(tc, y[tc]);
             }
         }
-        for (int e = tid; e < 2 * abStride; e += 512) Ab[e] = 0.f;
+        if constexpr (!Gm::BANDB)
+            for (int e = tid; e < 2 * abStride; e += 512) Ab[e] = 0.f;
         __syncthreads();
-        // ---- transposed pass B (ki -> il samples) with overlap-add over the il-centres
-        {
+        // packed inverse-DFT input of row r (0: ki 0, 1: ki n/2, 2q: cos q, 2q+1: sin q) for t row
+        // rt and window column cw, real (ch 0) or imaginary (ch 1) channel
+        auto packed_x = [&](int r, int rt, int cw, int ch) {
+            if (r == 0 || r == 1) {
+                const int u = r == 0 ? 0 : N / 2;
+                return Gi[ch * gbStride + (u * RT + rt) * 16 + cw];
+            }
+            const int q = r >> 1;
+            const float pr_ = Gi[(q * RT + rt) * 16 + cw], pi_ = Gi[gbStride + (q * RT + rt) * 16 + cw];
+            const float mr_ = Gi[((N - q) * RT + rt) * 16 + cw], mi_ = Gi[gbStride + ((N - q) * RT + rt) * 16 + cw];
+            if (r & 1) return ch ? pr_ - mr_ : mi_ - pi_;  // sin row: i (G(+q) - G(-q))
+            return ch ? pi_ + mi_ : pr_ + mr_;
+        };
+        if constexpr (Gm::BANDB) {
+            // ---- transposed pass B as one banded contraction per (4 t rows, channel): output
+            // rows il, columns (t row, xc), K = (il-centre, packed row); the overlap-add over the
+            // il-centres happens inside the contraction and every output is stored once
+            const int rtp = col >> 2, xc = col & 3;
+            for (int item = wave; item < 2 * ((RT + 3) / 4); item += 8) {
+                const int ch = item & 1, rt = 4 * (item >> 1) + rtp;
+                f4 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int k = 0; k < 8; k++) {
+                    const int K = 4 * k + grp;
+                    const float x = rt < RT ? packed_x(K & 7, rt, (K >> 3) * 4 + xc, ch) : 0.f;
+                    z = mfma4b(abandB[k], x, z);
+                }
+                if (rt < RT) {
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        const int il = 4 * grp + j;
+                        if (il < RI) Ab[ch * abStride + (rt * RI + il) * 4 + xc] = z[j];
+                    }
+                }
+            }
+        } else {
+            // ---- transposed pass B (ki -> il samples) with overlap-add over the il-centres
             const int ilc = col >> 2, xc = col & 3;
             for (int rt = wave; rt < RT; rt += 8) {
                 f4 zr = {0.f, 0.f, 0.f, 0.f}, zi = {0.f, 0.f, 0.f, 0.f};
