@@ -69,7 +69,7 @@ struct AdjGeom {
     // SEP: the inverse pass C accumulates into a buffer of its own, so each t-centre's
     // forward contraction, Y and inverse contraction run back to back (few live registers)
     static constexpr bool SEP = (base_floats + 2 * (size_t)N * RT * 16) * sizeof(float) <= 160 * 1024;
-    static constexpr size_t lds_floats = base_floats + (SEP ? 2 * (size_t)N * RT * 16 : 0);
+    static constexpr size_t lds_floats = base_floats + (SEP ? 2 * (size_t)N * RT * 16 : 0) + (N == 8 ? CT / 2 * 4 * 64 + 8 * 64 : 0);
     // PAIR (n = 8): the 8 packed rows of an n = 8 transform fill half of a 16-row matrix
     // operand, so pass C takes two t-centres per contraction: rows 8..15 hold the second
     // centre's (banded, K = n + s samples; block-diagonal for the inverse)
@@ -77,6 +77,10 @@ struct AdjGeom {
     // BANDB (n = 8, RI <= 16): the transposed pass B is one banded contraction per four t
     // rows, with the il rows of a whole tile as the 16 matrix rows
     static constexpr bool BANDB = PAIR && RI <= 16;
+    // BANDC (n = 8, RT <= 16): the inverse t-DFT of all t-centres of a ki slot accumulates in
+    // one 16-row register tile (banded operand over K = (centre, packed row), 16 per-lane
+    // values per centre pair kept in LDS), stored once
+    static constexpr bool BANDC = PAIR && RT <= 16;
     static_assert(lds_floats * sizeof(float) <= 160 * 1024, "adjoint tile exceeds the LDS");
 };
 
@@ -113,12 +117,32 @@ __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_
     float* tab = Gb + (size_t)2 * N * RT * 16;  // [KH][N][2] h cos, -h sin
     float* gel = tab + (size_t)KH * N * 2;        // [CT][16][3] upstream gradient of the tile's features
     float* Gi = Gm::SEP ? gel + CT * 16 * 3 : Gb;  // [2][N][RT][16] inverse pass C output
+    float* atab = Gi + (Gm::SEP ? 2 * N * RT * 16 : 0);  // [CT/2][4][64] banded inverse t operand (n = 8)
+    float* btab = atab + (N == 8 ? CT / 2 * 4 * 64 : 0);  // [8][64] banded inverse il operand (n = 8)
     constexpr int abStride = RT * RI * 4;
     constexpr int gbStride = N * RT * 16;
 
     const int64_t t0 = tt * CT * S - N / 2, i0 = ti * 4 * S - N / 2, x0 = tx * 4 * S - N / 2;
     stage_tile<512>(p.V, p.T, p.IL, p.XL, t0, i0, x0, RT, RI, RX, RXp, Vt);
     for (int e = tid; e < KH * N * 2; e += 512) tab[e] = p.passA[e];
+    if constexpr (Gm::BANDB) {
+        // banded transposed pass B: lane l at step k has row il = l & 15 and K slot
+        // 4 k + (l >> 4) = (il-centre K >> 3, packed row K & 7): the adjoint coefficient of
+        // sample il - centre*S
+        for (int e = tid; e < 8 * 64; e += 512) {
+            const int l = e & 63, k = e >> 6, K = 4 * k + (l >> 4), a = (l & 15) - (K >> 3) * S;
+            btab[e] = a >= 0 && a < N ? p.inv[a * 16 + (K & 7)] : 0.f;
+        }
+    }
+    if constexpr (Gm::BANDC) {
+        // lane l at step (pair pp, j): row t = l & 15, K slot l >> 4 = (centre 2 pp + (l >> 5),
+        // packed row 4 ((l >> 4) & 1) + j)
+        for (int e = tid; e < CT / 2 * 4 * 64; e += 512) {
+            const int l = e & 63, j = (e >> 6) & 3, pp = e >> 8;
+            const int a = (l & 15) - (2 * pp + (l >> 5)) * S;
+            atab[e] = a >= 0 && a < N ? p.inv[a * 16 + 4 * ((l >> 4) & 1) + j] : 0.f;
+        }
+    }
 
     float amat[NK], ainvB[NK], ainvC[4];
 #pragma unroll
@@ -130,14 +154,6 @@ __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_
     for (int j = 0; j < 4; j++) ainvC[j] = p.inv[col * 16 + 4 * grp + j];
     // paired operands: forward row col of centre col >> 3 at K slot 4 ks + grp (its sample
     // k - (col >> 3) S), inverse block-diagonal in (output centre, packed-row centre)
-    // banded transposed pass B: row il, K slot 4 k + grp = (il-centre (4k+grp) >> 3, packed row
-    // (4k+grp) & 7), the adjoint coefficient of sample il - centre*S
-    float abandB[8];
-#pragma unroll
-    for (int k = 0; k < 8; k++) {
-        const int K = 4 * k + grp, a = col - (K >> 3) * S;
-        abandB[k] = Gm::BANDB && a >= 0 && a < N ? p.inv[a * 16 + (K & 7)] : 0.f;
-    }
     float amatP[3], ainvP[4];
 #pragma unroll
     for (int ks = 0; ks < 3; ks++) {
@@ -281,10 +297,12 @@ __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_
                 lds_order();
             };
             if constexpr (Gm::PAIR) {
-                for (int e = lane; e < RT * 16; e += 64) {
-                    Gi[u * RT * 16 + e] = 0.f;
-                    Gi[gbStride + u * RT * 16 + e] = 0.f;
-                }
+                if constexpr (!Gm::BANDC)
+                    for (int e = lane; e < RT * 16; e += 64) {
+                        Gi[u * RT * 16 + e] = 0.f;
+                        Gi[gbStride + u * RT * 16 + e] = 0.f;
+                    }
+                f4 Zr = {0.f, 0.f, 0.f, 0.f}, Zi = {0.f, 0.f, 0.f, 0.f};  // banded: rows t of slot u
                 // a lane's rows belong to centre tc0 + (grp >> 1), packed rows 4 (grp & 1) + j
                 const float4* wp = p.wts + ((size_t)(kx * N + u) * 16 + 4 * (grp & 1));
                 const float4 v0 = wp[0], v1 = wp[1], v2 = wp[2], v3 = wp[3];
@@ -319,6 +337,18 @@ __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_
                         y[4 * pr + 2] = sp ? y1i : y1i + y2i;
                         y[4 * pr + 3] = sp ? y2i : y1r - y2r;
                     }
+                    if constexpr (Gm::BANDC) {
+                        const float* at = atab + (tc0 >> 1) * 256 + lane;
+                        Zr = mfma4b(at[0], y[0], Zr);
+                        Zi = mfma4b(at[0], y[2], Zi);
+                        Zr = mfma4b(at[64], y[1], Zr);
+                        Zi = mfma4b(at[64], y[3], Zi);
+                        Zr = mfma4b(at[128], y[4], Zr);
+                        Zi = mfma4b(at[128], y[6], Zi);
+                        Zr = mfma4b(at[192], y[5], Zr);
+                        Zi = mfma4b(at[192], y[7], Zi);
+                        continue;
+                    }
                     f4 zr = {0.f, 0.f, 0.f, 0.f}, zi = {0.f, 0.f, 0.f, 0.f};
                     zr = mfma4b(ainvP[0], y[0], zr);
                     zi = mfma4b(ainvP[0], y[2], zi);
@@ -341,6 +371,16 @@ __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_
                             }
                         }
                         lds_order();
+                    }
+                }
+                if constexpr (Gm::BANDC) {
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        const int t = 4 * grp + j;
+                        if (t < RT) {
+                            Gi[(u * RT + t) * 16 + col] = Zr[j];
+                            Gi[gbStride + (u * RT + t) * 16 + col] = Zi[j];
+                        }
                     }
                 }
             } else if constexpr (Gm::SEP) {
@@ -396,7 +436,7 @@ __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_
                 for (int k = 0; k < 8; k++) {
                     const int K = 4 * k + grp;
                     const float x = rt < RT ? packed_x(K & 7, rt, (K >> 3) * 4 + xc, ch) : 0.f;
-                    z = mfma4b(abandB[k], x, z);
+                    z = mfma4b(btab[k * 64 + lane], x, z);
                 }
                 if (rt < RT) {
 #pragma unroll
