@@ -50,7 +50,7 @@ struct AdjParams {
     const float* mat;
     const float* inv;
     const float4* wts;
-    float* part;  // [ntiles][RT][RI][RX]
+    float* part;  // [tilesT][tilesI][RT][RI][tilesX][RX]: each region row next to its xl neighbours'
 };
 
 template <int N, int S>
@@ -521,10 +521,11 @@ __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_
         }
     }
     __syncthreads();
-    float* out = p.part + tile * (int64_t)(RT * RI * RX);
+    // region row r = (rt, ri) of this tile goes next to the same row of its xl neighbours
+    float* out = p.part + ((tt * p.tilesI + ti) * (int64_t)(RT * RI) * p.tilesX + tx) * RX;
     for (int e = tid; e < RT * RI * RX; e += 512) {
         const int rx = e % RX, r = e / RX;
-        out[e] = Vt[r * RXp + rx];
+        out[(int64_t)r * p.tilesX * RX + rx] = Vt[r * RXp + rx];
     }
 }
 
@@ -569,15 +570,14 @@ __device__ __forceinline__ void gather_point(const GatherParams& p, I v) {
             }
         }
     }
-    const I regsz = (I)p.R[0] * p.R[1] * p.R[2];
+    // workspace [tilesT][tilesI][R0][R1][tilesX][R2]
     const I T1 = (I)p.tiles[1], T2 = (I)p.tiles[2];
     float acc = 0.f;
     for (int i = 0; i < cnt[0]; i++)
-        for (int j = 0; j < cnt[1]; j++)
-            for (int k = 0; k < cnt[2]; k++) {
-                const I tile = (tl[0][i] * T1 + tl[1][j]) * T2 + tl[2][k];
-                acc += p.part[tile * regsz + ((I)off[0][i] * p.R[1] + off[1][j]) * p.R[2] + off[2][k]];
-            }
+        for (int j = 0; j < cnt[1]; j++) {
+            const I row = ((tl[0][i] * T1 + tl[1][j]) * p.R[0] + off[0][i]) * p.R[1] + off[1][j];
+            for (int k = 0; k < cnt[2]; k++) acc += p.part[(row * T2 + tl[2][k]) * p.R[2] + off[2][k]];
+        }
     p.gV[v] = acc;
 }
 
