@@ -77,6 +77,19 @@ def test_plan_autotune_and_direct_launch(torch_sal):
     direct.close()
 
 
+def test_plan_autotune_reduced_precision(torch_sal):
+    """Autotuning times every candidate tile depth, so the reduced-precision kernels also
+    run with tiles shallower than the full depth; the tuned plan still equals the single calls."""
+    torch, sal = torch_sal
+    members = _members(torch, sal, 6, precision="split_bf16")
+    plan = sal.Plan(members, autotune=True)
+    print(plan.describe())
+    plan.launch()
+    torch.cuda.synchronize()
+    _same_as_single(torch, sal, plan, members)
+    plan.close()
+
+
 @pytest.mark.parametrize("precision", ["split_bf16", "fp16"])
 def test_plan_reduced_precision(torch_sal, precision):
     torch, sal = torch_sal
