@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--part", choices=["fwd_bwd", "batch"], default=None,
+                    help="time only the forward + adjoint on the gradient workload, or only the batch, "
+                         "and print that object (the commands profiled for those parts)")
     ap.add_argument("--traffic-pass", action="store_true",
                     help="launch a %d-byte device copy, then the feature kernel twice, and exit "
                          "(the command profiled with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)" % COPY_BYTES)
@@ -288,6 +291,12 @@ def main():
     from paper_2201_06174_amd import _lib, synth
     lib = _lib.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.part == "fwd_bwd":
+        print(json.dumps(time_fwd_bwd(torch, "grad", max(args.steps, 1), args.warmup)), flush=True)
+        return
+    if args.part == "batch":
+        print(json.dumps(time_batch(torch, lib, max(args.steps, 1))), flush=True)
+        return
     w = synth.workload(args.workload)
     V, M = synth.make_volume(w.spec, w.seed, with_mask=True)
     D, mask = synth.desired_map(M, w.s)
