@@ -219,6 +219,7 @@ __global__ __launch_bounds__(64) void k_fuse_solve(const double* __restrict__ pa
 __global__ __launch_bounds__(256) void k_combine(const float* __restrict__ Sm, const double* __restrict__ W,
                                                  int64_t Tg, int64_t ILg, int64_t XLg, int64_t T, int64_t IL,
                                                  int64_t XL, int s, float* __restrict__ S) {
+    (void)T;  // one block per (t, il) row: the grid carries T
     combine_row(Sm, W, Tg, ILg, XLg, IL, XL, s, (int64_t)blockIdx.x, S);
 }
 

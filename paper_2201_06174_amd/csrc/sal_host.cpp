@@ -222,7 +222,7 @@ sal_status get_tables(int n, int window, const Tables** out) {
     dt.t.cpx_h16 = (const uint16_t*)put(ch16.data(), ch16.size() * 2);
     if (!dt.t.passA || !dt.t.mat || !dt.t.wts || !dt.t.inv || !dt.t.wts_nat || !dt.t.wts_nat_h || !dt.t.cpx_hi ||
         !dt.t.cpx_lo || !dt.t.cpx_h16) {
-        hipFree(base);
+        (void)hipFree(base);  // already failing; the upload error is the one reported
         return fail(SAL_ERR_DEVICE, "uploading constant tables failed");
     }
     auto res = g_tables.emplace(key, dt);
@@ -263,7 +263,7 @@ sal_status get_pass_a_ops(int n, int s, int window, const uint16_t** out) {
     void* d = nullptr;
     if ((st = check_hip(hipMalloc(&d, ops.size() * 2), "hipMalloc(pass A operands)"))) return st;
     if ((st = check_hip(hipMemcpy(d, ops.data(), ops.size() * 2, hipMemcpyHostToDevice), "hipMemcpy(pass A operands)"))) {
-        hipFree(d);
+        (void)hipFree(d);  // already failing; the copy error is the one reported
         return st;
     }
     g_pa_ops.emplace(key, d);

@@ -182,12 +182,12 @@ sal_status autotune_class(sal_plan* plan, Class& c) {
         if ((st = launch_class(plan, c, s))) break;  // warm-up
         float ms = 1e30f;
         for (int r = 0; !st && r < 3; r++) {
-            hipEventRecord(e0, s);
-            st = launch_class(plan, c, s);
-            hipEventRecord(e1, s);
+            st = check_hip(hipEventRecord(e0, s), "hipEventRecord");
+            if (!st) st = launch_class(plan, c, s);
+            if (!st) st = check_hip(hipEventRecord(e1, s), "hipEventRecord");
             if (!st) st = check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
             float t = 0.f;
-            if (!st) hipEventElapsedTime(&t, e0, e1);
+            if (!st) st = check_hip(hipEventElapsedTime(&t, e0, e1), "hipEventElapsedTime");
             ms = std::min(ms, t);
         }
         snprintf(buf, sizeof(buf), "%sCT=%d:%.3fms", k ? " " : "", CT, ms);
@@ -197,9 +197,10 @@ sal_status autotune_class(sal_plan* plan, Class& c) {
             best_ct = CT;
         }
     }
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
-    if (s) hipStreamDestroy(s);
+    // cleanup of the tuning stream and events; their status does not change the tuning result
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
     if (st) return st;
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
@@ -208,12 +209,14 @@ sal_status autotune_class(sal_plan* plan, Class& c) {
     return build_class_params(plan, c, best_ct);
 }
 
+// Releases everything a plan owns.  A failing release cannot be acted on (the plan is gone
+// either way), so its status is dropped.
 void destroy(sal_plan* plan) {
     if (!plan) return;
-    if (plan->exec) hipGraphExecDestroy(plan->exec);
-    if (plan->graph) hipGraphDestroy(plan->graph);
-    if (plan->cap) hipStreamDestroy(plan->cap);
-    if (plan->dev) hipFree(plan->dev);
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    if (plan->cap) (void)hipStreamDestroy(plan->cap);
+    if (plan->dev) (void)hipFree(plan->dev);
     delete plan;
 }
 
