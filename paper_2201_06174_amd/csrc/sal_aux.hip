@@ -215,7 +215,40 @@ __global__ __launch_bounds__(64) void k_fuse_solve(const double* __restrict__ pa
     solve_weights(part, nparts, mode, w0, w1, w2, delta, W, stats_out, st);
 }
 
-// S(v) = sum_m W_m S_m(g(v)); one block per (t, il) row.
+// S(v) = sum_m W_m S_m(g(v)) (same arithmetic as combine_row): kCombineRows (t, il) rows per
+// block, each thread writing four consecutive xl samples with one 16-byte store (XL % 4 == 0
+// and a 16-byte aligned S),
+// the stride fixed at compile time (SS > 0) so the nearest-centre division is a constant one.
+constexpr int kCombineRows = 4;
+
+template <int SS>
+__global__ __launch_bounds__(256) void k_combine4(const float* __restrict__ Sm, const double* __restrict__ W,
+                                                  int64_t Tg, int64_t ILg, int64_t XLg, int64_t T, int64_t IL,
+                                                  int64_t XL, int s_rt, float* __restrict__ S) {
+    const int s = SS > 0 ? SS : s_rt;
+    const int64_t G = Tg * ILg * XLg;
+    const double W0 = W[0], W1 = W[1], W2 = W[2];
+    const int sh = (s - 1) / 2;
+    const int64_t q = XL / 4;
+    for (int64_t e = threadIdx.x; e < kCombineRows * q; e += blockDim.x) {
+        const int64_t row = (int64_t)blockIdx.x * kCombineRows + e / q;
+        if (row >= T * IL) break;
+        const int64_t t = row / IL, i = row % IL;
+        const int64_t base = (cell_of(t, s, Tg) * ILg + cell_of(i, s, ILg)) * XLg;
+        const int x0 = (int)(e % q) * 4;
+        float o[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            int gx = (x0 + k + sh) / s;
+            gx = gx < XLg - 1 ? gx : (int)XLg - 1;
+            const int64_t j = base + gx;
+            o[k] = (float)(W0 * (double)Sm[j] + W1 * (double)Sm[G + j] + W2 * (double)Sm[2 * G + j]);
+        }
+        *(float4*)&S[row * XL + x0] = make_float4(o[0], o[1], o[2], o[3]);
+    }
+}
+
+// S(v) = sum_m W_m S_m(g(v)); one block per (t, il) row (any XL).
 __global__ __launch_bounds__(256) void k_combine(const float* __restrict__ Sm, const double* __restrict__ W,
                                                  int64_t Tg, int64_t ILg, int64_t XLg, int64_t T, int64_t IL,
                                                  int64_t XL, int s, float* __restrict__ S) {
@@ -240,8 +273,21 @@ sal_status launch_fuse(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, co
     if (st) return st;
     if (T * IL * XL == 0) return SAL_OK;
     if (T * IL > INT32_MAX) return fail(SAL_ERR_SHAPE, "volume too large for one launch");
-    hipLaunchKernelGGL(k_combine, dim3((unsigned)(T * IL)), dim3(256), 0, stream, Sm, W, Tg, ILg, XLg, T, IL, XL, s,
-                       S);
+    if (XL % 4 == 0 && reinterpret_cast<uintptr_t>(S) % 16 == 0) {
+        const int64_t blocks = (T * IL + kCombineRows - 1) / kCombineRows;
+        if (s == 1)
+            hipLaunchKernelGGL(k_combine4<1>, dim3((unsigned)blocks), dim3(256), 0, stream, Sm, W, Tg, ILg, XLg, T, IL,
+                               XL, s, S);
+        else if (s == 2)
+            hipLaunchKernelGGL(k_combine4<2>, dim3((unsigned)blocks), dim3(256), 0, stream, Sm, W, Tg, ILg, XLg, T, IL,
+                               XL, s, S);
+        else
+            hipLaunchKernelGGL(k_combine4<0>, dim3((unsigned)blocks), dim3(256), 0, stream, Sm, W, Tg, ILg, XLg, T, IL,
+                               XL, s, S);
+    } else {
+        hipLaunchKernelGGL(k_combine, dim3((unsigned)(T * IL)), dim3(256), 0, stream, Sm, W, Tg, ILg, XLg, T, IL, XL,
+                           s, S);
+    }
     return check_hip(hipGetLastError(), "launch k_combine");
 }
 
@@ -300,12 +346,8 @@ __global__ __launch_bounds__(64) void k_gw_solve(const double* __restrict__ part
                                                  const double* __restrict__ stats, double delta,
                                                  double* __restrict__ lam) {
     __shared__ double gw[3];
-    if (threadIdx.x < 3) {
-        double s = 0.0;
-        for (int b = 0; b < nparts; b++) s += part[(int64_t)b * 3 + threadIdx.x];
-        gw[threadIdx.x] = s;
-    }
-    __syncthreads();
+    __shared__ double red[16 * 64];
+    sum_columns64(part, nparts, 3, red, gw);
     if (threadIdx.x != 0) return;
     const double A[9] = {stats[0] + delta, stats[1], stats[2], stats[1], stats[3] + delta, stats[4],
                          stats[2], stats[4], stats[5] + delta};

@@ -110,16 +110,37 @@ __device__ __forceinline__ int chol3(const double A[9], const double b[3], doubl
     return 0;
 }
 
+// Column sums of an FP64 table part[nparts][ncols] (ncols <= 16) by a block of 64 threads in a
+// fixed order (deterministic): thread t adds rows t, t + 64, ... in turn, then the 64 partial
+// sums of a column are combined by a pairwise tree.  red: 16 x 64 doubles of shared memory.
+__device__ __forceinline__ void sum_columns64(const double* __restrict__ part, int nparts, int ncols, double* red,
+                                              double* out) {
+    const int t = threadIdx.x;
+    for (int k = 0; k < ncols; k++) {
+        double s = 0.0;
+#pragma unroll 4
+        for (int b = t; b < nparts; b += 64) s += part[(int64_t)b * ncols + k];
+        red[k * 64 + t] = s;
+    }
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+        if (t < w)
+            for (int k = 0; k < ncols; k++) red[k * 64 + t] += red[k * 64 + t + w];
+        __syncthreads();
+    }
+    if (t < ncols) out[t] = red[t * 64];
+    __syncthreads();
+}
+
 // Weights of one volume from its reduced statistics (block of 64 threads): sums the
-// partials in block order, then solves; writes W[0..2] and the status word W[3].
+// partials (sum_columns64), then solves; writes W[0..2] and the status word W[3].
 __device__ __forceinline__ void solve_weights(const double* __restrict__ part, int nparts, int mode, double w0,
                                               double w1, double w2, double delta, double* __restrict__ W,
                                               double* __restrict__ stats_out, double* st) {
-    if (threadIdx.x < kStats && mode == SAL_FUSE_ADAPT_LS) {
-        double s = 0.0;
-        for (int b = 0; b < nparts; b++) s += part[(int64_t)b * kStats + threadIdx.x];
-        st[threadIdx.x] = s;
-        if (stats_out) stats_out[threadIdx.x] = s;
+    if (mode == SAL_FUSE_ADAPT_LS) {
+        __shared__ double red[16 * 64];
+        sum_columns64(part, nparts, kStats, red, st);
+        if (stats_out && threadIdx.x < kStats) stats_out[threadIdx.x] = st[threadIdx.x];
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
