@@ -55,7 +55,28 @@ sal_status make_stencil(const sal_stencil* st, int s, DcsStencil* out) {
     for (int k = st->q; k < SAL_MAX_STENCIL; k++) {
         out->o[k][0] = out->o[k][1] = out->o[k][2] = 0;
         out->w[k] = 0.f;
+        out->mirror[k] = 0;
     }
+    // one-to-one pairing of each offset with an unused copy of its negation; equal offsets
+    // are interchangeable, so the greedy pairing succeeds whenever the stencil equals its
+    // reflection as a multiset
+    bool used[SAL_MAX_STENCIL] = {};
+    out->symmetric = 1;
+    for (int k = 0; k < st->q && out->symmetric; k++) {
+        int m = -1;
+        for (int k2 = 0; k2 < st->q && m < 0; k2++)
+            if (!used[k2] && out->o[k2][0] == -out->o[k][0] && out->o[k2][1] == -out->o[k][1] &&
+                out->o[k2][2] == -out->o[k][2])
+                m = k2;
+        if (m < 0) {
+            out->symmetric = 0;
+        } else {
+            used[m] = true;
+            out->mirror[k] = m;
+        }
+    }
+    if (!out->symmetric)
+        for (int k = 0; k < st->q; k++) out->mirror[k] = 0;
     return SAL_OK;
 }
 

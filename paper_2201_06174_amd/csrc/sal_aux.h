@@ -15,8 +15,10 @@ struct DcsStencil {
     int q;
     int literal;
     int reach[3];  // largest |offset| per axis, in grid units
+    int symmetric; // every offset has its negation in the stencil: mirror[] pairs them one to one
     int o[SAL_MAX_STENCIL][3];
     float w[SAL_MAX_STENCIL];
+    int mirror[SAL_MAX_STENCIL];  // o[mirror[k]] == -o[k] (symmetric stencils only)
 };
 
 // Resolves a stencil (validation, Gaussian default weights) into grid units.
@@ -26,16 +28,20 @@ sal_status launch_local_spectra(const float* V, int64_t T, int64_t IL, int64_t X
                                 const int32_t* centers, int64_t cnt, float* F, hipStream_t stream);
 sal_status launch_dcs(const float* E, float* S, int64_t Tg, int64_t ILg, int64_t XLg, const DcsStencil& st,
                       hipStream_t stream);
-sal_status launch_dcs_adjoint(const float* E, const float* gSm, float* gE, int64_t Tg, int64_t ILg, int64_t XLg,
+// gE from E and R = gS_m / Q (the output of launch_fuse_adjoint).
+sal_status launch_dcs_adjoint(const float* E, const float* R, float* gE, int64_t Tg, int64_t ILg, int64_t XLg,
                               const DcsStencil& st, hipStream_t stream);
 size_t fuse_workspace_bytes();
 sal_status launch_fuse(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion& f, const float* D,
                        const uint8_t* mask, int64_t T, int64_t IL, int64_t XL, int s, double* W, float* S, double* ws,
                        hipStream_t stream);
 size_t fuse_adjoint_workspace_bytes();
+// Writes R_m(g) = gS_m(g) / Q(g), the fusion adjoint divided by the number Q(g) of stencil
+// neighbours of g inside the grid (0 where Q(g) = 0): the per-point factor of every term of
+// the center-surround adjoint.
 sal_status launch_fuse_adjoint(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion& f,
                                const float* D, const uint8_t* mask, const double* W, const float* gS, int64_t T,
-                               int64_t IL, int64_t XL, int s, float* cell, double* ws, float* gSm,
+                               int64_t IL, int64_t XL, int s, const DcsStencil& ds, float* cell, double* ws, float* R,
                                hipStream_t stream);
 sal_status launch_project_lowp(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s, int precision,
                                const Tables* tb, float* E, hipStream_t stream);

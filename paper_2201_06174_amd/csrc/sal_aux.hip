@@ -116,81 +116,81 @@ sal_status launch_dcs(const float* E, float* S, int64_t Tg, int64_t ILg, int64_t
     return check_hip(hipGetLastError(), "launch k_dcs");
 }
 
-// Adjoint of Eq. 3 as a gather: each grid point collects its own terms and the
-// terms in which it is the neighbour of g - o.  sgn(0) = 0.  Neighbour counts do not
-// depend on the plane and are found once; a point at least twice the stencil reach away
-// from every border (so its neighbours' stencils stay inside too) has all of them equal
-// to q.  The terms of each plane are summed in the same order as a per-plane loop would.
-template <typename I>
-__device__ __forceinline__ void dcs_adjoint_point(const float* __restrict__ E, const float* __restrict__ gSm,
+// Adjoint of Eq. 3 as a gather: each grid point collects its own terms and the terms in
+// which it is the neighbour of g - o, with sgn(0) = 0.  R = gS_m / Q carries the division by
+// each point's neighbour count.  For a symmetric stencil the neighbour term of the mirrored
+// offset reads the same point g + o as the own term of o, so every neighbour is read once;
+// a point at least the stencil reach away from every border skips the bounds tests.
+template <typename I, bool SYM>
+__device__ __forceinline__ void dcs_adjoint_point(const float* __restrict__ E, const float* __restrict__ R,
                                                   float* __restrict__ gE, I Tg, I ILg, I XLg, const DcsStencil& st,
                                                   I j) {
     const I G = Tg * ILg * XLg;
     const I gx = j % XLg, gi = (j / XLg) % ILg, gt = j / (XLg * ILg);
     auto inside = [&](I a, I b, I c) { return a >= 0 && a < Tg && b >= 0 && b < ILg && c >= 0 && c < XLg; };
-    auto count = [&](I a, I b, I c) {
-        int Q = 0;
-        for (int k = 0; k < st.q; k++) Q += inside(a + st.o[k][0], b + st.o[k][1], c + st.o[k][2]);
-        return Q;
-    };
-    const bool inner = gt >= 2 * st.reach[0] && gt + 2 * st.reach[0] < Tg && gi >= 2 * st.reach[1] &&
-                       gi + 2 * st.reach[1] < ILg && gx >= 2 * st.reach[2] && gx + 2 * st.reach[2] < XLg;
-    float e0[3], cg[3], acc[3] = {0.f, 0.f, 0.f};
-    const int Qg = inner ? st.q : count(gt, gi, gx);
+    auto sgn = [](float d) { return d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f); };
+    const bool inner = gt >= st.reach[0] && gt + st.reach[0] < Tg && gi >= st.reach[1] && gi + st.reach[1] < ILg &&
+                       gx >= st.reach[2] && gx + st.reach[2] < XLg;
+    // own[m] = sum_k (literal ? 1 : w_k) sgn(e0 - (literal ? w_k : 1) e_k); nbr[m] = the
+    // neighbour terms without their sign flip
+    float e0[3], own[3] = {0.f, 0.f, 0.f}, nbr[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-    for (int m = 0; m < 3; m++) {
-        e0[m] = E[m * G + j];
-        cg[m] = Qg ? gSm[m * G + j] / (float)Qg : 0.f;
-    }
-    if (Qg) {
-        for (int k = 0; k < st.q; k++) {
-            const I nt = gt + st.o[k][0], ni = gi + st.o[k][1], nx = gx + st.o[k][2];
-            if (!inner && !inside(nt, ni, nx)) continue;
-            const I jn = (nt * ILg + ni) * XLg + nx;
+    for (int m = 0; m < 3; m++) e0[m] = E[m * G + j];
+    for (int k = 0; k < st.q; k++) {
+        const I nt = gt + st.o[k][0], ni = gi + st.o[k][1], nx = gx + st.o[k][2];
+        if (!inner && !inside(nt, ni, nx)) continue;
+        const I jn = (nt * ILg + ni) * XLg + nx;
+        const float wk = st.w[k];
 #pragma unroll
-            for (int m = 0; m < 3; m++) {
-                const float e1 = E[m * G + jn];
-                const float d = st.literal ? e0[m] - st.w[k] * e1 : e0[m] - e1;
-                const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
-                acc[m] += cg[m] * (st.literal ? 1.f : st.w[k]) * sg;
+        for (int m = 0; m < 3; m++) {
+            const float e1 = E[m * G + jn];
+            own[m] += st.literal ? sgn(e0[m] - wk * e1) : wk * sgn(e0[m] - e1);
+            if (SYM) {
+                // g = (g + o_k) - o_mirror: the mirrored offset's neighbour term
+                const float wm = st.w[st.mirror[k]];
+                nbr[m] += R[m * G + jn] * wm * sgn(st.literal ? e1 - wm * e0[m] : e1 - e0[m]);
             }
         }
     }
-    for (int k = 0; k < st.q; k++) {
-        const I pt = gt - st.o[k][0], pi = gi - st.o[k][1], px = gx - st.o[k][2];
-        if (!inner && !inside(pt, pi, px)) continue;
-        const I jp = (pt * ILg + pi) * XLg + px;
-        const int Qp = inner ? st.q : count(pt, pi, px);
+    if (!SYM) {
+        for (int k = 0; k < st.q; k++) {
+            const I pt = gt - st.o[k][0], pi = gi - st.o[k][1], px = gx - st.o[k][2];
+            if (!inner && !inside(pt, pi, px)) continue;
+            const I jp = (pt * ILg + pi) * XLg + px;
+            const float wk = st.w[k];
 #pragma unroll
-        for (int m = 0; m < 3; m++) {
-            const float ep = E[m * G + jp];
-            const float d = st.literal ? ep - st.w[k] * e0[m] : ep - e0[m];
-            const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
-            acc[m] -= gSm[m * G + jp] / (float)Qp * st.w[k] * sg;
+            for (int m = 0; m < 3; m++) {
+                const float ep = E[m * G + jp];
+                nbr[m] += R[m * G + jp] * wk * sgn(st.literal ? ep - wk * e0[m] : ep - e0[m]);
+            }
         }
     }
 #pragma unroll
-    for (int m = 0; m < 3; m++) gE[m * G + j] = acc[m];
+    for (int m = 0; m < 3; m++) gE[m * G + j] = R[m * G + j] * own[m] - nbr[m];
 }
 
-__global__ __launch_bounds__(256) void k_dcs_adjoint(const float* __restrict__ E, const float* __restrict__ gSm,
+template <bool SYM>
+__global__ __launch_bounds__(256) void k_dcs_adjoint(const float* __restrict__ E, const float* __restrict__ R,
                                                      float* __restrict__ gE, int64_t Tg, int64_t ILg, int64_t XLg,
                                                      DcsStencil st) {
     const int64_t G = Tg * ILg * XLg;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= G) return;
     if (3 * G < (int64_t(1) << 31))
-        dcs_adjoint_point<int32_t>(E, gSm, gE, (int32_t)Tg, (int32_t)ILg, (int32_t)XLg, st, (int32_t)j);
+        dcs_adjoint_point<int32_t, SYM>(E, R, gE, (int32_t)Tg, (int32_t)ILg, (int32_t)XLg, st, (int32_t)j);
     else
-        dcs_adjoint_point<int64_t>(E, gSm, gE, Tg, ILg, XLg, st, j);
+        dcs_adjoint_point<int64_t, SYM>(E, R, gE, Tg, ILg, XLg, st, j);
 }
 
-sal_status launch_dcs_adjoint(const float* E, const float* gSm, float* gE, int64_t Tg, int64_t ILg, int64_t XLg,
+sal_status launch_dcs_adjoint(const float* E, const float* R, float* gE, int64_t Tg, int64_t ILg, int64_t XLg,
                               const DcsStencil& st, hipStream_t stream) {
     const int64_t G = Tg * ILg * XLg;
     if (G == 0) return SAL_OK;
-    hipLaunchKernelGGL(k_dcs_adjoint, dim3((unsigned)((G + 255) / 256)), dim3(256), 0, stream, E, gSm, gE, Tg, ILg,
-                       XLg, st);
+    const dim3 grid((unsigned)((G + 255) / 256));
+    if (st.symmetric)
+        hipLaunchKernelGGL(k_dcs_adjoint<true>, grid, dim3(256), 0, stream, E, R, gE, Tg, ILg, XLg, st);
+    else
+        hipLaunchKernelGGL(k_dcs_adjoint<false>, grid, dim3(256), 0, stream, E, R, gE, Tg, ILg, XLg, st);
     return check_hip(hipGetLastError(), "launch k_dcs_adjoint");
 }
 
@@ -356,13 +356,27 @@ __global__ __launch_bounds__(64) void k_gw_solve(const double* __restrict__ part
     lam[0] = x[0]; lam[1] = x[1]; lam[2] = x[2];
 }
 
-// gSm(g) = W_m c(g) (+ on the mask, ADAPT_LS: lambda_m (D - W.u) - W_m (lambda.u)).
+// gS_m(g) = W_m c(g) (+ on the mask, ADAPT_LS: lambda_m (D - W.u) - W_m (lambda.u)), stored
+// divided by the neighbour count Q(g).
 __global__ __launch_bounds__(256) void k_gsm(const float* __restrict__ Sm, const float* __restrict__ cell,
                                              const double* __restrict__ W, const double* __restrict__ lam,
-                                             const float* __restrict__ D, const uint8_t* __restrict__ mask, int64_t G,
-                                             int adapt, float* __restrict__ gSm) {
+                                             const float* __restrict__ D, const uint8_t* __restrict__ mask,
+                                             int64_t Tg, int64_t ILg, int64_t XLg, DcsStencil ds, int adapt,
+                                             float* __restrict__ R) {
+    const int64_t G = Tg * ILg * XLg;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= G) return;
+    // neighbours of g inside the grid (all q of them away from the borders)
+    const int64_t gx = j % XLg, gi = (j / XLg) % ILg, gt = j / (XLg * ILg);
+    int Q = ds.q;
+    if (!(gt >= ds.reach[0] && gt + ds.reach[0] < Tg && gi >= ds.reach[1] && gi + ds.reach[1] < ILg &&
+          gx >= ds.reach[2] && gx + ds.reach[2] < XLg)) {
+        Q = 0;
+        for (int k = 0; k < ds.q; k++) {
+            const int64_t a = gt + ds.o[k][0], b = gi + ds.o[k][1], c = gx + ds.o[k][2];
+            Q += a >= 0 && a < Tg && b >= 0 && b < ILg && c >= 0 && c < XLg;
+        }
+    }
     const double c = cell[j];
     double g[3] = {W[0] * c, W[1] * c, W[2] * c};
     if (adapt && W[3] == 0.0 && (!mask || mask[j])) {
@@ -371,14 +385,13 @@ __global__ __launch_bounds__(256) void k_gsm(const float* __restrict__ Sm, const
         const double lu = lam[0] * u0 + lam[1] * u1 + lam[2] * u2;
         for (int m = 0; m < 3; m++) g[m] += lam[m] * r - W[m] * lu;
     }
-    gSm[j] = (float)g[0];
-    gSm[G + j] = (float)g[1];
-    gSm[2 * G + j] = (float)g[2];
+#pragma unroll
+    for (int m = 0; m < 3; m++) R[m * G + j] = Q ? (float)g[m] / (float)Q : 0.f;
 }
 
 sal_status launch_fuse_adjoint(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion& f,
                                const float* D, const uint8_t* mask, const double* W, const float* gS, int64_t T,
-                               int64_t IL, int64_t XL, int s, float* cell, double* ws, float* gSm,
+                               int64_t IL, int64_t XL, int s, const DcsStencil& ds, float* cell, double* ws, float* R,
                                hipStream_t stream) {
     const int64_t G = Tg * ILg * XLg;
     if (G == 0) return SAL_OK;
@@ -403,7 +416,8 @@ sal_status launch_fuse_adjoint(const float* Sm, int64_t Tg, int64_t ILg, int64_t
                            f.delta, lam);
         if ((st = check_hip(hipGetLastError(), "launch k_gw_solve"))) return st;
     }
-    hipLaunchKernelGGL(k_gsm, dim3(blocks), dim3(256), 0, stream, Sm, cell, W, lam, D, mask, G, adapt, gSm);
+    hipLaunchKernelGGL(k_gsm, dim3(blocks), dim3(256), 0, stream, Sm, cell, W, lam, D, mask, Tg, ILg, XLg, ds, adapt,
+                       R);
     return check_hip(hipGetLastError(), "launch k_gsm");
 }
 

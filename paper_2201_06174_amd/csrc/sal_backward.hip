@@ -541,54 +541,77 @@ struct GatherParams {
     int n, s;
 };
 
+// Per axis, a voxel p is reached at up to three virtual positions (itself and its two
+// half-sample reflections); each lies in the regions of a contiguous range of tiles.
+// The ranges are found on the fly (no per-thread arrays, which would live in scratch) and
+// visited axis by axis in a fixed order: virtual position, then tile.
+template <typename I>
+struct GatherAxis {
+    I q[3];    // virtual positions relative to the start of tile 0's region
+    I lo[3], hi[3];
+    int nq;
+};
+
+template <typename I>
+__device__ __forceinline__ GatherAxis<I> gather_axis(I pa, I Na, int half, int R, I step, I ntiles) {
+    GatherAxis<I> g;
+    g.nq = 0;
+    g.q[0] = g.q[1] = g.q[2] = 0;
+    g.q[g.nq++] = pa + half;
+    if (-1 - pa >= -half) g.q[g.nq++] = -1 - pa + half;
+    if (Na - 1 - pa < half) g.q[g.nq++] = (Na - 1 - pa) + Na + half;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const I lo = g.q[k] - R + 1;
+        g.lo[k] = lo <= 0 ? 0 : (lo + step - 1) / step;
+        const I hi = g.q[k] / step;
+        g.hi[k] = hi > ntiles - 1 ? ntiles - 1 : hi;
+    }
+    return g;
+}
+
 template <typename I>
 __device__ __forceinline__ void gather_point(const GatherParams& p, I v) {
     const I N1 = (I)p.N3[1], N2 = (I)p.N3[2];
     const I c3[3] = {v / (N1 * N2), (v / N2) % N1, v % N2};
-    I tl[3][16];
-    int off[3][16];
-    int cnt[3] = {0, 0, 0};
     const int half = p.n / 2;
-    for (int a = 0; a < 3; a++) {
-        const I Na = (I)p.N3[a], pa = c3[a];
-        I qs[3];
-        int nq = 0;
-        qs[nq++] = pa;
-        if (-1 - pa >= -half) qs[nq++] = -1 - pa;
-        if (2 * Na - 1 - pa < Na + half) qs[nq++] = 2 * Na - 1 - pa;
-        const I step = (I)p.C[a] * p.s;
-        for (int k = 0; k < nq; k++) {
-            const I q = qs[k] + half;  // position relative to the start of tile 0's region
-            I lo = q - p.R[a] + 1;
-            lo = lo <= 0 ? 0 : (lo + step - 1) / step;
-            I hi = q / step;
-            if (hi > (I)p.tiles[a] - 1) hi = (I)p.tiles[a] - 1;
-            for (I tix = lo; tix <= hi && cnt[a] < 16; tix++) {
-                tl[a][cnt[a]] = tix;
-                off[a][cnt[a]] = (int)(q - tix * step);
-                cnt[a]++;
+    GatherAxis<I> ax[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+        ax[a] = gather_axis<I>(c3[a], (I)p.N3[a], half, p.R[a], (I)p.C[a] * p.s, (I)p.tiles[a]);
+    const I step0 = (I)p.C[0] * p.s, step1 = (I)p.C[1] * p.s, step2 = (I)p.C[2] * p.s;
+    // workspace [tilesT][tilesI][R0][R1][tilesX][R2]
+    const I T1 = (I)p.tiles[1], T2 = (I)p.tiles[2];
+    // element k of a 3-array by selects (a dynamic index would put the array in scratch)
+    auto sel = [](const I* x, int k) { return k == 0 ? x[0] : (k == 1 ? x[1] : x[2]); };
+    float acc = 0.f;
+    for (int k0 = 0; k0 < ax[0].nq; k0++) {
+        const I q0 = sel(ax[0].q, k0), hi0 = sel(ax[0].hi, k0);
+        for (I t0 = sel(ax[0].lo, k0); t0 <= hi0; t0++) {
+            const I o0 = q0 - t0 * step0;
+            for (int k1 = 0; k1 < ax[1].nq; k1++) {
+                const I q1 = sel(ax[1].q, k1), hi1 = sel(ax[1].hi, k1);
+                for (I t1 = sel(ax[1].lo, k1); t1 <= hi1; t1++) {
+                    const I row = ((t0 * T1 + t1) * p.R[0] + o0) * p.R[1] + (q1 - t1 * step1);
+                    const float* pr = p.part + row * T2 * p.R[2];
+                    for (int k2 = 0; k2 < ax[2].nq; k2++) {
+                        const I q2 = sel(ax[2].q, k2), hi2 = sel(ax[2].hi, k2);
+                        for (I t2 = sel(ax[2].lo, k2); t2 <= hi2; t2++) acc += pr[t2 * p.R[2] + (q2 - t2 * step2)];
+                    }
+                }
             }
         }
     }
-    // workspace [tilesT][tilesI][R0][R1][tilesX][R2]
-    const I T1 = (I)p.tiles[1], T2 = (I)p.tiles[2];
-    float acc = 0.f;
-    for (int i = 0; i < cnt[0]; i++)
-        for (int j = 0; j < cnt[1]; j++) {
-            const I row = ((tl[0][i] * T1 + tl[1][j]) * p.R[0] + off[0][i]) * p.R[1] + off[1][j];
-            for (int k = 0; k < cnt[2]; k++) acc += p.part[(row * T2 + tl[2][k]) * p.R[2] + off[2][k]];
-        }
     p.gV[v] = acc;
 }
 
-// 32-bit index arithmetic whenever the workspace and the volume fit it
+// I = int32_t whenever the workspace, the volume and every virtual position fit it
+template <typename I>
 __global__ __launch_bounds__(256) void k_gather(GatherParams p) {
     const int64_t NV = p.N3[0] * p.N3[1] * p.N3[2];
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= NV) return;
-    const int64_t parts = p.tiles[0] * p.tiles[1] * p.tiles[2] * (int64_t)p.R[0] * p.R[1] * p.R[2];
-    if (parts < (int64_t(1) << 31) && NV < (int64_t(1) << 31)) gather_point<int32_t>(p, (int32_t)v);
-    else gather_point<int64_t>(p, v);
+    gather_point<I>(p, (I)v);
 }
 
 struct AdjLayout {
@@ -650,7 +673,7 @@ static sal_status launch_adj_dispatch(int n, int s, const AdjParams& p, const Ad
 }
 
 // Workspace layout of sal_backward (each part 256-byte aligned):
-//   cell [G] f32 | gSm [3G] f32 | gE [3G] f32 | fusion-adjoint doubles | tile partials
+//   cell [G] f32 | gS_m / Q [3G] f32 | gE [3G] f32 | fusion-adjoint doubles | tile partials
 struct BwdWs {
     size_t cell, gsm, ge, fus, part, total;
 };
@@ -706,16 +729,17 @@ sal_status sal_backward(const float* V, int64_t T, int64_t IL, int64_t XL, const
     if (!ws || ws_bytes < lay.total) return fail(SAL_ERR_NOMEM, "workspace smaller than sal_backward_workspace_size()");
     char* base = (char*)ws;
     float* cell = (float*)(base + lay.cell);
-    float* gSm = (float*)(base + lay.gsm);
+    float* gSq = (float*)(base + lay.gsm);  // gS_m / Q
     float* gE = (float*)(base + lay.ge);
     double* fws = (double*)(base + lay.fus);
     float* part = (float*)(base + lay.part);
     const Tables* tb = nullptr;
     if ((st = get_tables(spec->n, spec->window, &tb))) return st;
 
-    if ((st = launch_fuse_adjoint(Sm, Tg, ILg, XLg, *fusion, D, mask, W, gS, T, IL, XL, s, cell, fws, gSm, stream)))
+    if ((st = launch_fuse_adjoint(Sm, Tg, ILg, XLg, *fusion, D, mask, W, gS, T, IL, XL, s, ds, cell, fws, gSq,
+                                  stream)))
         return st;
-    if ((st = launch_dcs_adjoint(E, gSm, gE, Tg, ILg, XLg, ds, stream))) return st;
+    if ((st = launch_dcs_adjoint(E, gSq, gE, Tg, ILg, XLg, ds, stream))) return st;
 
     AdjParams p;
     p.V = V;
@@ -740,7 +764,13 @@ sal_status sal_backward(const float* V, int64_t T, int64_t IL, int64_t XL, const
     gp.n = spec->n;
     gp.s = s;
     const int64_t NV = T * IL * XL;
-    hipLaunchKernelGGL(k_gather, dim3((unsigned)((NV + 255) / 256)), dim3(256), 0, stream, gp);
+    const int64_t parts = L.tilesT * L.tilesI * L.tilesX * (int64_t)L.RT * L.RI * L.RX;
+    const int64_t lim = int64_t(1) << 30;
+    const dim3 grid((unsigned)((NV + 255) / 256));
+    if (parts < 2 * lim && NV < 2 * lim && T < lim && IL < lim && XL < lim)
+        hipLaunchKernelGGL(k_gather<int32_t>, grid, dim3(256), 0, stream, gp);
+    else
+        hipLaunchKernelGGL(k_gather<int64_t>, grid, dim3(256), 0, stream, gp);
     return check_hip(hipGetLastError(), "launch k_gather");
 }
 

@@ -74,6 +74,9 @@ CASES = [
     ((25, 24, 23), 12, 3, synth.axis_stencil(6), "fixed", False, "hann"),
     ((13, 10, 9), 4, 1, synth.axis_stencil(2), "equal", False, "hann"),
     ((8, 9, 8), 16, 2, synth.axis_stencil(2), "equal", False, "hann"),   # axes of n/2 voxels
+    # one-sided stencils (no offset pairs with its negation), both forms of Eq. 3
+    ((18, 16, 17), 8, 1, np.array([[1, 0, 0], [0, 2, 0], [0, 0, -1], [1, 1, 1], [-2, 0, 1]]), "equal", False, "hann"),
+    ((16, 19, 18), 8, 2, np.array([[2, 0, 0], [0, -2, 2], [0, 0, 4], [-4, 2, 0]]), "adapt_ls", True, "hann"),
 ]
 
 
