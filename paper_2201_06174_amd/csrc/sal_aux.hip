@@ -102,8 +102,9 @@ sal_status launch_local_spectra(const float* V, int64_t T, int64_t IL, int64_t X
 
 __global__ __launch_bounds__(256) void k_dcs(const float* __restrict__ E, float* __restrict__ S, int64_t Tg,
                                              int64_t ILg, int64_t XLg, DcsStencil st) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= Tg * ILg * XLg) return;
+    const int64_t G = Tg * ILg * XLg;
+    const int64_t j = xcd_block((G + 255) / 256) * 256 + threadIdx.x;
+    if (j >= G) return;
     dcs_point(E, S, Tg, ILg, XLg, st, j);
 }
 
@@ -111,7 +112,7 @@ sal_status launch_dcs(const float* E, float* S, int64_t Tg, int64_t ILg, int64_t
                       hipStream_t stream) {
     const int64_t G = Tg * ILg * XLg;
     if (G == 0) return SAL_OK;
-    const int64_t blocks = (G + 255) / 256;
+    const int64_t blocks = xcd_grid((G + 255) / 256);
     hipLaunchKernelGGL(k_dcs, dim3((unsigned)blocks), dim3(256), 0, stream, E, S, Tg, ILg, XLg, st);
     return check_hip(hipGetLastError(), "launch k_dcs");
 }
@@ -174,7 +175,7 @@ __global__ __launch_bounds__(256) void k_dcs_adjoint(const float* __restrict__ E
                                                      float* __restrict__ gE, int64_t Tg, int64_t ILg, int64_t XLg,
                                                      DcsStencil st) {
     const int64_t G = Tg * ILg * XLg;
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t j = xcd_block((G + 255) / 256) * 256 + threadIdx.x;
     if (j >= G) return;
     if (3 * G < (int64_t(1) << 31))
         dcs_adjoint_point<int32_t, SYM>(E, R, gE, (int32_t)Tg, (int32_t)ILg, (int32_t)XLg, st, (int32_t)j);
@@ -186,7 +187,7 @@ sal_status launch_dcs_adjoint(const float* E, const float* R, float* gE, int64_t
                               const DcsStencil& st, hipStream_t stream) {
     const int64_t G = Tg * ILg * XLg;
     if (G == 0) return SAL_OK;
-    const dim3 grid((unsigned)((G + 255) / 256));
+    const dim3 grid((unsigned)xcd_grid((G + 255) / 256));
     if (st.symmetric)
         hipLaunchKernelGGL(k_dcs_adjoint<true>, grid, dim3(256), 0, stream, E, R, gE, Tg, ILg, XLg, st);
     else
@@ -293,16 +294,14 @@ sal_status launch_fuse(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, co
 
 // ---------------------------------------------------------------- fusion adjoint
 
-// Cell sums c(g) = sum of gS over the voxels whose nearest centre is g.
-__global__ __launch_bounds__(256) void k_cell_sum(const float* __restrict__ gS, int64_t T, int64_t IL, int64_t XL,
-                                                  int s, int64_t Tg, int64_t ILg, int64_t XLg,
-                                                  float* __restrict__ cell) {
-    const int64_t G = Tg * ILg * XLg;
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= G) return;
-    const int64_t gx = j % XLg, gi = (j / XLg) % ILg, gt = j / (XLg * ILg);
-    const int64_t N3[3] = {T, IL, XL}, Ng[3] = {Tg, ILg, XLg}, g3[3] = {gt, gi, gx};
-    int64_t lo[3], hi[3];
+// Cell sum c(g) = sum of gS over the voxels whose nearest centre is g.  I = int32_t when
+// the volume fits it.
+template <typename I>
+__device__ __forceinline__ float cell_sum(const float* __restrict__ gS, I T, I IL, I XL, int s, I Tg, I ILg, I XLg,
+                                          I gt, I gi, I gx) {
+    const I N3[3] = {T, IL, XL}, Ng[3] = {Tg, ILg, XLg}, g3[3] = {gt, gi, gx};
+    I lo[3], hi[3];
+#pragma unroll
     for (int a = 0; a < 3; a++) {
         lo[a] = g3[a] * s - (s - 1) / 2;
         if (lo[a] < 0) lo[a] = 0;
@@ -310,10 +309,20 @@ __global__ __launch_bounds__(256) void k_cell_sum(const float* __restrict__ gS, 
         if (hi[a] > N3[a] - 1) hi[a] = N3[a] - 1;
     }
     double acc = 0.0;
-    for (int64_t t = lo[0]; t <= hi[0]; t++)
-        for (int64_t i = lo[1]; i <= hi[1]; i++)
-            for (int64_t x = lo[2]; x <= hi[2]; x++) acc += (double)gS[(t * IL + i) * XL + x];
-    cell[j] = (float)acc;
+    for (I t = lo[0]; t <= hi[0]; t++)
+        for (I i = lo[1]; i <= hi[1]; i++)
+            for (I x = lo[2]; x <= hi[2]; x++) acc += (double)gS[(t * IL + i) * XL + x];
+    return (float)acc;
+}
+
+template <typename I>
+__global__ __launch_bounds__(256) void k_cell_sum(const float* __restrict__ gS, int64_t T, int64_t IL, int64_t XL,
+                                                  int s, int64_t Tg_, int64_t ILg_, int64_t XLg_,
+                                                  float* __restrict__ cell) {
+    const I Tg = (I)Tg_, ILg = (I)ILg_, XLg = (I)XLg_;
+    const I j = (I)blockIdx.x * (I)blockDim.x + (I)threadIdx.x;
+    if (j >= Tg * ILg * XLg) return;
+    cell[j] = cell_sum<I>(gS, (I)T, (I)IL, (I)XL, s, Tg, ILg, XLg, j / (XLg * ILg), (j / XLg) % ILg, j % XLg);
 }
 
 // Per-block FP64 partials of gW_m = sum_g S_m(g) c(g), and (ADAPT_LS) nothing else:
@@ -357,27 +366,32 @@ __global__ __launch_bounds__(64) void k_gw_solve(const double* __restrict__ part
 }
 
 // gS_m(g) = W_m c(g) (+ on the mask, ADAPT_LS: lambda_m (D - W.u) - W_m (lambda.u)), stored
-// divided by the neighbour count Q(g).
+// divided by the neighbour count Q(g).  Without a cell-sum buffer (cell == nullptr) c(g) is
+// summed here from gS.
+// I = int32_t when the grid's three planes fit it.
+template <typename I>
 __global__ __launch_bounds__(256) void k_gsm(const float* __restrict__ Sm, const float* __restrict__ cell,
                                              const double* __restrict__ W, const double* __restrict__ lam,
                                              const float* __restrict__ D, const uint8_t* __restrict__ mask,
-                                             int64_t Tg, int64_t ILg, int64_t XLg, DcsStencil ds, int adapt,
+                                             int64_t Tg_, int64_t ILg_, int64_t XLg_, DcsStencil ds, int adapt,
+                                             const float* __restrict__ gS, int64_t T, int64_t IL, int64_t XL, int s,
                                              float* __restrict__ R) {
-    const int64_t G = Tg * ILg * XLg;
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const I Tg = (I)Tg_, ILg = (I)ILg_, XLg = (I)XLg_;
+    const I G = Tg * ILg * XLg;
+    const I j = (I)blockIdx.x * (I)blockDim.x + (I)threadIdx.x;
     if (j >= G) return;
     // neighbours of g inside the grid (all q of them away from the borders)
-    const int64_t gx = j % XLg, gi = (j / XLg) % ILg, gt = j / (XLg * ILg);
+    const I gx = j % XLg, gi = (j / XLg) % ILg, gt = j / (XLg * ILg);
     int Q = ds.q;
     if (!(gt >= ds.reach[0] && gt + ds.reach[0] < Tg && gi >= ds.reach[1] && gi + ds.reach[1] < ILg &&
           gx >= ds.reach[2] && gx + ds.reach[2] < XLg)) {
         Q = 0;
         for (int k = 0; k < ds.q; k++) {
-            const int64_t a = gt + ds.o[k][0], b = gi + ds.o[k][1], c = gx + ds.o[k][2];
+            const I a = gt + ds.o[k][0], b = gi + ds.o[k][1], c = gx + ds.o[k][2];
             Q += a >= 0 && a < Tg && b >= 0 && b < ILg && c >= 0 && c < XLg;
         }
     }
-    const double c = cell[j];
+    const double c = cell ? cell[j] : cell_sum<I>(gS, (I)T, (I)IL, (I)XL, s, Tg, ILg, XLg, gt, gi, gx);
     double g[3] = {W[0] * c, W[1] * c, W[2] * c};
     if (adapt && W[3] == 0.0 && (!mask || mask[j])) {
         const double u0 = Sm[j], u1 = Sm[G + j], u2 = Sm[2 * G + j];
@@ -396,10 +410,21 @@ sal_status launch_fuse_adjoint(const float* Sm, int64_t Tg, int64_t ILg, int64_t
     const int64_t G = Tg * ILg * XLg;
     if (G == 0) return SAL_OK;
     const unsigned blocks = (unsigned)((G + 255) / 256);
-    hipLaunchKernelGGL(k_cell_sum, dim3(blocks), dim3(256), 0, stream, gS, T, IL, XL, s, Tg, ILg, XLg, cell);
-    sal_status st = check_hip(hipGetLastError(), "launch k_cell_sum");
-    if (st) return st;
+    // 32-bit index arithmetic when the volume and the grid's three planes fit it
+    const bool i32 = T * IL * XL < (int64_t(1) << 31) && 3 * G < (int64_t(1) << 31);
     const int adapt = f.mode == SAL_FUSE_ADAPT_LS;
+    sal_status st = SAL_OK;
+    // the adapted weights need every c(g) before gS_m; otherwise k_gsm sums its own cell
+    if (adapt) {
+        if (i32)
+            hipLaunchKernelGGL(k_cell_sum<int32_t>, dim3(blocks), dim3(256), 0, stream, gS, T, IL, XL, s, Tg, ILg,
+                               XLg, cell);
+        else
+            hipLaunchKernelGGL(k_cell_sum<int64_t>, dim3(blocks), dim3(256), 0, stream, gS, T, IL, XL, s, Tg, ILg,
+                               XLg, cell);
+        if ((st = check_hip(hipGetLastError(), "launch k_cell_sum"))) return st;
+    }
+    const float* cellp = adapt ? cell : nullptr;
     double* lam = ws + kFuseParts * kStats + 11;  // after the forward's reduced statistics
     if (adapt) {
         // statistics of the forward, recomputed here so the adjoint does not depend on workspace state
@@ -416,8 +441,12 @@ sal_status launch_fuse_adjoint(const float* Sm, int64_t Tg, int64_t ILg, int64_t
                            f.delta, lam);
         if ((st = check_hip(hipGetLastError(), "launch k_gw_solve"))) return st;
     }
-    hipLaunchKernelGGL(k_gsm, dim3(blocks), dim3(256), 0, stream, Sm, cell, W, lam, D, mask, Tg, ILg, XLg, ds, adapt,
-                       R);
+    if (i32)
+        hipLaunchKernelGGL(k_gsm<int32_t>, dim3(blocks), dim3(256), 0, stream, Sm, cellp, W, lam, D, mask, Tg, ILg,
+                           XLg, ds, adapt, gS, T, IL, XL, s, R);
+    else
+        hipLaunchKernelGGL(k_gsm<int64_t>, dim3(blocks), dim3(256), 0, stream, Sm, cellp, W, lam, D, mask, Tg, ILg,
+                           XLg, ds, adapt, gS, T, IL, XL, s, R);
     return check_hip(hipGetLastError(), "launch k_gsm");
 }
 

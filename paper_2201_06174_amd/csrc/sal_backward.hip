@@ -16,6 +16,7 @@
 // it directly or through the border reflection, in a fixed order (no atomics,
 // bitwise reproducible).
 #include "sal_aux.h"
+#include "sal_device.h"
 #include "sal_stage.h"
 
 namespace sal {
@@ -609,7 +610,7 @@ __device__ __forceinline__ void gather_point(const GatherParams& p, I v) {
 template <typename I>
 __global__ __launch_bounds__(256) void k_gather(GatherParams p) {
     const int64_t NV = p.N3[0] * p.N3[1] * p.N3[2];
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t v = xcd_block((NV + 255) / 256) * 256 + threadIdx.x;
     if (v >= NV) return;
     gather_point<I>(p, (I)v);
 }
@@ -766,7 +767,7 @@ sal_status sal_backward(const float* V, int64_t T, int64_t IL, int64_t XL, const
     const int64_t NV = T * IL * XL;
     const int64_t parts = L.tilesT * L.tilesI * L.tilesX * (int64_t)L.RT * L.RI * L.RX;
     const int64_t lim = int64_t(1) << 30;
-    const dim3 grid((unsigned)((NV + 255) / 256));
+    const dim3 grid((unsigned)xcd_grid((NV + 255) / 256));
     if (parts < 2 * lim && NV < 2 * lim && T < lim && IL < lim && XL < lim)
         hipLaunchKernelGGL(k_gather<int32_t>, grid, dim3(256), 0, stream, gp);
     else
