@@ -63,6 +63,7 @@ sal_status project_fp32_batch(int n, int s, const void* items, const int64_t* pr
 sal_status project_lowp_batch(int n, int s, int precision, int CT, const void* items, const int64_t* prefix,
                               int nitems, int64_t total, size_t lds, int grid, hipStream_t stream);
 sal_status project_fp32_batch_occupancy(int n, int s, size_t lds, int* per_cu);
+int64_t project_fp32_batch_grid(int n, int64_t total, int64_t resident);
 sal_status project_lowp_batch_occupancy(int n, int s, int precision, int CT, size_t lds, int* per_cu);
 
 }  // namespace sal

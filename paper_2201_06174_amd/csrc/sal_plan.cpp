@@ -109,6 +109,8 @@ sal_status build_class_params(sal_plan* plan, Class& c, int CT) {
     int64_t grid = (int64_t)cus * per_cu;
     grid = std::min<int64_t>(grid, 8 * ((total + 7) / 8));
     grid = std::max<int64_t>(8, grid / 8 * 8);
+    if (c.spec.precision == SAL_PREC_FP32) grid = project_fp32_batch_grid(c.spec.n, total, grid);
+    if (grid > INT32_MAX) return fail(SAL_ERR_SHAPE, "batch class too large for one launch");
     c.grid = (int)grid;
     return SAL_OK;
 }

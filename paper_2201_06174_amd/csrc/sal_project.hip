@@ -435,6 +435,28 @@ __global__ __launch_bounds__(kNT, (fp32_waves_per_simd<N>())) void k_project_fp3
     }
 }
 
+// n = 8 (two workgroups per CU within 64 registers): the batch takes one tile per workgroup
+// like the single-volume kernel, since the persistent loop's extra live state does not fit
+// that register budget.
+template <int N>
+constexpr bool fp32_batch_one_tile() { return fp32_waves_per_simd<N>() > 4; }
+
+template <int N, int S, int CTW>
+__global__ __launch_bounds__(kNT, (fp32_waves_per_simd<N>())) void k_project_fp32_batch1(const ProjParams* __restrict__ items,
+                                                             const int64_t* __restrict__ prefix, int nitems,
+                                                             int64_t total) {
+    extern __shared__ float lds[];
+    const int64_t per = (total + 7) / 8;
+    const int64_t g = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (g >= total) return;
+    int a = 0, b = nitems - 1;  // last item with prefix[item] <= g
+    while (a < b) {
+        const int m = (a + b + 1) / 2;
+        if (prefix[m] <= g) a = m; else b = m - 1;
+    }
+    project_tile_fp32<N, S, CTW>(items[a], g - prefix[a], lds);
+}
+
 static size_t proj_lds_bytes(int n, int s, int CT, int* RT, int* RI, int* RX, int* RXp) {
     *RT = (CT - 1) * s + n;
     *RI = 3 * s + n;
@@ -552,18 +574,39 @@ template <int N, int S, int CTW>
 static sal_status launch_batch(const void* items, const int64_t* prefix, int nitems, int64_t total, size_t lds,
                                int grid, hipStream_t stream) {
     // the LDS attribute was set by project_fp32_batch_occupancy(), outside any stream capture
-    hipLaunchKernelGGL((k_project_fp32_batch<N, S, CTW>), dim3((unsigned)grid), dim3(kNT), lds, stream,
-                       (const ProjParams*)items, prefix, nitems, total);
+    if constexpr (fp32_batch_one_tile<N>()) {
+        (void)grid;
+        const int64_t g1 = 8 * ((total + 7) / 8);
+        if (g1 > INT32_MAX) return fail(SAL_ERR_SHAPE, "batch too large for one launch");
+        hipLaunchKernelGGL((k_project_fp32_batch1<N, S, CTW>), dim3((unsigned)g1), dim3(kNT), lds, stream,
+                           (const ProjParams*)items, prefix, nitems, total);
+    } else {
+        hipLaunchKernelGGL((k_project_fp32_batch<N, S, CTW>), dim3((unsigned)grid), dim3(kNT), lds, stream,
+                           (const ProjParams*)items, prefix, nitems, total);
+    }
     return check_hip(hipGetLastError(), "launch k_project_fp32_batch");
 }
 
 template <int N, int S, int CTW>
 static sal_status batch_occupancy(size_t lds, int* per_cu) {
-    sal_status st = set_lds_attr(k_project_fp32_batch<N, S, CTW>, "hipFuncSetAttribute(project batch)");
-    if (st) return st;
-    return check_hip(
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_project_fp32_batch<N, S, CTW>, kNT, lds),
-        "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+    if constexpr (fp32_batch_one_tile<N>()) {
+        sal_status st = set_lds_attr(k_project_fp32_batch1<N, S, CTW>, "hipFuncSetAttribute(project batch)");
+        if (st) return st;
+        return check_hip(
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_project_fp32_batch1<N, S, CTW>, kNT, lds),
+            "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+    } else {
+        sal_status st = set_lds_attr(k_project_fp32_batch<N, S, CTW>, "hipFuncSetAttribute(project batch)");
+        if (st) return st;
+        return check_hip(
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_project_fp32_batch<N, S, CTW>, kNT, lds),
+            "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+    }
+}
+
+// Workgroups of a batched launch: one per tile for the one-tile form, else `resident`.
+int64_t project_fp32_batch_grid(int n, int64_t total, int64_t resident) {
+    return n == 8 ? 8 * ((total + 7) / 8) : resident;
 }
 
 sal_status project_fp32_batch(int n, int s, const void* items, const int64_t* prefix, int nitems, int64_t total,
