@@ -134,6 +134,32 @@ def time_forward(torch, pipe, steps, warmup):
     return total_ms / steps, float(np.mean(kern_ms)), wall
 
 
+def progress(msg):
+    """A progress line on stderr (stdout carries only the result line)."""
+    print("[bench] %s" % msg, file=sys.stderr, flush=True)
+
+
+def precision_forms(torch, lib, Vd, w, fusion, Dd, Md, steps, done):
+    """The forward step in FP32, split-BF16 and FP16 on one volume; `done` holds (ms per step,
+    kernel ms) of a precision already timed."""
+    nvox = int(np.prod(Vd.shape))
+    forms = {}
+    for prec in ("fp32", "split_bf16", "fp16"):
+        if prec in done:
+            m2, k2 = done[prec]
+        else:
+            progress("%s forward on %s" % (prec, "x".join(str(v) for v in Vd.shape)))
+            pp = Pipeline(torch, lib, Vd, w, prec, fusion, Dd, Md)
+            m2, k2, _ = time_forward(torch, pp, steps, 2)
+            del pp
+        nwin = int(np.prod([-(-N // w.s) for N in Vd.shape]))
+        forms[prec] = {"ms_per_step": round(m2, 4), "kernel_ms": round(k2, 4),
+                       "mvoxel_s": round(nvox / (m2 * 1e-3) / 1e6, 3), "graded": graded(w, nwin, prec, k2)}
+    for prec in ("fp32", "split_bf16", "fp16"):
+        forms[prec]["speedup_vs_fp32"] = round(forms["fp32"]["ms_per_step"] / forms[prec]["ms_per_step"], 3)
+    return forms
+
+
 def time_fwd_bwd(torch, w_name, steps, warmup):
     """Forward plus the hand-written adjoint on one workload (equal fusion)."""
     import paper_2201_06174_amd as sal
@@ -308,6 +334,7 @@ def main():
     if args.traffic_pass:
         traffic_pass(torch, pipe)
         return
+    progress("%s forward on %s" % (args.precision, args.workload))
     ms, kern_ms, wall = time_forward(torch, pipe, args.steps, args.warmup)
     nvox = int(np.prod(V.shape))
     nwin = int(np.prod(pipe.grid))
@@ -340,24 +367,31 @@ def main():
     }
     if not args.no_extra:
         extra = {}
-        forms = {}
-        for prec in ("fp32", "split_bf16", "fp16"):
-            if prec == args.precision:
-                forms[prec] = {"ms_per_step": round(ms, 4), "kernel_ms": round(kern_ms, 4),
-                               "mvoxel_s": round(value, 3), "graded": graded(w, nwin, prec, kern_ms)}
-                continue
-            pp = Pipeline(torch, lib, Vd, w, prec, args.fusion, Dd, Md)
-            m2, k2, _ = time_forward(torch, pp, max(3, args.steps // 2), 2)
-            forms[prec] = {"ms_per_step": round(m2, 4), "kernel_ms": round(k2, 4),
-                           "mvoxel_s": round(nvox / (m2 * 1e-3) / 1e6, 3), "graded": graded(w, nwin, prec, k2)}
-            del pp
-        for prec in forms:
-            forms[prec]["speedup_vs_fp32"] = round(forms["fp32"]["ms_per_step"] / forms[prec]["ms_per_step"], 3)
-        extra["precision_forms"] = forms
+        done = {args.precision: (ms, kern_ms)}
+        extra["precision_forms"] = precision_forms(torch, lib, Vd, w, args.fusion, Dd, Md, max(3, args.steps // 2),
+                                                   done)
+        if args.workload != "salt":
+            # the precision form's own configuration: the 512^3 salt-dome volume
+            del pipe
+            progress("generating the salt volume")
+            ws_ = synth.workload("salt")
+            Vs, Ms = synth.make_volume(ws_.spec, ws_.seed, with_mask=True)
+            Ds, masks = synth.desired_map(Ms, ws_.s)
+            Vsd, Dsd, Msd = (torch.from_numpy(a).to(dev) for a in (Vs, Ds, masks))
+            del Vs, Ms, Ds, masks
+            forms = precision_forms(torch, lib, Vsd, ws_, args.fusion, Dsd, Msd, 3, {})
+            forms["workload"] = "salt: %s volume, window %d^3 Hann, stride %d, %d neighbours, %s fusion" % (
+                "x".join(str(v) for v in Vsd.shape), ws_.n, ws_.s, len(ws_.offsets), args.fusion)
+            extra["precision_forms_salt"] = forms
+            del Vsd, Dsd, Msd
+            torch.cuda.empty_cache()
+        progress("forward + adjoint on grad")
         extra["fwd_bwd"] = time_fwd_bwd(torch, "grad", 5, 2)
+        progress("batch plan")
         extra["batch"] = time_batch(torch, lib, 5)
         out["extra"] = extra
     if not args.no_cpu_baseline:
+        progress("oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(V, w, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
