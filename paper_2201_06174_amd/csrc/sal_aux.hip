@@ -17,7 +17,7 @@ __device__ __forceinline__ int64_t reflect_index(int64_t p, int64_t N) {
 // DFT passes (xl, il, t), each output a direct n-term sum.
 __global__ __launch_bounds__(256) void k_local_spectra(const float* __restrict__ V, int64_t T, int64_t IL, int64_t XL,
                                                        int n, int window, const int32_t* __restrict__ centers,
-                                                       float* __restrict__ F) {
+                                                       int64_t cnt, float* __restrict__ F) {
     extern __shared__ float sh[];
     const int n3 = n * n * n;
     float* xr = sh;
@@ -26,7 +26,8 @@ __global__ __launch_bounds__(256) void k_local_spectra(const float* __restrict__
     float* yi = sh + 3 * n3;
     float* tw = sh + 4 * n3;  // [n][n][2] cos/sin(2 pi k a / n)
     float* h = tw + 2 * n * n;
-    const int64_t c = blockIdx.x;
+    const int64_t c = block_id();
+    if (c >= cnt) return;
     const int64_t ct = centers[3 * c], ci = centers[3 * c + 1], cx = centers[3 * c + 2];
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
         const int k = e / n, a = e % n;
@@ -88,14 +89,10 @@ sal_status launch_local_spectra(const float* V, int64_t T, int64_t IL, int64_t X
         if (st) return st;
         attr = true;
     }
-    for (int64_t off = 0; off < cnt; off += (1 << 30)) {
-        const int64_t m = cnt - off < (1 << 30) ? cnt - off : (1 << 30);
-        hipLaunchKernelGGL(k_local_spectra, dim3((unsigned)m), dim3(256), lds, stream, V, T, IL, XL, n, window,
-                           centers + 3 * off, F + off * 2 * (int64_t)n * n * n);
-        sal_status st = check_hip(hipGetLastError(), "launch k_local_spectra");
-        if (st) return st;
-    }
-    return SAL_OK;
+    if (!wide_grid_fits(cnt, 256)) return fail(SAL_ERR_SHAPE, "too many centres for one launch");
+    hipLaunchKernelGGL(k_local_spectra, wide_grid(cnt, 256), dim3(256), lds, stream, V, T, IL, XL, n, window, centers,
+                       cnt, F);
+    return check_hip(hipGetLastError(), "launch k_local_spectra");
 }
 
 // ---------------------------------------------------------------- center-surround (Eq. 3)
@@ -113,7 +110,8 @@ sal_status launch_dcs(const float* E, float* S, int64_t Tg, int64_t ILg, int64_t
     const int64_t G = Tg * ILg * XLg;
     if (G == 0) return SAL_OK;
     const int64_t blocks = xcd_grid((G + 255) / 256);
-    hipLaunchKernelGGL(k_dcs, dim3((unsigned)blocks), dim3(256), 0, stream, E, S, Tg, ILg, XLg, st);
+    if (!wide_grid_fits(blocks, 256)) return fail(SAL_ERR_SHAPE, "grid too large for one launch");
+    hipLaunchKernelGGL(k_dcs, wide_grid(blocks, 256), dim3(256), 0, stream, E, S, Tg, ILg, XLg, st);
     return check_hip(hipGetLastError(), "launch k_dcs");
 }
 
@@ -187,7 +185,9 @@ sal_status launch_dcs_adjoint(const float* E, const float* R, float* gE, int64_t
                               const DcsStencil& st, hipStream_t stream) {
     const int64_t G = Tg * ILg * XLg;
     if (G == 0) return SAL_OK;
-    const dim3 grid((unsigned)xcd_grid((G + 255) / 256));
+    const int64_t blocks = xcd_grid((G + 255) / 256);
+    if (!wide_grid_fits(blocks, 256)) return fail(SAL_ERR_SHAPE, "grid too large for one launch");
+    const dim3 grid = wide_grid(blocks, 256);
     if (st.symmetric)
         hipLaunchKernelGGL(k_dcs_adjoint<true>, grid, dim3(256), 0, stream, E, R, gE, Tg, ILg, XLg, st);
     else
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256) void k_combine4(const float* __restrict__ Sm, 
     const int sh = (s - 1) / 2;
     const int64_t q = XL / 4;
     for (int64_t e = threadIdx.x; e < kCombineRows * q; e += blockDim.x) {
-        const int64_t row = (int64_t)blockIdx.x * kCombineRows + e / q;
+        const int64_t row = block_id() * kCombineRows + e / q;
         if (row >= T * IL) break;
         const int64_t t = row / IL, i = row % IL;
         const int64_t base = (cell_of(t, s, Tg) * ILg + cell_of(i, s, ILg)) * XLg;
@@ -253,8 +253,9 @@ __global__ __launch_bounds__(256) void k_combine4(const float* __restrict__ Sm, 
 __global__ __launch_bounds__(256) void k_combine(const float* __restrict__ Sm, const double* __restrict__ W,
                                                  int64_t Tg, int64_t ILg, int64_t XLg, int64_t T, int64_t IL,
                                                  int64_t XL, int s, float* __restrict__ S) {
-    (void)T;  // one block per (t, il) row: the grid carries T
-    combine_row(Sm, W, Tg, ILg, XLg, IL, XL, s, (int64_t)blockIdx.x, S);
+    const int64_t row = block_id();  // one block per (t, il) row
+    if (row >= T * IL) return;
+    combine_row(Sm, W, Tg, ILg, XLg, IL, XL, s, row, S);
 }
 
 size_t fuse_workspace_bytes() { return sizeof(double) * (kFuseParts * kStats + 16); }
@@ -273,20 +274,20 @@ sal_status launch_fuse(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, co
     sal_status st = check_hip(hipGetLastError(), "launch k_fuse_solve");
     if (st) return st;
     if (T * IL * XL == 0) return SAL_OK;
-    if (T * IL > INT32_MAX) return fail(SAL_ERR_SHAPE, "volume too large for one launch");
+    if (!wide_grid_fits(T * IL, 256)) return fail(SAL_ERR_SHAPE, "volume too large for one launch");
     if (XL % 4 == 0 && reinterpret_cast<uintptr_t>(S) % 16 == 0) {
         const int64_t blocks = (T * IL + kCombineRows - 1) / kCombineRows;
         if (s == 1)
-            hipLaunchKernelGGL(k_combine4<1>, dim3((unsigned)blocks), dim3(256), 0, stream, Sm, W, Tg, ILg, XLg, T, IL,
+            hipLaunchKernelGGL(k_combine4<1>, wide_grid(blocks, 256), dim3(256), 0, stream, Sm, W, Tg, ILg, XLg, T, IL,
                                XL, s, S);
         else if (s == 2)
-            hipLaunchKernelGGL(k_combine4<2>, dim3((unsigned)blocks), dim3(256), 0, stream, Sm, W, Tg, ILg, XLg, T, IL,
+            hipLaunchKernelGGL(k_combine4<2>, wide_grid(blocks, 256), dim3(256), 0, stream, Sm, W, Tg, ILg, XLg, T, IL,
                                XL, s, S);
         else
-            hipLaunchKernelGGL(k_combine4<0>, dim3((unsigned)blocks), dim3(256), 0, stream, Sm, W, Tg, ILg, XLg, T, IL,
+            hipLaunchKernelGGL(k_combine4<0>, wide_grid(blocks, 256), dim3(256), 0, stream, Sm, W, Tg, ILg, XLg, T, IL,
                                XL, s, S);
     } else {
-        hipLaunchKernelGGL(k_combine, dim3((unsigned)(T * IL)), dim3(256), 0, stream, Sm, W, Tg, ILg, XLg, T, IL, XL,
+        hipLaunchKernelGGL(k_combine, wide_grid(T * IL, 256), dim3(256), 0, stream, Sm, W, Tg, ILg, XLg, T, IL, XL,
                            s, S);
     }
     return check_hip(hipGetLastError(), "launch k_combine");
@@ -320,8 +321,9 @@ __global__ __launch_bounds__(256) void k_cell_sum(const float* __restrict__ gS, 
                                                   int s, int64_t Tg_, int64_t ILg_, int64_t XLg_,
                                                   float* __restrict__ cell) {
     const I Tg = (I)Tg_, ILg = (I)ILg_, XLg = (I)XLg_;
-    const I j = (I)blockIdx.x * (I)blockDim.x + (I)threadIdx.x;
-    if (j >= Tg * ILg * XLg) return;
+    const int64_t j64 = block_id() * blockDim.x + threadIdx.x;
+    if (j64 >= (int64_t)Tg_ * ILg_ * XLg_) return;
+    const I j = (I)j64;
     cell[j] = cell_sum<I>(gS, (I)T, (I)IL, (I)XL, s, Tg, ILg, XLg, j / (XLg * ILg), (j / XLg) % ILg, j % XLg);
 }
 
@@ -378,8 +380,9 @@ __global__ __launch_bounds__(256) void k_gsm(const float* __restrict__ Sm, const
                                              float* __restrict__ R) {
     const I Tg = (I)Tg_, ILg = (I)ILg_, XLg = (I)XLg_;
     const I G = Tg * ILg * XLg;
-    const I j = (I)blockIdx.x * (I)blockDim.x + (I)threadIdx.x;
-    if (j >= G) return;
+    const int64_t j64 = block_id() * blockDim.x + threadIdx.x;
+    if (j64 >= (int64_t)G) return;
+    const I j = (I)j64;
     // neighbours of g inside the grid (all q of them away from the borders)
     const I gx = j % XLg, gi = (j / XLg) % ILg, gt = j / (XLg * ILg);
     int Q = ds.q;
@@ -409,7 +412,9 @@ sal_status launch_fuse_adjoint(const float* Sm, int64_t Tg, int64_t ILg, int64_t
                                hipStream_t stream) {
     const int64_t G = Tg * ILg * XLg;
     if (G == 0) return SAL_OK;
-    const unsigned blocks = (unsigned)((G + 255) / 256);
+    const int64_t nb = (G + 255) / 256;
+    if (!wide_grid_fits(nb, 256)) return fail(SAL_ERR_SHAPE, "grid too large for one launch");
+    const dim3 blocks = wide_grid(nb, 256);
     // 32-bit index arithmetic when the volume and the grid's three planes fit it
     const bool i32 = T * IL * XL < (int64_t(1) << 31) && 3 * G < (int64_t(1) << 31);
     const int adapt = f.mode == SAL_FUSE_ADAPT_LS;
@@ -417,10 +422,10 @@ sal_status launch_fuse_adjoint(const float* Sm, int64_t Tg, int64_t ILg, int64_t
     // the adapted weights need every c(g) before gS_m; otherwise k_gsm sums its own cell
     if (adapt) {
         if (i32)
-            hipLaunchKernelGGL(k_cell_sum<int32_t>, dim3(blocks), dim3(256), 0, stream, gS, T, IL, XL, s, Tg, ILg,
+            hipLaunchKernelGGL(k_cell_sum<int32_t>, blocks, dim3(256), 0, stream, gS, T, IL, XL, s, Tg, ILg,
                                XLg, cell);
         else
-            hipLaunchKernelGGL(k_cell_sum<int64_t>, dim3(blocks), dim3(256), 0, stream, gS, T, IL, XL, s, Tg, ILg,
+            hipLaunchKernelGGL(k_cell_sum<int64_t>, blocks, dim3(256), 0, stream, gS, T, IL, XL, s, Tg, ILg,
                                XLg, cell);
         if ((st = check_hip(hipGetLastError(), "launch k_cell_sum"))) return st;
     }
@@ -442,10 +447,10 @@ sal_status launch_fuse_adjoint(const float* Sm, int64_t Tg, int64_t ILg, int64_t
         if ((st = check_hip(hipGetLastError(), "launch k_gw_solve"))) return st;
     }
     if (i32)
-        hipLaunchKernelGGL(k_gsm<int32_t>, dim3(blocks), dim3(256), 0, stream, Sm, cellp, W, lam, D, mask, Tg, ILg,
+        hipLaunchKernelGGL(k_gsm<int32_t>, blocks, dim3(256), 0, stream, Sm, cellp, W, lam, D, mask, Tg, ILg,
                            XLg, ds, adapt, gS, T, IL, XL, s, R);
     else
-        hipLaunchKernelGGL(k_gsm<int64_t>, dim3(blocks), dim3(256), 0, stream, Sm, cellp, W, lam, D, mask, Tg, ILg,
+        hipLaunchKernelGGL(k_gsm<int64_t>, blocks, dim3(256), 0, stream, Sm, cellp, W, lam, D, mask, Tg, ILg,
                            XLg, ds, adapt, gS, T, IL, XL, s, R);
     return check_hip(hipGetLastError(), "launch k_gsm");
 }

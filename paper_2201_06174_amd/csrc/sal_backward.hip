@@ -105,8 +105,7 @@ __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_
     const int col = lane & 15;
     const int grp = lane >> 4;
 
-    const int64_t per = (p.ntiles + 7) / 8;
-    const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    const int64_t tile = xcd_block(p.ntiles);
     if (tile >= p.ntiles) return;
     const int64_t tx = tile % p.tilesX;
     const int64_t ti = (tile / p.tilesX) % p.tilesI;
@@ -657,8 +656,9 @@ static sal_status launch_adj(const AdjParams& p, const AdjLayout& L, hipStream_t
         if (st) return st;
         attr = true;
     }
-    const int64_t grid = 8 * ((L.ntiles + 7) / 8);
-    hipLaunchKernelGGL((k_spectral_adjoint<N, S>), dim3((unsigned)grid), dim3(512), L.lds, stream, p);
+    const int64_t grid = xcd_grid(L.ntiles);
+    if (!wide_grid_fits(grid, 512)) return fail(SAL_ERR_SHAPE, "volume too large for one launch");
+    hipLaunchKernelGGL((k_spectral_adjoint<N, S>), wide_grid(grid, 512), dim3(512), L.lds, stream, p);
     return check_hip(hipGetLastError(), "launch k_spectral_adjoint");
 }
 
@@ -767,7 +767,9 @@ sal_status sal_backward(const float* V, int64_t T, int64_t IL, int64_t XL, const
     const int64_t NV = T * IL * XL;
     const int64_t parts = L.tilesT * L.tilesI * L.tilesX * (int64_t)L.RT * L.RI * L.RX;
     const int64_t lim = int64_t(1) << 30;
-    const dim3 grid((unsigned)xcd_grid((NV + 255) / 256));
+    const int64_t nb = xcd_grid((NV + 255) / 256);
+    if (!wide_grid_fits(nb, 256)) return fail(SAL_ERR_SHAPE, "volume too large for one launch");
+    const dim3 grid = wide_grid(nb, 256);
     if (parts < 2 * lim && NV < 2 * lim && T < lim && IL < lim && XL < lim)
         hipLaunchKernelGGL(k_gather<int32_t>, grid, dim3(256), 0, stream, gp);
     else

@@ -17,9 +17,10 @@ __device__ __forceinline__ int find_item(const int64_t* __restrict__ first, int 
 
 __global__ __launch_bounds__(256) void k_dcs_batch(const DcsItem* __restrict__ items,
                                                    const int64_t* __restrict__ first, int n) {
-    const int a = find_item(first, n, blockIdx.x);
+    const int64_t b = block_id();
+    const int a = find_item(first, n, b);
     const DcsItem& it = items[a];
-    const int64_t j = (int64_t)(blockIdx.x - first[a]) * blockDim.x + threadIdx.x;
+    const int64_t j = (b - first[a]) * blockDim.x + threadIdx.x;
     if (j >= it.Tg * it.ILg * it.XLg) return;
     dcs_point(it.E, it.S, it.Tg, it.ILg, it.XLg, it.st, j);
 }
@@ -41,15 +42,18 @@ __global__ __launch_bounds__(64) void k_fuse_solve_batch(const FuseItem* __restr
 }
 
 __global__ __launch_bounds__(256) void k_combine_batch(const FuseItem* __restrict__ items,
-                                                       const int64_t* __restrict__ first, int n) {
-    const int a = find_item(first, n, blockIdx.x);
+                                                       const int64_t* __restrict__ first, int n, int64_t rows) {
+    const int64_t b = block_id();
+    if (b >= rows) return;
+    const int a = find_item(first, n, b);
     const FuseItem& it = items[a];
-    combine_row(it.Sm, it.W, it.Tg, it.ILg, it.XLg, it.IL, it.XL, it.s, (int64_t)(blockIdx.x - first[a]), it.S);
+    combine_row(it.Sm, it.W, it.Tg, it.ILg, it.XLg, it.IL, it.XL, it.s, b - first[a], it.S);
 }
 
 sal_status launch_dcs_batch(const DcsItem* items, const int64_t* first, int n, int64_t blocks, hipStream_t stream) {
     if (blocks == 0) return SAL_OK;
-    hipLaunchKernelGGL(k_dcs_batch, dim3((unsigned)blocks), dim3(256), 0, stream, items, first, n);
+    if (!wide_grid_fits(blocks, 256)) return fail(SAL_ERR_SHAPE, "batch too large for one launch");
+    hipLaunchKernelGGL(k_dcs_batch, wide_grid(blocks, 256), dim3(256), 0, stream, items, first, n);
     return check_hip(hipGetLastError(), "launch k_dcs_batch");
 }
 
@@ -64,7 +68,8 @@ sal_status launch_fuse_batch(const FuseItem* items, int n, const int* adapt_list
     hipLaunchKernelGGL(k_fuse_solve_batch, dim3((unsigned)n), dim3(64), 0, stream, items);
     if ((st = check_hip(hipGetLastError(), "launch k_fuse_solve_batch"))) return st;
     if (rows == 0) return SAL_OK;
-    hipLaunchKernelGGL(k_combine_batch, dim3((unsigned)rows), dim3(256), 0, stream, items, first, n);
+    if (!wide_grid_fits(rows, 256)) return fail(SAL_ERR_SHAPE, "batch too large for one launch");
+    hipLaunchKernelGGL(k_combine_batch, wide_grid(rows, 256), dim3(256), 0, stream, items, first, n, rows);
     return check_hip(hipGetLastError(), "launch k_combine_batch");
 }
 

@@ -3,17 +3,9 @@
 #pragma once
 
 #include "sal_aux.h"
+#include "sal_grid.h"
 
 namespace sal {
-
-// Workgroups are dealt to the 8 XCDs round-robin.  xcd_block(nblocks) renumbers a launch of
-// xcd_grid(nblocks) workgroups so that each XCD takes a contiguous eighth of the range
-// [0, nblocks) (its neighbour reads then stay in that XCD's L2); numbers >= nblocks are
-// padding and do nothing.
-__host__ __device__ inline int64_t xcd_grid(int64_t nblocks) { return 8 * ((nblocks + 7) / 8); }
-__device__ __forceinline__ int64_t xcd_block(int64_t nblocks) {
-    return (int64_t)(blockIdx.x % 8) * ((nblocks + 7) / 8) + blockIdx.x / 8;
-}
 
 // S_m at grid point j of one volume (Sec. 2, Eq. 3): (1/Q) sum over in-grid neighbours.
 // A point at least the stencil reach away from every border has all q neighbours in the

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "sal_aux.h"
+#include "sal_grid.h"
 #include "sal_stage.h"
 
 namespace sal {
@@ -591,8 +592,7 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
 template <int N, int S, int PREC, int CTW, bool FIX>
 __global__ __launch_bounds__(kNTL) void k_project_lowp(LowpParams p) {
     extern __shared__ float lds[];
-    const int64_t per = (p.ntiles + 7) / 8;
-    const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    const int64_t tile = xcd_block(p.ntiles);
     if (tile >= p.ntiles) return;
     project_tile_lowp<N, S, PREC, CTW, FIX>(p, tile, lds);
 }
@@ -709,9 +709,9 @@ static sal_status launch_lowp_k(const LowpParams& p, size_t lds, hipStream_t str
         if (st) return st;
         attr = true;
     }
-    const int64_t grid = 8 * ((p.ntiles + 7) / 8);
-    if (grid > INT32_MAX) return fail(SAL_ERR_SHAPE, "volume too large for one launch");
-    hipLaunchKernelGGL((k_project_lowp<N, S, PREC, CTW, FIX>), dim3((unsigned)grid), dim3(kNTL), lds, stream, p);
+    const int64_t grid = xcd_grid(p.ntiles);
+    if (!wide_grid_fits(grid, kNTL)) return fail(SAL_ERR_SHAPE, "volume too large for one launch");
+    hipLaunchKernelGGL((k_project_lowp<N, S, PREC, CTW, FIX>), wide_grid(grid, kNTL), dim3(kNTL), lds, stream, p);
     return check_hip(hipGetLastError(), "launch k_project_lowp");
 }
 

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "sal_aux.h"
+#include "sal_grid.h"
 #include "sal_stage.h"
 
 namespace sal {
@@ -406,8 +407,7 @@ constexpr int fp32_waves_per_simd() { return N == 8 ? 8 : 4; }
 template <int N, int S, int CTW>
 __global__ __launch_bounds__(kNT, (fp32_waves_per_simd<N>())) void k_project_fp32(ProjParams p) {
     extern __shared__ float lds[];
-    const int64_t per = (p.ntiles + 7) / 8;
-    const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    const int64_t tile = xcd_block(p.ntiles);
     if (tile >= p.ntiles) return;
     project_tile_fp32<N, S, CTW>(p, tile, lds);
 }
@@ -446,8 +446,7 @@ __global__ __launch_bounds__(kNT, (fp32_waves_per_simd<N>())) void k_project_fp3
                                                              const int64_t* __restrict__ prefix, int nitems,
                                                              int64_t total) {
     extern __shared__ float lds[];
-    const int64_t per = (total + 7) / 8;
-    const int64_t g = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    const int64_t g = xcd_block(total);
     if (g >= total) return;
     int a = 0, b = nitems - 1;  // last item with prefix[item] <= g
     while (a < b) {
@@ -551,9 +550,9 @@ static sal_status launch_project(const ProjParams& p, size_t lds, hipStream_t st
         if (st) return st;
         attr_set = true;
     }
-    const int64_t grid = 8 * ((p.ntiles + 7) / 8);
-    if (grid > INT32_MAX) return fail(SAL_ERR_SHAPE, "volume too large for one launch");
-    hipLaunchKernelGGL((k_project_fp32<N, S, CTW>), dim3((unsigned)grid), dim3(kNT), lds, stream, p);
+    const int64_t grid = xcd_grid(p.ntiles);
+    if (!wide_grid_fits(grid, kNT)) return fail(SAL_ERR_SHAPE, "volume too large for one launch");
+    hipLaunchKernelGGL((k_project_fp32<N, S, CTW>), wide_grid(grid, kNT), dim3(kNT), lds, stream, p);
     return check_hip(hipGetLastError(), "launch k_project_fp32");
 }
 
@@ -576,9 +575,9 @@ static sal_status launch_batch(const void* items, const int64_t* prefix, int nit
     // the LDS attribute was set by project_fp32_batch_occupancy(), outside any stream capture
     if constexpr (fp32_batch_one_tile<N>()) {
         (void)grid;
-        const int64_t g1 = 8 * ((total + 7) / 8);
-        if (g1 > INT32_MAX) return fail(SAL_ERR_SHAPE, "batch too large for one launch");
-        hipLaunchKernelGGL((k_project_fp32_batch1<N, S, CTW>), dim3((unsigned)g1), dim3(kNT), lds, stream,
+        const int64_t g1 = xcd_grid(total);
+        if (!wide_grid_fits(g1, kNT)) return fail(SAL_ERR_SHAPE, "batch too large for one launch");
+        hipLaunchKernelGGL((k_project_fp32_batch1<N, S, CTW>), wide_grid(g1, kNT), dim3(kNT), lds, stream,
                            (const ProjParams*)items, prefix, nitems, total);
     } else {
         hipLaunchKernelGGL((k_project_fp32_batch<N, S, CTW>), dim3((unsigned)grid), dim3(kNT), lds, stream,

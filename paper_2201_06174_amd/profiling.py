@@ -25,7 +25,7 @@ CSRC = os.path.join(HERE, "csrc")
 
 # the sources of the FP32 feature kernel's code, launch shape and memory accesses (the
 # host-built constant tables change values, not traffic)
-FP32_KERNEL_SOURCES = ("sal_project.hip", "sal_stage.h", "sal_aux.h", "sal_internal.h")
+FP32_KERNEL_SOURCES = ("sal_project.hip", "sal_stage.h", "sal_grid.h", "sal_aux.h", "sal_internal.h")
 
 
 def source_digest(files=FP32_KERNEL_SOURCES) -> str:

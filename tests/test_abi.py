@@ -51,6 +51,7 @@ def _err(rc):
     (8, 1, 5, 0, (32, 32, 32), "SAL_ERR_ARG"),            # window
     (8, 1, 0, 9, (32, 32, 32), "SAL_ERR_ARG"),            # precision
     (16, 2, 0, 0, (7, 32, 32), "SAL_ERR_SHAPE"),          # axis shorter than n/2
+    (8, 1, 0, 0, (32, 0, 32), "SAL_ERR_SHAPE"),           # empty volume
 ])
 def test_project_rejects_bad_spec(n, s, window, prec, shape, code):
     lib = _lib.load()
@@ -78,6 +79,18 @@ def test_stencil_validation():
     assert _err(lib.sal_center_surround(E, 4, 4, 4, 1, st, S, None)) == "SAL_ERR_ARG"  # too many
     st, keep = _lib.make_stencil([[1, 0, 0]])
     assert _err(lib.sal_center_surround(E, 4, 4, 4, 1, st, E, None)) == "SAL_ERR_ARG"  # aliasing
+
+
+def test_empty_work_is_a_no_op():
+    """Zero centres and an empty grid are valid and launch nothing (no device needed)."""
+    lib = _lib.load()
+    sp = _lib.SalSpec(8, 1, 0, 0)
+    assert _err(lib.sal_local_spectra(None, 32, 32, 32, sp, None, 0, None, None)) == "SAL_OK"
+    assert _err(lib.sal_local_spectra(None, 32, 32, 32, sp, None, -1, None, None)) == "SAL_ERR_ARG"
+    st, keep = _lib.make_stencil([[1, 0, 0], [-1, 0, 0]])
+    E, S = ctypes.c_void_p(16), ctypes.c_void_p(32)
+    assert _err(lib.sal_center_surround(E, 0, 4, 4, 1, st, S, None)) == "SAL_OK"
+    assert _err(lib.sal_center_surround(E, -1, 4, 4, 1, st, S, None)) == "SAL_ERR_SHAPE"
 
 
 def test_fuse_validation():
