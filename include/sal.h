@@ -41,7 +41,8 @@ typedef struct ihipStream_t* sal_stream; /* a hipStream_t; NULL is the null stre
 typedef enum {
     SAL_OK = 0,
     SAL_ERR_ARG = 1,         /* bad pointer, size, or option value */
-    SAL_ERR_SHAPE = 2,       /* inconsistent shapes (e.g. an axis shorter than n/2) */
+    SAL_ERR_SHAPE = 2,       /* inconsistent shapes (e.g. an axis shorter than n/2), or more work
+                                than one launch holds (about 2^47 work-items: far beyond HBM) */
     SAL_ERR_UNSUPPORTED = 3, /* valid for the method, not built into this library (e.g. n = 10) */
     SAL_ERR_NOMEM = 4,       /* workspace too small or allocation failed */
     SAL_ERR_DEVICE = 5       /* a HIP runtime call failed */
