@@ -104,6 +104,26 @@ def test_backward_matches_oracle(torch_sal, shape, n, s, off, fusion, literal, w
     _check(gV, ref, amb, TOL_GRAD)
 
 
+def test_isolated_points(torch_sal):
+    """Degenerate stencil: every neighbour lies outside the 8^3 grid, so Q = 0 at every point,
+    S_m = 0 (Eq. 3 with no terms) and no gradient reaches V."""
+    torch, sal = torch_sal
+    print("isolated points (8, 8, 8) offset 8", flush=True)
+    shape, off = (8, 8, 8), synth.axis_stencil(8)
+    rng = np.random.default_rng(3)
+    V = rng.standard_normal(shape).astype(np.float32)
+    gS = rng.uniform(size=shape).astype(np.float32)
+    cfg = sal.Config(n=8, s=1, offsets=off, fusion="equal")
+    r = sal.saliency(_dev(torch, V), cfg)
+    gV = sal.backward(_dev(torch, V), cfg, r["E"], r["Sm"], r["W"], _dev(torch, gS)).cpu().numpy()
+    p = orc.Params(n=8, s=1, offsets=off, fusion="equal")
+    ref, W, fb = orc.backward(V, p, gS)
+    assert not np.any(ref)
+    assert not r["Sm"].cpu().numpy().any() and not r["S"].cpu().numpy().any()
+    assert not np.any(gV)
+    assert r["E"].abs().max().item() > 0
+
+
 def test_autograd_function(torch_sal):
     torch, sal = torch_sal
     shape = (20, 16, 18)
