@@ -41,12 +41,6 @@ struct LowpParams {
     float* E;
 };
 
-__device__ __forceinline__ int64_t reflect_clamp_l(int64_t p, int64_t N) {
-    if (p < 0) p = -1 - p;
-    if (p >= N) p = 2 * N - 1 - p;
-    return p < 0 ? 0 : (p >= N ? N - 1 : p);
-}
-
 template <int PREC>
 struct Lp;
 

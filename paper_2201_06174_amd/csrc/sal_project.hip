@@ -44,12 +44,6 @@ struct ProjParams {
     float* E;
 };
 
-__device__ __forceinline__ int64_t reflect_clamp(int64_t p, int64_t N) {
-    if (p < 0) p = -1 - p;
-    if (p >= N) p = 2 * N - 1 - p;
-    return p < 0 ? 0 : (p >= N ? N - 1 : p);
-}
-
 __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
