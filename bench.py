@@ -154,7 +154,8 @@ def precision_forms(torch, lib, Vd, w, fusion, Dd, Md, steps, done):
             del pp
         nwin = int(np.prod([-(-N // w.s) for N in Vd.shape]))
         forms[prec] = {"ms_per_step": round(m2, 4), "kernel_ms": round(k2, 4),
-                       "mvoxel_s": round(nvox / (m2 * 1e-3) / 1e6, 3), "graded": graded(w, nwin, prec, k2)}
+                       "mvoxel_s": round(nvox / (m2 * 1e-3) / 1e6, 3), "graded": graded(w, nwin, prec, k2),
+                       "mfma_counted": feature_mfma(w.name, prec, k2)}
     for prec in ("fp32", "split_bf16", "fp16"):
         forms[prec]["speedup_vs_fp32"] = round(forms["fp32"]["ms_per_step"] / forms[prec]["ms_per_step"], 3)
     return forms
@@ -197,7 +198,12 @@ def time_fwd_bwd(torch, w_name, steps, warmup):
         "fwd_ms": round(fwd, 4), "bwd_ms": round(bwd, 4),
         "fwd_bwd_mvoxel_s": round(nvox / ((fwd + bwd) * 1e-3) / 1e6, 3),
         "roofline": {"bound": "mfma", "t_roof_ms": round(t_roof, 4), "frac": round(t_roof / (fwd + bwd), 4),
-                     "peak_tflops": PEAK_FP32_MFMA_TFLOPS}}
+                     "peak_tflops": PEAK_FP32_MFMA_TFLOPS,
+                     # matrix-core work of the forward feature kernel and the spectral adjoint
+                     # counted by rocprofv3, over the whole forward + backward time
+                     "mfma_counted": stored_mfma("k_spectral_adjoint_grad_mfma.txt",
+                                                 ["k_project_fp32<8, 1, 1>", "k_spectral_adjoint<8, 1>"], "adjoint",
+                                                 fwd + bwd, PEAK_FP32_MFMA_TFLOPS)}}
 
 
 def time_batch(torch, lib, steps, count=96):
@@ -266,6 +272,40 @@ def stored_traffic(workload, precision):
     if not t or t.get("source_digest") != profiling.source_digest():
         return None
     return float(t["traffic_bytes_per_launch"])
+
+
+# committed rocprofv3 MFMA-counter summaries of the feature kernel: (workload, precision) ->
+# (file, kernel, source set)
+MFMA_PROFILES = {
+    ("survey", "fp32"): ("k_project_fp32_survey_mfma.txt", "k_project_fp32<16, 2, 1>", "fp32"),
+    ("survey", "split_bf16"): ("k_project_lowp_survey_split_bf16_mfma.txt", "k_project_lowp<16, 2, 1, 1, true>",
+                               "lowp"),
+    ("survey", "fp16"): ("k_project_lowp_survey_fp16_mfma.txt", "k_project_lowp<16, 2, 2, 1, true>", "lowp"),
+}
+
+
+def feature_mfma(workload, precision, kern_ms):
+    if (workload, precision) not in MFMA_PROFILES:
+        return None
+    fname, kernel, sources = MFMA_PROFILES[(workload, precision)]
+    peak = PEAK_FP32_MFMA_TFLOPS if precision == "fp32" else PEAK_BF16_MFMA_TFLOPS
+    return stored_mfma(fname, [kernel], sources, kern_ms, peak)
+
+
+def stored_mfma(fname, kernels, sources, ms, peak_tflops):
+    """Matrix-core flops per launch counted by rocprofv3 (SQ_INSTS_VALU_MFMA_MOPS_*) from a
+    committed summary, summed over `kernels`, as a rate over `ms` against the precision's
+    peak; None when the summary is missing or its kernels changed since."""
+    from paper_2201_06174_amd import profiling
+    tot = 0.0
+    for k in kernels:
+        f = profiling.read_mfma(os.path.join(TRAFFIC_DIR, fname), k, sources)
+        if f is None:
+            return None
+        tot += f
+    t = tot / (ms * 1e-3) / 1e12
+    return {"counted_flops": tot, "tflops": round(t, 3), "peak": peak_tflops, "frac": round(t / peak_tflops, 4),
+            "profile": "profiles/" + fname}
 
 
 def traffic_pass(torch, pipe):
@@ -363,7 +403,8 @@ def main():
                      "frac": round(achieved / peak, 4), "traffic": stored_traffic(args.workload, args.precision),
                      "kernel": "%s (sal_project)" % kname, "kernel_ms": round(kern_ms, 4),
                      "flops_per_window": algorithmic_flops_per_window(w.n),
-                     "graded": graded(w, nwin, args.precision, kern_ms)},
+                     "graded": graded(w, nwin, args.precision, kern_ms),
+                     "mfma_counted": feature_mfma(args.workload, args.precision, kern_ms)},
     }
     if not args.no_extra:
         extra = {}

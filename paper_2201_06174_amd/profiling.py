@@ -2,6 +2,7 @@
 
     python -m paper_2201_06174_amd.profiling stats DB TITLE COMMAND > profiles/NAME.md
     python -m paper_2201_06174_amd.profiling traffic FETCH_DB WRITE_DB KERNEL COPY_BYTES COMMAND > profiles/NAME.txt
+    python -m paper_2201_06174_amd.profiling mfma DB SOURCES KERNEL [KERNEL ...] -- COMMAND > profiles/NAME.txt
 
 ``stats`` renders the kernel-trace statistics table of one ``--kernel-trace --stats``
 run.  ``traffic`` combines one ``--pmc FETCH_SIZE`` and one ``--pmc WRITE_SIZE`` run of
@@ -10,7 +11,10 @@ COPY_BYTES bytes (it reads and writes exactly that many bytes), then the timed
 feature kernel.  Each counter of the feature kernel is scaled by COPY_BYTES over what
 the same counter reads for the copy, and the result is stored together with a
 digest of the kernel's source files, so a later change of the kernel makes the
-stored figure stale (bench.py then reports the traffic as null).
+stored figure stale (bench.py then reports the traffic as null).  ``mfma`` reads one run with
+the MFMA_COUNTERS and stores, per named kernel, the matrix-core flops the hardware counted for
+one launch (SQ_INSTS_VALU_MFMA_MOPS_* count multiply and add operations in units of 512), with
+the digest of the source set SOURCES (fp32, lowp or adjoint).
 """
 from __future__ import annotations
 
@@ -26,6 +30,15 @@ CSRC = os.path.join(HERE, "csrc")
 # the sources of the FP32 feature kernel's code, launch shape and memory accesses (the
 # host-built constant tables change values, not traffic)
 FP32_KERNEL_SOURCES = ("sal_project.hip", "sal_stage.h", "sal_grid.h", "sal_aux.h", "sal_internal.h")
+
+
+LOWP_KERNEL_SOURCES = ("sal_lowp.hip", "sal_stage.h", "sal_grid.h", "sal_aux.h", "sal_internal.h")
+ADJOINT_SOURCES = FP32_KERNEL_SOURCES + ("sal_backward.hip", "sal_device.h")
+SOURCE_SETS = {"fp32": FP32_KERNEL_SOURCES, "lowp": LOWP_KERNEL_SOURCES, "adjoint": ADJOINT_SOURCES}
+
+# one rocprofv3 --pmc pass: 5 SQ counters and 1 GRBM counter
+MFMA_COUNTERS = ("SQ_INSTS_VALU_MFMA_MOPS_F32", "SQ_INSTS_VALU_MFMA_MOPS_BF16", "SQ_INSTS_VALU_MFMA_MOPS_F16",
+                 "SQ_VALU_MFMA_BUSY_CYCLES", "SQ_BUSY_CYCLES", "GRBM_GUI_ACTIVE")
 
 
 def source_digest(files=FP32_KERNEL_SOURCES) -> str:
@@ -130,6 +143,39 @@ def traffic_text(fetch_db, write_db, kernel, copy_bytes, command) -> str:
     return "\n".join(lines) + "\n"
 
 
+def mfma_text(db, sources, kernels, command) -> str:
+    """Matrix-core flops per launch of each kernel (mean over its dispatches in the run)."""
+    per = {c: counter_per_dispatch(db, c) for c in MFMA_COUNTERS}
+    lines = ["# Matrix-core work per launch, counted by the hardware", "command: %s" % command]
+    for k in kernels:
+        name, mops = None, 0.0
+        for c in ("SQ_INSTS_VALU_MFMA_MOPS_F32", "SQ_INSTS_VALU_MFMA_MOPS_BF16", "SQ_INSTS_VALU_MFMA_MOPS_F16"):
+            hits = {n: v for n, v in per[c].items() if k in n}
+            if hits:
+                n, v = max(hits.items(), key=lambda kv: sum(kv[1]) / len(kv[1]))
+                name = n
+                mops += sum(v) / len(v)
+        if name is None:
+            raise KeyError("no dispatch of a kernel matching %r" % k)
+        busy = per["SQ_VALU_MFMA_BUSY_CYCLES"].get(name, [0.0])
+        key = k.replace(" ", "")
+        lines += ["%s.kernel_name: %s" % (key, name),
+                  "%s.dispatches: %d" % (key, len(busy)),
+                  "%s.mfma_flops_per_launch: %.0f" % (key, 512.0 * mops),
+                  "%s.mfma_busy_cycles_per_launch: %.0f" % (key, sum(busy) / len(busy))]
+    lines.append("source_digest: %s" % source_digest(SOURCE_SETS[sources]))
+    return "\n".join(lines) + "\n"
+
+
+def read_mfma(path, kernel, sources):
+    """Stored matrix-core flops per launch of `kernel`, or None when missing or stale."""
+    t = read_traffic(path)
+    if not t or t.get("source_digest") != source_digest(SOURCE_SETS[sources]):
+        return None
+    v = t.get("%s.mfma_flops_per_launch" % kernel.replace(" ", ""))
+    return float(v) if v is not None else None
+
+
 def read_traffic(path):
     """Parsed key/value lines of a stored traffic summary, or None."""
     if not os.path.exists(path):
@@ -146,6 +192,10 @@ def read_traffic(path):
 def main(argv):
     if len(argv) >= 4 and argv[0] == "stats":
         sys.stdout.write(stats_markdown(argv[1], argv[2], argv[3]))
+        return 0
+    if len(argv) >= 5 and argv[0] == "mfma" and "--" in argv:
+        cut = argv.index("--")
+        sys.stdout.write(mfma_text(argv[1], argv[2], argv[3:cut], " ".join(argv[cut + 1:])))
         return 0
     if len(argv) >= 6 and argv[0] == "traffic":
         sys.stdout.write(traffic_text(argv[1], argv[2], argv[3], int(argv[4]), argv[5]))
