@@ -1,12 +1,13 @@
 """Maximum-size case: a volume whose grid planes (3 x 720 x 1024 x 1024 floats) and adjoint
 tile workspace exceed 2^31 elements, so every kernel of the forward and the adjoint runs
-its 64-bit index form.  Two checks that hold at any size:
+its 64-bit index form.  Checks that hold at any size:
 
 * locality: each output at distance >= 16 from the borders of a 64^3 crop depends only on
   samples inside the crop (window half-width 4, stencil reach 4 twice through the center-
   surround adjoint, half-width 4 again for the adjoint synthesis), so the large run and a run
   on the crop alone (32-bit index forms, tiles aligned the same way) agree there;
-* oracle samples: E at a few interior centres against the FP64 oracle on the crop.
+* oracle samples: E at a few interior centres against the FP64 oracle on the crop;
+* the split-BF16 and FP16 feature kernels, large volume against crop.
 
 Equal fusion keeps W independent of the volume.  The inputs are drawn on the device from a
 seeded generator; about 100 GB of device memory is used."""
@@ -77,5 +78,15 @@ def test_int64_paths_match_crop_and_oracle(torch_sal):
     print("  E vs oracle at 8 centres: %.2e" % err, flush=True)
     assert err <= 1e-5
 
-    del V, gS, r, gV, rc, gVc
+    # the reduced-precision feature kernels take the same 64-bit paths
+    del gV, gVc
+    for prec in ("split_bf16", "fp16"):
+        El = sal.project(V, 8, 1, "hann", prec)
+        Ec = sal.project(Vc, 8, 1, "hann", prec)
+        e = _rel(El[(slice(None),) + inner], Ec[(slice(None),) + ci])
+        print("  %s features, large vs crop: %.2e" % (prec, e), flush=True)
+        assert e <= 1e-6
+        del El, Ec
+
+    del V, gS, r, rc
     torch.cuda.empty_cache()
