@@ -81,14 +81,9 @@ sal_status launch_local_spectra(const float* V, int64_t T, int64_t IL, int64_t X
                                 const int32_t* centers, int64_t cnt, float* F, hipStream_t stream) {
     if (cnt == 0) return SAL_OK;
     const size_t lds = sizeof(float) * (4 * (size_t)n * n * n + 2 * n * n + n);
-    static bool attr = false;
-    if (!attr) {
-        sal_status st = check_hip(hipFuncSetAttribute((const void*)k_local_spectra,
-                                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024),
-                                  "hipFuncSetAttribute(local_spectra)");
-        if (st) return st;
-        attr = true;
-    }
+    static std::atomic<uint64_t> attr{0};
+    sal_status st = lds_limit_once((const void*)k_local_spectra, 160 * 1024, attr, "hipFuncSetAttribute(local_spectra)");
+    if (st) return st;
     if (!wide_grid_fits(cnt, 256)) return fail(SAL_ERR_SHAPE, "too many centres for one launch");
     hipLaunchKernelGGL(k_local_spectra, wide_grid(cnt, 256), dim3(256), lds, stream, V, T, IL, XL, n, window, centers,
                        cnt, F);

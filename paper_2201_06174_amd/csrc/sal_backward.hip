@@ -642,14 +642,10 @@ static sal_status adj_layout_dispatch(int n, int s, int64_t T, int64_t IL, int64
 
 template <int N, int S>
 static sal_status launch_adj(const AdjParams& p, const AdjLayout& L, hipStream_t stream) {
-    static bool attr = false;
-    if (!attr) {
-        sal_status st = check_hip(hipFuncSetAttribute((const void*)k_spectral_adjoint<N, S>,
-                                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024),
-                                  "hipFuncSetAttribute(adjoint)");
-        if (st) return st;
-        attr = true;
-    }
+    static std::atomic<uint64_t> attr{0};
+    sal_status st = lds_limit_once((const void*)k_spectral_adjoint<N, S>, 160 * 1024, attr,
+                                   "hipFuncSetAttribute(adjoint)");
+    if (st) return st;
     const int64_t grid = xcd_grid(L.ntiles);
     if (!wide_grid_fits(grid, 512)) return fail(SAL_ERR_SHAPE, "volume too large for one launch");
     hipLaunchKernelGGL((k_spectral_adjoint<N, S>), wide_grid(grid, 512), dim3(512), L.lds, stream, p);

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <string>
 
@@ -15,6 +16,20 @@ namespace sal {
 void set_error(const std::string& msg);
 sal_status fail(sal_status code, const std::string& msg);
 sal_status check_hip(hipError_t e, const char* what);
+
+// Raises the dynamic-LDS limit of `kernel` to `bytes` on the current device, once per device
+// (`done` holds a bit per device id below 64).  The attribute call is idempotent, so two
+// threads racing on the first launch only repeat it.
+inline sal_status lds_limit_once(const void* kernel, int bytes, std::atomic<uint64_t>& done, const char* what) {
+    int dev = 0;
+    sal_status st = check_hip(hipGetDevice(&dev), "hipGetDevice");
+    if (st) return st;
+    const uint64_t bit = dev >= 0 && dev < 64 ? uint64_t(1) << dev : 0;
+    if (bit && (done.load(std::memory_order_acquire) & bit)) return SAL_OK;
+    st = check_hip(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes), what);
+    if (!st && bit) done.fetch_or(bit, std::memory_order_release);
+    return st;
+}
 
 // ---------------------------------------------------------------- shapes
 

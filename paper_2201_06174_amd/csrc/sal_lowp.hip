@@ -697,12 +697,10 @@ static sal_status set_lds_attr_l(K kernel, const char* what) {
 
 template <int N, int S, int PREC, int CTW, bool FIX>
 static sal_status launch_lowp_k(const LowpParams& p, size_t lds, hipStream_t stream) {
-    static bool attr = false;
-    if (!attr) {
-        sal_status st = set_lds_attr_l(k_project_lowp<N, S, PREC, CTW, FIX>, "hipFuncSetAttribute(project lowp)");
-        if (st) return st;
-        attr = true;
-    }
+    static std::atomic<uint64_t> attr{0};
+    sal_status st = lds_limit_once((const void*)k_project_lowp<N, S, PREC, CTW, FIX>, (int)kLdsMaxL, attr,
+                                   "hipFuncSetAttribute(project lowp)");
+    if (st) return st;
     const int64_t grid = xcd_grid(p.ntiles);
     if (!wide_grid_fits(grid, kNTL)) return fail(SAL_ERR_SHAPE, "volume too large for one launch");
     hipLaunchKernelGGL((k_project_lowp<N, S, PREC, CTW, FIX>), wide_grid(grid, kNTL), dim3(kNTL), lds, stream, p);

@@ -538,12 +538,10 @@ static sal_status set_lds_attr(K kernel, const char* what) {
 
 template <int N, int S, int CTW>
 static sal_status launch_project(const ProjParams& p, size_t lds, hipStream_t stream) {
-    static bool attr_set = false;
-    if (!attr_set) {
-        sal_status st = set_lds_attr(k_project_fp32<N, S, CTW>, "hipFuncSetAttribute(project)");
-        if (st) return st;
-        attr_set = true;
-    }
+    static std::atomic<uint64_t> attr{0};
+    sal_status st = lds_limit_once((const void*)k_project_fp32<N, S, CTW>, (int)kLdsMax, attr,
+                                   "hipFuncSetAttribute(project)");
+    if (st) return st;
     const int64_t grid = xcd_grid(p.ntiles);
     if (!wide_grid_fits(grid, kNT)) return fail(SAL_ERR_SHAPE, "volume too large for one launch");
     hipLaunchKernelGGL((k_project_fp32<N, S, CTW>), wide_grid(grid, kNT), dim3(kNT), lds, stream, p);
