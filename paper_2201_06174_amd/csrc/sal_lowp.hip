@@ -165,6 +165,14 @@ __host__ __device__ constexpr int lowp_rtp(int CT, int s) {
     return 2 * R;
 }
 
+// Offset between the real and imaginary planes of a pass output, in 16-bit samples: the
+// plane size rounded up to 16 modulo 32 dwords.  The two planes then start in opposite
+// halves of the 32 LDS banks, so the lane groups of a wave that read both planes at the same
+// position (rows of 16 consecutive banks, or of an odd dword pitch) never share a bank.
+__host__ __device__ constexpr int plane_pitch16(int n16) {
+    return 2 * (n16 / 2 + (16 - (n16 / 2) % 32 + 32) % 32);
+}
+
 // Sum over the 16 lanes of a DPP row (the bins kt of one lane group): rotations by 8, 4, 2
 // and 1 within the row leave the total in every lane, without a trip through LDS.
 __device__ __forceinline__ float row_sum16(float x) {
@@ -242,12 +250,13 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
     constexpr int NVP = L::split ? 2 : 1;
     const size_t vbytes = FIX ? (size_t)NVP * FG.VP * 2 : (((size_t)RT * RI * RXp + 3) & ~(size_t)3) * 4;
     uint16_t* Ab = (uint16_t*)((char*)lds + vbytes);                      // [NPL][RTe][IQ2][4][2]
-    const int abPlane = RTe * IQ2 * 8;
-    uint16_t* Gh = Ab + (size_t)NPL * abPlane;                          // [2][N][16][RTp]
-    uint16_t* Gl = Gh + (size_t)2 * N * 16 * RTp;                        // same, lo parts (split only)
-    float4* Wl = (float4*)(Gl + (L::split ? (size_t)2 * N * 16 * RTp : 0));  // [N][16] weights of this kx
+    const int abPlane = plane_pitch16(RTe * IQ2 * 8);
+    const int gStrideRi = N * 16 * RTp;         // one plane [N][16][RTp]
+    const int gPlane = plane_pitch16(gStrideRi);  // real plane to imaginary plane
+    uint16_t* Gh = Ab + (size_t)NPL * abPlane;                          // [re, im][N][16][RTp]
+    uint16_t* Gl = Gh + (size_t)gPlane + gStrideRi;                      // same, lo parts (split only)
+    float4* Wl = (float4*)(Gl + (L::split ? (size_t)gPlane + gStrideRi : 0));  // [N][16] weights of this kx
     const int gRow = RTp;  // one (ri, u, col) sample row; RTp is even, rows stay 4-byte aligned
-    const int gStrideRi = N * 16 * RTp;
 
     const int64_t t0 = tt * CT * s - N / 2, i0 = ti * 4 * s - N / 2, x0 = tx * 4 * s - N / 2;
     if constexpr (FIX) {
@@ -292,26 +301,34 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
     for (int e = tid; e < 2 * N * 16 * (RTp - RT); e += kNTL) {
         const int pad = RTp - RT;
         const int r = e / pad, k = RT + e % pad;
-        Gh[r * RTp + k] = 0;
-        if constexpr (L::split) Gl[r * RTp + k] = 0;
+        const int at = (r >= N * 16 ? gPlane - gStrideRi : 0) + r * RTp + k;
+        Gh[at] = 0;
+        if constexpr (L::split) Gl[at] = 0;
     }
 
-    // DFT operands: lane supplies bin = col, K slots 8*grp .. 8*grp+7
+    // The K slots of passes B and C are (channel, sample): K = 16 * half + b0 + i, half = the
+    // real or imaginary plane of the data, b0 + i the sample.  Lane group grp takes half =
+    // grp & 1 and b0 = 8 (grp >> 1), so the 32 lanes that the LDS serves together read the two
+    // planes at the same sample offset (no bank shared, see plane_pitch16).
+    const int half = grp & 1;
+    const int b0 = 8 * (grp >> 1);
+    const int kslot = 16 * half + b0;
+    // DFT operands: lane supplies bin = col, K slots kslot .. kslot + 7
     vec are_h, are_l, aim_h, aim_l;
     {
         uint16_t b[8];
 #pragma unroll
-        for (int i = 0; i < 8; i++) b[i] = p.cpx_a[(0 * 16 + col) * 32 + 8 * grp + i];
+        for (int i = 0; i < 8; i++) b[i] = p.cpx_a[(0 * 16 + col) * 32 + kslot + i];
         are_h = L::from_bits(b);
 #pragma unroll
-        for (int i = 0; i < 8; i++) b[i] = p.cpx_a[(1 * 16 + col) * 32 + 8 * grp + i];
+        for (int i = 0; i < 8; i++) b[i] = p.cpx_a[(1 * 16 + col) * 32 + kslot + i];
         aim_h = L::from_bits(b);
         if constexpr (L::split) {
 #pragma unroll
-            for (int i = 0; i < 8; i++) b[i] = p.cpx_b[(0 * 16 + col) * 32 + 8 * grp + i];
+            for (int i = 0; i < 8; i++) b[i] = p.cpx_b[(0 * 16 + col) * 32 + kslot + i];
             are_l = L::from_bits(b);
 #pragma unroll
-            for (int i = 0; i < 8; i++) b[i] = p.cpx_b[(1 * 16 + col) * 32 + 8 * grp + i];
+            for (int i = 0; i < 8; i++) b[i] = p.cpx_b[(1 * 16 + col) * 32 + kslot + i];
             aim_l = L::from_bits(b);
         } else {
             are_l = are_h;
@@ -335,9 +352,6 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
     for (int c = 0; c < CTW; c++)
 #pragma unroll
         for (int j = 0; j < 4; j++) acc[c][j][0] = acc[c][j][1] = acc[c][j][2] = 0.f;
-
-    const int half = grp >> 1;       // 0: real part samples, 1: imaginary part samples
-    const int b0 = 8 * (grp & 1);    // first sample of this lane's K slots
 
     __syncthreads();
 
@@ -457,14 +471,14 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
                     const int u = 4 * grp + j;
                     if (u < N) {
                         uint32_t* gre = (uint32_t*)(Gh + (u * 16 + col) * gRow) + pi;
-                        uint32_t* gim = (uint32_t*)(Gh + gStrideRi + (u * 16 + col) * gRow) + pi;
+                        uint32_t* gim = (uint32_t*)(Gh + gPlane + (u * 16 + col) * gRow) + pi;
                         const uint32_t rh = L::pack_hi(dre[0][j], dre[1][j]);
                         const uint32_t ih = L::pack_hi(dim[0][j], dim[1][j]);
                         *gre = rh;
                         *gim = ih;
                         if constexpr (L::split) {
                             uint32_t* lre = (uint32_t*)(Gl + (u * 16 + col) * gRow) + pi;
-                            uint32_t* lim = (uint32_t*)(Gl + gStrideRi + (u * 16 + col) * gRow) + pi;
+                            uint32_t* lim = (uint32_t*)(Gl + gPlane + (u * 16 + col) * gRow) + pi;
                             *lre = L::pack_lo(dre[0][j], dre[1][j], rh);
                             *lim = L::pack_lo(dim[0][j], dim[1][j], ih);
                         }
@@ -484,8 +498,8 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
             const int tc = wtc + 8 * c;
             if (tc >= CT) break;
             const int ts = tc * s + b0;
-            const uint16_t* ghb = Gh + half * gStrideRi + col * gRow;
-            const uint16_t* glb = Gl + half * gStrideRi + col * gRow;
+            const uint16_t* ghb = Gh + half * gPlane + col * gRow;
+            const uint16_t* glb = Gl + half * gPlane + col * gRow;
             auto run = [&](auto odd, auto count) {
                 constexpr bool ODD = decltype(odd)::value;
                 constexpr int CNT = decltype(count)::value;
@@ -627,8 +641,9 @@ static size_t lowp_lds_bytes(int n, int s, int CT, bool split, LowpParams* p) {
     p->RXp = p->RX | 1;
     p->IQ2 = ab_iq2(s);
     const size_t RTe = (size_t)((p->RT + 1) & ~1);
-    const size_t ab = (split ? 4 : 2) * RTe * p->IQ2 * 8;
-    const size_t g = std::max<size_t>((size_t)2 * n * 16 * p->RTp * (split ? 2 : 1), 8 * 16 * 3 * 2 * 2);
+    const size_t ab = (split ? 4 : 2) * (size_t)plane_pitch16((int)RTe * p->IQ2 * 8);
+    const size_t plane = (size_t)n * 16 * p->RTp;
+    const size_t g = std::max<size_t>((plane + plane_pitch16((int)plane)) * (split ? 2 : 1), 8 * 16 * 3 * 2 * 2);
     if (lowp_fixed(n, s, CT)) {
         // 16-bit staged planes, no weight staging
         const FixGeom fg = fix_geom(n, s, CT);
