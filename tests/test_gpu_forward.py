@@ -57,6 +57,12 @@ CASES = [
     ((40, 9, 13), 4, 1, "hann"),
     ((8, 8, 8), 16, 7, "hann"),      # each axis exactly n/2 long, largest stride
     ((4, 5, 6), 8, 1, "rect"),       # minimal extents
+    # strides without a compile-time instance (run-time stride), over several tiles
+    ((41, 35, 44), 16, 5, "hann"),
+    ((33, 38, 29), 12, 4, "hann"),
+    ((35, 28, 33), 16, 3, "hann"),
+    ((27, 31, 22), 12, 1, "rect"),
+    ((26, 21, 30), 4, 1, "rect"),
 ]
 
 

@@ -32,7 +32,9 @@ CASES = [((37, 29, 23), 8, 1, "hann"), ((30, 41, 27), 8, 2, "hann"), ((45, 26, 3
          ((40, 9, 13), 4, 1, "hann"), ((8, 8, 8), 16, 7, "hann"),
          # split-bf16 at n = 16, s = 3 takes a shallower tile than the full depth (LDS), the
          # general kernel with a compile-time stride; fp16 keeps the full-depth one
-         ((50, 23, 29), 16, 3, "hann")]
+         ((50, 23, 29), 16, 3, "hann"),
+         # a run-time stride (no compile-time instance) over several tiles
+         ((33, 38, 29), 12, 4, "hann"), ((41, 35, 44), 16, 5, "hann")]
 
 
 @pytest.mark.parametrize("precision", ["split_bf16", "fp16"])
