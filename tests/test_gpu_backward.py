@@ -72,6 +72,7 @@ CASES = [
     ((20, 18, 17), 16, 1, synth.axis_stencil(8), "adapt_ls", False, "hann"),
     ((26, 22, 19), 12, 2, synth.axis_stencil(6), "equal", False, "hann"),
     ((25, 24, 23), 12, 3, synth.axis_stencil(6), "fixed", False, "hann"),
+    ((23, 19, 21), 12, 1, synth.cube_stencil(3), "adapt_ls", False, "hann"),
     ((13, 10, 9), 4, 1, synth.axis_stencil(2), "equal", False, "hann"),
     ((8, 9, 8), 16, 2, synth.axis_stencil(2), "equal", False, "hann"),   # axes of n/2 voxels
     # one-sided stencils (no offset pairs with its negation), both forms of Eq. 3
