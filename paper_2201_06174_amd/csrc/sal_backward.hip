@@ -33,7 +33,21 @@ __device__ __forceinline__ void lds_fence() { asm volatile("s_waitcnt lgkmcnt(0)
 // wave sees that write without waiting for it first.
 __device__ __forceinline__ void lds_order() { asm volatile("" ::: "memory"); }
 
-constexpr int kAdjCT = 8;  // t-centres per adjoint tile (one per wave in the t-slot loops)
+// LDS floats of an adjoint tile of CT t-centres (with or without the separate inverse buffer)
+constexpr size_t adj_base_floats(int N, int S, int CT) {
+    const size_t RT = (size_t)(CT - 1) * S + N, RI = (size_t)3 * S + N, RXp = (size_t)(3 * S + N) | 1;
+    return ((RT * RI * RXp + 3) & ~(size_t)3) + 2 * RT * RI * 4 + 2 * (size_t)N * RT * 16 +
+           (size_t)(N / 2 + 1) * N * 2 + (size_t)CT * 16 * 3;
+}
+constexpr size_t adj_band_floats(int N, int CT) { return N == 8 ? (size_t)CT / 2 * 4 * 64 + 8 * 64 : 0; }
+
+// t-centres per adjoint tile: 8, or the deepest of 4, 2, 1 whose tile fits the LDS (wide
+// strides of n = 12 and 16)
+constexpr int adj_ct(int N, int S) {
+    for (int CT = 8; CT > 1; CT /= 2)
+        if ((adj_base_floats(N, S, CT) + adj_band_floats(N, CT)) * sizeof(float) <= 160 * 1024) return CT;
+    return 1;
+}
 
 struct AdjParams {
     const float* V;
@@ -50,7 +64,7 @@ struct AdjParams {
 
 template <int N, int S>
 struct AdjGeom {
-    static constexpr int CT = kAdjCT;
+    static constexpr int CT = adj_ct(N, S);
     static constexpr int KH = N / 2 + 1;
     static constexpr int NK = N / 4;
     static constexpr int RT = (CT - 1) * S + N;
@@ -58,13 +72,11 @@ struct AdjGeom {
     static constexpr int RX = 3 * S + N;
     static constexpr int RXp = RX | 1;
     static constexpr int ROWS = (RT * RI + 511) / 512;
-    static constexpr size_t base_floats = (((size_t)RT * RI * RXp + 3) & ~(size_t)3) + 2 * (size_t)RT * RI * 4 +
-                                          2 * (size_t)N * RT * 16 +
-                                          (size_t)KH * N * 2 + (size_t)CT * 16 * 3;
+    static constexpr size_t base_floats = adj_base_floats(N, S, CT);
     // SEP: the inverse pass C accumulates into a buffer of its own, so each t-centre's
     // forward contraction, Y and inverse contraction run back to back (few live registers)
     static constexpr bool SEP = (base_floats + 2 * (size_t)N * RT * 16) * sizeof(float) <= 160 * 1024;
-    static constexpr size_t lds_floats = base_floats + (SEP ? 2 * (size_t)N * RT * 16 : 0) + (N == 8 ? CT / 2 * 4 * 64 + 8 * 64 : 0);
+    static constexpr size_t lds_floats = base_floats + (SEP ? 2 * (size_t)N * RT * 16 : 0) + adj_band_floats(N, CT);
     // PAIR (n = 8): the 8 packed rows of an n = 8 transform fill half of a 16-row matrix
     // operand, so pass C takes two t-centres per contraction: rows 8..15 hold the second
     // centre's (banded, K = n + s samples; block-diagonal for the inverse)
@@ -81,10 +93,12 @@ struct AdjGeom {
 
 // With a separate inverse buffer two tiles share a CU (4 waves per SIMD, at most 128
 // registers each), three for n = 8 at s <= 2 (6 waves, at most 85 registers; its LDS tile
-// is 45 KB); otherwise the t-centres' Y values stay live and one tile takes the CU.
+// is 45 KB); otherwise, or where a thread's synthesis accumulators (ROWS x RX registers)
+// are many, one tile takes the CU.
 template <int N, int S>
 constexpr int adj_waves_per_simd() {
-    return AdjGeom<N, S>::SEP ? (N <= 8 && S <= 2 ? 6 : 4) : 2;
+    using Gm = AdjGeom<N, S>;
+    return Gm::SEP && Gm::ROWS * Gm::RX <= 40 ? (N <= 8 && S <= 2 ? 6 : 4) : 2;
 }
 
 template <int N, int S>
@@ -609,7 +623,7 @@ __global__ __launch_bounds__(256) void k_gather(GatherParams p) {
 }
 
 struct AdjLayout {
-    int RT, RI, RX;
+    int CT, RT, RI, RX;
     int64_t tilesT, tilesI, tilesX, ntiles;
     size_t lds;
     size_t part_bytes;
@@ -619,7 +633,7 @@ template <int N, int S>
 static AdjLayout adj_layout(int64_t T, int64_t IL, int64_t XL) {
     using Gm = AdjGeom<N, S>;
     AdjLayout L;
-    L.RT = Gm::RT; L.RI = Gm::RI; L.RX = Gm::RX;
+    L.CT = Gm::CT; L.RT = Gm::RT; L.RI = Gm::RI; L.RX = Gm::RX;
     L.tilesT = ceil_div(ceil_div(T, S), Gm::CT);
     L.tilesI = ceil_div(ceil_div(IL, S), 4);
     L.tilesX = ceil_div(ceil_div(XL, S), 4);
@@ -634,10 +648,11 @@ static sal_status adj_layout_dispatch(int n, int s, int64_t T, int64_t IL, int64
     if (n == NN && s == SS) { *L = adj_layout<NN, SS>(T, IL, XL); return SAL_OK; }
     SAL_ADJ_CASE(4, 1)
     SAL_ADJ_CASE(8, 1) SAL_ADJ_CASE(8, 2) SAL_ADJ_CASE(8, 3)
-    SAL_ADJ_CASE(12, 1) SAL_ADJ_CASE(12, 2) SAL_ADJ_CASE(12, 3)
-    SAL_ADJ_CASE(16, 1) SAL_ADJ_CASE(16, 2)
+    SAL_ADJ_CASE(12, 1) SAL_ADJ_CASE(12, 2) SAL_ADJ_CASE(12, 3) SAL_ADJ_CASE(12, 4) SAL_ADJ_CASE(12, 5)
+    SAL_ADJ_CASE(16, 1) SAL_ADJ_CASE(16, 2) SAL_ADJ_CASE(16, 3) SAL_ADJ_CASE(16, 4) SAL_ADJ_CASE(16, 5)
+    SAL_ADJ_CASE(16, 6) SAL_ADJ_CASE(16, 7)
 #undef SAL_ADJ_CASE
-    return fail(SAL_ERR_UNSUPPORTED, "adjoint built for n = 4 (s = 1), n = 8 and 12 (s <= 3) and n = 16 (s <= 2)");
+    return fail(SAL_ERR_UNSUPPORTED, "adjoint built for n in {4, 8, 12, 16} and 1 <= s < n/2");
 }
 
 template <int N, int S>
@@ -657,8 +672,9 @@ static sal_status launch_adj_dispatch(int n, int s, const AdjParams& p, const Ad
     if (n == NN && s == SS) return launch_adj<NN, SS>(p, L, stream);
     SAL_ADJ_CASE(4, 1)
     SAL_ADJ_CASE(8, 1) SAL_ADJ_CASE(8, 2) SAL_ADJ_CASE(8, 3)
-    SAL_ADJ_CASE(12, 1) SAL_ADJ_CASE(12, 2) SAL_ADJ_CASE(12, 3)
-    SAL_ADJ_CASE(16, 1) SAL_ADJ_CASE(16, 2)
+    SAL_ADJ_CASE(12, 1) SAL_ADJ_CASE(12, 2) SAL_ADJ_CASE(12, 3) SAL_ADJ_CASE(12, 4) SAL_ADJ_CASE(12, 5)
+    SAL_ADJ_CASE(16, 1) SAL_ADJ_CASE(16, 2) SAL_ADJ_CASE(16, 3) SAL_ADJ_CASE(16, 4) SAL_ADJ_CASE(16, 5)
+    SAL_ADJ_CASE(16, 6) SAL_ADJ_CASE(16, 7)
 #undef SAL_ADJ_CASE
     return fail(SAL_ERR_UNSUPPORTED, "adjoint not built for this window/stride");
 }
@@ -750,7 +766,7 @@ sal_status sal_backward(const float* V, int64_t T, int64_t IL, int64_t XL, const
     gp.gV = gV_out;
     gp.N3[0] = T; gp.N3[1] = IL; gp.N3[2] = XL;
     gp.tiles[0] = L.tilesT; gp.tiles[1] = L.tilesI; gp.tiles[2] = L.tilesX;
-    gp.C[0] = kAdjCT; gp.C[1] = 4; gp.C[2] = 4;
+    gp.C[0] = L.CT; gp.C[1] = 4; gp.C[2] = 4;
     gp.R[0] = L.RT; gp.R[1] = L.RI; gp.R[2] = L.RX;
     gp.n = spec->n;
     gp.s = s;

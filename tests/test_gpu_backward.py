@@ -75,6 +75,14 @@ CASES = [
     ((23, 19, 21), 12, 1, synth.cube_stencil(3), "adapt_ls", False, "hann"),
     ((13, 10, 9), 4, 1, synth.axis_stencil(2), "equal", False, "hann"),
     ((8, 9, 8), 16, 2, synth.axis_stencil(2), "equal", False, "hann"),   # axes of n/2 voxels
+    # wide strides: shallower adjoint tiles (4, 2 or 1 t-centres) that fit the LDS
+    ((37, 33, 35), 12, 4, synth.axis_stencil(8), "equal", False, "hann"),
+    ((33, 36, 31), 12, 5, synth.cube_stencil(5), "adapt_ls", False, "hann"),
+    ((34, 31, 36), 16, 3, synth.axis_stencil(6), "equal", False, "hann"),
+    ((39, 34, 37), 16, 4, synth.cube_stencil(8), "fixed", False, "hann"),
+    ((41, 38, 36), 16, 5, synth.axis_stencil(10), "equal", True, "rect"),
+    ((40, 37, 43), 16, 6, synth.axis_stencil(6), "equal", False, "hann"),
+    ((45, 39, 41), 16, 7, synth.axis_stencil(7), "adapt_ls", False, "hann"),
     # one-sided stencils (no offset pairs with its negation), both forms of Eq. 3
     ((18, 16, 17), 8, 1, np.array([[1, 0, 0], [0, 2, 0], [0, 0, -1], [1, 1, 1], [-2, 0, 1]]), "equal", False, "hann"),
     ((16, 19, 18), 8, 2, np.array([[2, 0, 0], [0, -2, 2], [0, 0, 4], [-4, 2, 0]]), "adapt_ls", True, "hann"),
