@@ -164,7 +164,7 @@ def test_backward_deterministic(torch_sal):
 def test_grad_workload_oracle_and_fd(torch_sal):
     """128^3 faulted volume, window 8^3, loss sum(S * U(0,1) weights): the
     adjoint against the FP64 oracle gradient at 64 random voxels, and against
-    central differences (h = 1e-3) of the HIP forward at the same voxels."""
+    central differences (h = 1e-3) of the HIP forward at the same 64 voxels."""
     torch, sal = torch_sal
     w = synth.workload("grad")
     V = synth.make_volume(w.spec, w.seed)
@@ -189,7 +189,7 @@ def test_grad_workload_oracle_and_fd(torch_sal):
     gS64 = gS.astype(np.float64)
     fd_err = []
     skipped = 0
-    for q in pts[:32]:
+    for q in pts:
         vals = []
         for d in (-h, 0.0, h):
             Vp = V.copy()
@@ -207,4 +207,4 @@ def test_grad_workload_oracle_and_fd(torch_sal):
     # h = 1e-3 is about 1/60 of the data's standard deviation, so the central difference
     # itself carries a curvature error of a few percent (the oracle-side pin shows the same
     # at this step); the 1e-5 gate is the comparison with the oracle gradient above.
-    assert len(fd_err) >= 24 and float(np.median(fd_err)) < 1e-2 and max(fd_err) < 0.15
+    assert len(fd_err) >= 48 and float(np.median(fd_err)) < 1e-2 and max(fd_err) < 0.15
