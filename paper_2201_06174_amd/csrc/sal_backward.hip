@@ -15,6 +15,8 @@
 // workspace; a gather kernel then sums, for every voxel, the regions that cover
 // it directly or through the border reflection, in a fixed order (no atomics,
 // bitwise reproducible).
+#include <algorithm>
+
 #include "sal_aux.h"
 #include "sal_device.h"
 #include "sal_stage.h"
@@ -578,48 +580,45 @@ __device__ __forceinline__ GatherAxis<I> gather_axis(I pa, I Na, int half, int R
     return g;
 }
 
+// One workgroup per (t, il) row of the volume: the t and il ranges of covering tiles are the
+// same for the whole row (scalar work), each lane then walks the xl tiles of its voxels.
+// The sum runs over virtual position, then tile, axis by axis, a fixed order.
 template <typename I>
-__device__ __forceinline__ void gather_point(const GatherParams& p, I v) {
+__global__ __launch_bounds__(256) void k_gather(GatherParams p) {
+    const int64_t nrows = p.N3[0] * p.N3[1];
+    const int64_t r = xcd_block(nrows);
+    if (r >= nrows) return;
     const I N1 = (I)p.N3[1], N2 = (I)p.N3[2];
-    const I c3[3] = {v / (N1 * N2), (v / N2) % N1, v % N2};
     const int half = p.n / 2;
-    GatherAxis<I> ax[3];
-#pragma unroll
-    for (int a = 0; a < 3; a++)
-        ax[a] = gather_axis<I>(c3[a], (I)p.N3[a], half, p.R[a], (I)p.C[a] * p.s, (I)p.tiles[a]);
+    const GatherAxis<I> a0 = gather_axis<I>((I)(r / N1), (I)p.N3[0], half, p.R[0], (I)p.C[0] * p.s, (I)p.tiles[0]);
+    const GatherAxis<I> a1 = gather_axis<I>((I)(r % N1), N1, half, p.R[1], (I)p.C[1] * p.s, (I)p.tiles[1]);
     const I step0 = (I)p.C[0] * p.s, step1 = (I)p.C[1] * p.s, step2 = (I)p.C[2] * p.s;
     // workspace [tilesT][tilesI][R0][R1][tilesX][R2]
     const I T1 = (I)p.tiles[1], T2 = (I)p.tiles[2];
     // element k of a 3-array by selects (a dynamic index would put the array in scratch)
     auto sel = [](const I* x, int k) { return k == 0 ? x[0] : (k == 1 ? x[1] : x[2]); };
-    float acc = 0.f;
-    for (int k0 = 0; k0 < ax[0].nq; k0++) {
-        const I q0 = sel(ax[0].q, k0), hi0 = sel(ax[0].hi, k0);
-        for (I t0 = sel(ax[0].lo, k0); t0 <= hi0; t0++) {
-            const I o0 = q0 - t0 * step0;
-            for (int k1 = 0; k1 < ax[1].nq; k1++) {
-                const I q1 = sel(ax[1].q, k1), hi1 = sel(ax[1].hi, k1);
-                for (I t1 = sel(ax[1].lo, k1); t1 <= hi1; t1++) {
-                    const I row = ((t0 * T1 + t1) * p.R[0] + o0) * p.R[1] + (q1 - t1 * step1);
-                    const float* pr = p.part + row * T2 * p.R[2];
-                    for (int k2 = 0; k2 < ax[2].nq; k2++) {
-                        const I q2 = sel(ax[2].q, k2), hi2 = sel(ax[2].hi, k2);
-                        for (I t2 = sel(ax[2].lo, k2); t2 <= hi2; t2++) acc += pr[t2 * p.R[2] + (q2 - t2 * step2)];
+    for (I x = (I)threadIdx.x; x < N2; x += (I)blockDim.x) {
+        const GatherAxis<I> a2 = gather_axis<I>(x, N2, half, p.R[2], step2, T2);
+        float acc = 0.f;
+        for (int k0 = 0; k0 < a0.nq; k0++) {
+            const I q0 = sel(a0.q, k0), hi0 = sel(a0.hi, k0);
+            for (I t0 = sel(a0.lo, k0); t0 <= hi0; t0++) {
+                const I o0 = q0 - t0 * step0;
+                for (int k1 = 0; k1 < a1.nq; k1++) {
+                    const I q1 = sel(a1.q, k1), hi1 = sel(a1.hi, k1);
+                    for (I t1 = sel(a1.lo, k1); t1 <= hi1; t1++) {
+                        const I row = ((t0 * T1 + t1) * p.R[0] + o0) * p.R[1] + (q1 - t1 * step1);
+                        const float* pr = p.part + row * T2 * p.R[2];
+                        for (int k2 = 0; k2 < a2.nq; k2++) {
+                            const I q2 = sel(a2.q, k2), hi2 = sel(a2.hi, k2);
+                            for (I t2 = sel(a2.lo, k2); t2 <= hi2; t2++) acc += pr[t2 * p.R[2] + (q2 - t2 * step2)];
+                        }
                     }
                 }
             }
         }
+        p.gV[r * N2 + x] = acc;
     }
-    p.gV[v] = acc;
-}
-
-// I = int32_t whenever the workspace, the volume and every virtual position fit it
-template <typename I>
-__global__ __launch_bounds__(256) void k_gather(GatherParams p) {
-    const int64_t NV = p.N3[0] * p.N3[1] * p.N3[2];
-    const int64_t v = xcd_block((NV + 255) / 256) * 256 + threadIdx.x;
-    if (v >= NV) return;
-    gather_point<I>(p, (I)v);
 }
 
 struct AdjLayout {
@@ -773,13 +772,14 @@ sal_status sal_backward(const float* V, int64_t T, int64_t IL, int64_t XL, const
     const int64_t NV = T * IL * XL;
     const int64_t parts = L.tilesT * L.tilesI * L.tilesX * (int64_t)L.RT * L.RI * L.RX;
     const int64_t lim = int64_t(1) << 30;
-    const int64_t nb = xcd_grid((NV + 255) / 256);
+    const int64_t nb = xcd_grid(T * IL);  // one workgroup per (t, il) row
     if (!wide_grid_fits(nb, 256)) return fail(SAL_ERR_SHAPE, "volume too large for one launch");
     const dim3 grid = wide_grid(nb, 256);
+    const dim3 block((unsigned)std::min<int64_t>(256, (XL + 63) / 64 * 64));
     if (parts < 2 * lim && NV < 2 * lim && T < lim && IL < lim && XL < lim)
-        hipLaunchKernelGGL(k_gather<int32_t>, grid, dim3(256), 0, stream, gp);
+        hipLaunchKernelGGL(k_gather<int32_t>, grid, block, 0, stream, gp);
     else
-        hipLaunchKernelGGL(k_gather<int64_t>, grid, dim3(256), 0, stream, gp);
+        hipLaunchKernelGGL(k_gather<int64_t>, grid, block, 0, stream, gp);
     return check_hip(hipGetLastError(), "launch k_gather");
 }
 
