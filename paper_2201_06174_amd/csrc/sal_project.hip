@@ -50,10 +50,26 @@ __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
 
 constexpr int kNT = 1024;  // threads per workgroup: 16 waves, 4 per SIMD
 
-// One tile of CT x 4 x 4 centres.  S > 0 fixes the stride at compile time (rows of
-// pass A then live in registers); S == 0 reads it from the parameters.
+// Persistent form with a prefetched region (n >= 12 at a compile-time stride whose full-depth
+// region takes at most 16 t planes per lane): a workgroup walks several tiles, and during
+// the last kx step of a tile, when no pass reads the staged region any more, the next tile's
+// region is loaded into registers and stored over it, so the staging latency is hidden.
 template <int N, int S, int CTW>
-__device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int64_t tile, float* lds) {
+constexpr int fp32_prefetch_planes() {
+    return N >= 12 && S > 0 && CTW == 1 ? stage_planes<kNT>(7 * S + N, 3 * S + N, 3 * S + N) : 0;
+}
+template <int N, int S, int CTW>
+constexpr bool fp32_prefetch() {
+    return fp32_prefetch_planes<N, S, CTW>() > 0 && fp32_prefetch_planes<N, S, CTW>() <= 16;
+}
+
+// One tile of CT x 4 x 4 centres.  S > 0 fixes the stride at compile time (rows of
+// pass A then live in registers); S == 0 reads it from the parameters.  With `staged` the
+// region is already in LDS; with `has_next` the region of tile `next` is fetched into LDS
+// during the last kx step (fp32_prefetch instances, full-depth tiles).
+template <int N, int S, int CTW>
+__device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int64_t tile, float* lds,
+                                                  bool staged = false, bool has_next = false, int64_t next = 0) {
     constexpr int KH = N / 2 + 1;
     constexpr int NK = N / 4;
     constexpr int NW = kNT / 64;           // waves per workgroup (8 or 16)
@@ -80,8 +96,10 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
     const int gbStride = N * RT * 16;
 
     // stage the tile and its halo, reflected at the volume borders
-    const int64_t t0 = tt * CT * s - N / 2, i0 = ti * 4 * s - N / 2, x0 = tx * 4 * s - N / 2;
-    stage_tile<kNT>(p.V, p.T, p.IL, p.XL, t0, i0, x0, RT, RI, RX, RXp, Vt);
+    if (!staged) {
+        const int64_t t0 = tt * CT * s - N / 2, i0 = ti * 4 * s - N / 2, x0 = tx * 4 * s - N / 2;
+        stage_tile<kNT>(p.V, p.T, p.IL, p.XL, t0, i0, x0, RT, RI, RX, RXp, Vt);
+    }
 
     // A operand of both MFMA passes: packed taper*DFT rows
     float amat[NK];
@@ -106,7 +124,7 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
 
     __syncthreads();
 
-    for (int kx = 0; kx < KH; kx++) {
+    auto kstep = [&](const int kx) {
         // ---- pass A: real DFT along xl at bin kx for every staged (t, il) row
         {
             float cA[N], sA[N];
@@ -261,7 +279,7 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
                 contractP(ua, d0r, d0i);
                 epilogue(ua, d0r, d0i);
             }
-            continue;
+            return;
         }
         const int ua = (wave >> 3) ? (mirror ? (N / 2 + 2) / 2 : UH) : 0;
 #pragma unroll
@@ -322,6 +340,22 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
             else run(std::integral_constant<int, (N / 2 + 2) / 2>{});
         }
         // the next pass A writes only Ab, whose readers (pass B) all passed the barrier above
+    };
+    if constexpr (fp32_prefetch<N, S, CTW>()) {
+        for (int kx = 0; kx + 1 < KH; kx++) kstep(kx);
+        // the last kx step reads the region in pass A only; its loads for the next tile are in
+        // flight meanwhile and land after the step (every wave passed the barrier behind pass A)
+        constexpr int NPL = fp32_prefetch_planes<N, S, CTW>();
+        float pf[NPL];
+        if (has_next) {
+            const int64_t nx = next % p.tilesX, ni = (next / p.tilesX) % p.tilesI, nt = next / (p.tilesX * p.tilesI);
+            stage_issue<kNT, NPL>(pf, p.V, p.T, p.IL, p.XL, nt * CT * s - N / 2, ni * 4 * s - N / 2,
+                                  nx * 4 * s - N / 2, RT, RI, RX);
+        }
+        kstep(KH - 1);
+        if (has_next) stage_commit<kNT, NPL>(pf, RT, RI, RX, RXp, Vt);
+    } else {
+        for (int kx = 0; kx < KH; kx++) kstep(kx);
     }
 
     const int64_t G = p.Tg * p.ILg * p.XLg;
@@ -401,6 +435,15 @@ constexpr int fp32_waves_per_simd() { return N == 8 ? 8 : 4; }
 template <int N, int S, int CTW>
 __global__ __launch_bounds__(kNT, (fp32_waves_per_simd<N>())) void k_project_fp32(ProjParams p) {
     extern __shared__ float lds[];
+    if constexpr (fp32_prefetch<N, S, CTW>()) {
+        // persistent (full-depth tiles only, checked at launch): workgroup b of XCD b % 8
+        // walks that XCD's contiguous share of the tiles with a static stride
+        const int64_t per = (p.ntiles + 7) / 8, stride = gridDim.x / 8;
+        const int64_t lo = (int64_t)(blockIdx.x % 8) * per, hi = lo + per < p.ntiles ? lo + per : p.ntiles;
+        for (int64_t g = lo + blockIdx.x / 8; g < hi; g += stride)
+            project_tile_fp32<N, S, CTW>(p, g, lds, g != lo + blockIdx.x / 8, g + stride < hi, g + stride);
+        return;
+    }
     const int64_t tile = xcd_block(p.ntiles);
     if (tile >= p.ntiles) return;
     project_tile_fp32<N, S, CTW>(p, tile, lds);
@@ -542,7 +585,20 @@ static sal_status launch_project(const ProjParams& p, size_t lds, hipStream_t st
     sal_status st = lds_limit_once((const void*)k_project_fp32<N, S, CTW>, (int)kLdsMax, attr,
                                    "hipFuncSetAttribute(project)");
     if (st) return st;
-    const int64_t grid = xcd_grid(p.ntiles);
+    int64_t grid = xcd_grid(p.ntiles);
+    if constexpr (fp32_prefetch<N, S, CTW>()) {
+        if (p.CT != 8 * CTW) return fail(SAL_ERR_UNSUPPORTED, "the persistent feature kernel takes full-depth tiles");
+        // as many workgroups as are resident at once, a multiple of 8 (one share per XCD)
+        int dev = 0, cus = 0, per_cu = 0;
+        if ((st = check_hip(hipGetDevice(&dev), "hipGetDevice"))) return st;
+        if ((st = check_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev),
+                            "hipDeviceGetAttribute")))
+            return st;
+        if ((st = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_project_fp32<N, S, CTW>, kNT, lds),
+                            "hipOccupancyMaxActiveBlocksPerMultiprocessor")))
+            return st;
+        grid = std::min<int64_t>(grid, std::max<int64_t>(8, (int64_t)cus * std::max(per_cu, 1) / 8 * 8));
+    }
     if (!wide_grid_fits(grid, kNT)) return fail(SAL_ERR_SHAPE, "volume too large for one launch");
     hipLaunchKernelGGL((k_project_fp32<N, S, CTW>), wide_grid(grid, kNT), dim3(kNT), lds, stream, p);
     return check_hip(hipGetLastError(), "launch k_project_fp32");

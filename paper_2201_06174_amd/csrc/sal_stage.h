@@ -67,6 +67,66 @@ __device__ __forceinline__ void stage_tile_with(const float* __restrict__ V, int
     }
 }
 
+// Split form of stage_tile for a region whose columns fit the waves in one pass
+// (RI * RX <= NT) and whose planes fit NPL per lane (stage_planes() <= NPL):
+// stage_issue starts the loads of a region into registers, stage_commit stores them, so
+// their latency is covered by the work in between (the next tile's region is fetched while
+// the current tile finishes).  The lane's position is recomputed by stage_commit, so only
+// the loaded values stay live in between.
+struct StageLane {
+    int g, G, ri, rx;
+    bool act;
+};
+
+template <int NT>
+__device__ __forceinline__ StageLane stage_lane(int RI, int RX) {
+    constexpr int NWV = NT / 64;
+    const int PQ = RI * RX;
+    const int WPG = (PQ + 63) / 64;
+    StageLane L;
+    L.G = NWV / WPG;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    L.g = wave / WPG;
+    const int q = (wave - L.g * WPG) * 64 + (int)(threadIdx.x & 63);
+    L.act = L.g < L.G && q < PQ;
+    const int qc = q < PQ ? q : PQ - 1;
+    L.ri = qc / RX;
+    L.rx = qc - L.ri * RX;
+    return L;
+}
+
+// t planes per lane of the split form (0 if the columns do not fit the waves in one pass)
+template <int NT>
+__host__ __device__ constexpr int stage_planes(int RT, int RI, int RX) {
+    return (RI * RX + 63) / 64 > NT / 64 ? 0 : (RT + NT / 64 / ((RI * RX + 63) / 64) - 1) / (NT / 64 / ((RI * RX + 63) / 64));
+}
+
+template <int NT, int NPL>
+__device__ __forceinline__ void stage_issue(float (&v)[NPL], const float* __restrict__ V, int64_t T, int64_t IL,
+                                            int64_t XL, int64_t t0, int64_t i0, int64_t x0, int RT, int RI, int RX) {
+    const StageLane L = stage_lane<NT>(RI, RX);
+    if (L.g >= L.G) return;  // wave-uniform: idle waves issue nothing
+    const int64_t PS = IL * XL;
+    const int64_t off = reflect_clamp_s(i0 + L.ri, IL) * XL + reflect_clamp_s(x0 + L.rx, XL);
+#pragma unroll
+    for (int u = 0; u < NPL; u++) {
+        const int rt = min(L.g + u * L.G, RT - 1);
+        v[u] = V[reflect_clamp_s(t0 + rt, T) * PS + off];
+    }
+}
+
+template <int NT, int NPL>
+__device__ __forceinline__ void stage_commit(const float (&v)[NPL], int RT, int RI, int RX, int RXp,
+                                             float* __restrict__ Vt) {
+    const StageLane L = stage_lane<NT>(RI, RX);
+    if (L.g >= L.G) return;
+#pragma unroll
+    for (int u = 0; u < NPL; u++) {
+        const int rt = L.g + u * L.G;
+        if (rt < RT && L.act) Vt[(rt * RI + L.ri) * RXp + L.rx] = v[u];
+    }
+}
+
 // fp32 rows of pitch RXp: Vt[(rt * RI + ri) * RXp + rx]
 template <int NT>
 __device__ __forceinline__ void stage_tile(const float* __restrict__ V, int64_t T, int64_t IL, int64_t XL,
