@@ -51,9 +51,10 @@ __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
 constexpr int kNT = 1024;  // threads per workgroup: 16 waves, 4 per SIMD
 
 // Persistent form with a prefetched region (n >= 12 at a compile-time stride whose full-depth
-// region takes at most 16 t planes per lane): a workgroup walks several tiles, and during
-// the last kx step of a tile, when no pass reads the staged region any more, the next tile's
-// region is loaded into registers and stored over it, so the staging latency is hidden.
+// region takes at most 16 t planes per lane; shallower tiles take fewer): a workgroup walks
+// several tiles, and during the last kx step of a tile, when no pass reads the staged region
+// any more, the next tile's region is loaded into registers and stored over it, so the
+// staging latency is hidden.
 template <int N, int S, int CTW>
 constexpr int fp32_prefetch_planes() {
     return N >= 12 && S > 0 && CTW == 1 ? stage_planes<kNT>(7 * S + N, 3 * S + N, 3 * S + N) : 0;
@@ -65,11 +66,13 @@ constexpr bool fp32_prefetch() {
 
 // One tile of CT x 4 x 4 centres.  S > 0 fixes the stride at compile time (rows of
 // pass A then live in registers); S == 0 reads it from the parameters.  With `staged` the
-// region is already in LDS; with `has_next` the region of tile `next` is fetched into LDS
-// during the last kx step (fp32_prefetch instances, full-depth tiles).
+// region is already in LDS; with `has_next` the region of tile `next` (of the volume pn, of
+// the same window class and tile depth) is fetched into LDS during the last kx step
+// (fp32_prefetch instances).
 template <int N, int S, int CTW>
 __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int64_t tile, float* lds,
-                                                  bool staged = false, bool has_next = false, int64_t next = 0) {
+                                                  bool staged = false, bool has_next = false, int64_t next = 0,
+                                                  const ProjParams* pn = nullptr) {
     constexpr int KH = N / 2 + 1;
     constexpr int NK = N / 4;
     constexpr int NW = kNT / 64;           // waves per workgroup (8 or 16)
@@ -348,8 +351,9 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
         constexpr int NPL = fp32_prefetch_planes<N, S, CTW>();
         float pf[NPL];
         if (has_next) {
-            const int64_t nx = next % p.tilesX, ni = (next / p.tilesX) % p.tilesI, nt = next / (p.tilesX * p.tilesI);
-            stage_issue<kNT, NPL>(pf, p.V, p.T, p.IL, p.XL, nt * CT * s - N / 2, ni * 4 * s - N / 2,
+            const ProjParams& q = pn ? *pn : p;
+            const int64_t nx = next % q.tilesX, ni = (next / q.tilesX) % q.tilesI, nt = next / (q.tilesX * q.tilesI);
+            stage_issue<kNT, NPL>(pf, q.V, q.T, q.IL, q.XL, nt * CT * s - N / 2, ni * 4 * s - N / 2,
                                   nx * 4 * s - N / 2, RT, RI, RX);
         }
         kstep(KH - 1);
@@ -436,8 +440,8 @@ template <int N, int S, int CTW>
 __global__ __launch_bounds__(kNT, (fp32_waves_per_simd<N>())) void k_project_fp32(ProjParams p) {
     extern __shared__ float lds[];
     if constexpr (fp32_prefetch<N, S, CTW>()) {
-        // persistent (full-depth tiles only, checked at launch): workgroup b of XCD b % 8
-        // walks that XCD's contiguous share of the tiles with a static stride
+        // persistent: workgroup b of XCD b % 8 walks that XCD's contiguous share of the tiles
+        // with a static stride
         const int64_t per = (p.ntiles + 7) / 8, stride = gridDim.x / 8;
         const int64_t lo = (int64_t)(blockIdx.x % 8) * per, hi = lo + per < p.ntiles ? lo + per : p.ntiles;
         for (int64_t g = lo + blockIdx.x / 8; g < hi; g += stride)
@@ -461,12 +465,30 @@ __global__ __launch_bounds__(kNT, (fp32_waves_per_simd<N>())) void k_project_fp3
     const int64_t per = (total + 7) / 8;
     const int64_t xcd = blockIdx.x % 8, local = blockIdx.x / 8, stride = gridDim.x / 8;
     const int64_t lo = xcd * per, hi = lo + per < total ? lo + per : total;
-    for (int64_t g = lo + local; g < hi; g += stride) {
-        int a = 0, b = nitems - 1;  // last item with prefix[item] <= g
+    auto item_of = [&](int64_t g) {  // last item with prefix[item] <= g
+        int a = 0, b = nitems - 1;
         while (a < b) {
             const int m = (a + b + 1) / 2;
             if (prefix[m] <= g) a = m; else b = m - 1;
         }
+        return a;
+    };
+    if constexpr (fp32_prefetch<N, S, CTW>()) {
+        // each next region (possibly of the next member) is fetched during the current tile
+        int64_t g = lo + local;
+        if (g >= hi) return;
+        int a = item_of(g);
+        for (bool staged = false; g < hi; g += stride, staged = true) {
+            const bool more = g + stride < hi;
+            const int an = more ? item_of(g + stride) : a;
+            project_tile_fp32<N, S, CTW>(items[a], g - prefix[a], lds, staged, more, g + stride - prefix[an],
+                                         &items[an]);
+            a = an;
+        }
+        return;
+    }
+    for (int64_t g = lo + local; g < hi; g += stride) {
+        const int a = item_of(g);
         __syncthreads();
         project_tile_fp32<N, S, CTW>(items[a], g - prefix[a], lds);
     }
@@ -587,7 +609,6 @@ static sal_status launch_project(const ProjParams& p, size_t lds, hipStream_t st
     if (st) return st;
     int64_t grid = xcd_grid(p.ntiles);
     if constexpr (fp32_prefetch<N, S, CTW>()) {
-        if (p.CT != 8 * CTW) return fail(SAL_ERR_UNSUPPORTED, "the persistent feature kernel takes full-depth tiles");
         // as many workgroups as are resident at once, a multiple of 8 (one share per XCD)
         int dev = 0, cus = 0, per_cu = 0;
         if ((st = check_hip(hipGetDevice(&dev), "hipGetDevice"))) return st;
