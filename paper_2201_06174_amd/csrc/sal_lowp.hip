@@ -215,8 +215,29 @@ __host__ __device__ constexpr FixGeom fix_geom(int n, int s, int CT) {
 // and pitch is a compile-time constant (addresses fold into instruction offsets), and the
 // volume is staged once per tile as 16-bit operands: pass A then also runs on the matrix
 // cores, and the bin weights are read from the (cached) global table.
+// Persistent form with a prefetched region (fixed tile, n >= 12, at most 16 t planes per
+// lane): during the last kx step of a tile, when pass A no longer reads the staged planes,
+// the next tile's region is loaded into registers, then rounded and stored over them.  FP16
+// only: the split form already uses all 128 registers, and the prefetch registers' spills
+// cost more than the hidden staging saves (measured).
 template <int N, int S, int PREC, int CTW, bool FIX>
-__device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int64_t tile, float* lds) {
+constexpr int lowp_prefetch_planes() {
+    return FIX && PREC == SAL_PREC_FP16 && N >= 12 && S > 0 && CTW == 1
+               ? stage_planes<kNTL>(7 * S + N, 3 * S + N, 3 * S + N)
+               : 0;
+}
+template <int N, int S, int PREC, int CTW, bool FIX>
+constexpr bool lowp_prefetch() {
+    return lowp_prefetch_planes<N, S, PREC, CTW, FIX>() > 0 && lowp_prefetch_planes<N, S, PREC, CTW, FIX>() <= 16;
+}
+
+// One tile.  With `staged` the region (and the constant pads) are already in LDS; with
+// `has_next` the region of tile `next` of pn (same window class) is fetched during the last
+// kx step (lowp_prefetch instances).
+template <int N, int S, int PREC, int CTW, bool FIX>
+__device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int64_t tile, float* lds,
+                                                  bool staged = false, bool has_next = false, int64_t next = 0,
+                                                  const LowpParams* pn = nullptr) {
     using L = Lp<PREC>;
     typedef typename L::vec vec;
     constexpr int KH = N / 2 + 1;
@@ -259,7 +280,9 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
     const int gRow = RTp;  // one (ri, u, col) sample row; RTp is even, rows stay 4-byte aligned
 
     const int64_t t0 = tt * CT * s - N / 2, i0 = ti * 4 * s - N / 2, x0 = tx * 4 * s - N / 2;
-    if constexpr (FIX) {
+    if (staged) {
+        // region and pads are in place (the pads are never overwritten)
+    } else if constexpr (FIX) {
         stage_tile_with<kNTL>(p.V, p.T, p.IL, p.XL, t0, i0, x0, RT, RI, RX, [&](int rt, int ri, int rx, float v) {
             const int at = (rt * FG.RIE + ri) * FG.XP + rx;
             const uint16_t h = L::hi(v);
@@ -296,14 +319,6 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
             }
     } else {
         stage_tile<kNTL>(p.V, p.T, p.IL, p.XL, t0, i0, x0, RT, RI, RX, RXp, Vt);
-    }
-    // the samples past the last staged row only meet zero coefficients; keep them finite
-    for (int e = tid; e < 2 * N * 16 * (RTp - RT); e += kNTL) {
-        const int pad = RTp - RT;
-        const int r = e / pad, k = RT + e % pad;
-        const int at = (r >= N * 16 ? gPlane - gStrideRi : 0) + r * RTp + k;
-        Gh[at] = 0;
-        if constexpr (L::split) Gl[at] = 0;
     }
 
     // The K slots of passes B and C are (channel, sample): K = 16 * half + b0 + i, half = the
@@ -354,8 +369,18 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
         for (int j = 0; j < 4; j++) acc[c][j][0] = acc[c][j][1] = acc[c][j][2] = 0.f;
 
     __syncthreads();
+    // the samples past the last staged row only meet zero coefficients; keep them finite.
+    // Written after the barrier: the previous tile of a persistent workgroup reduced its sums
+    // in these rows, and pass C reads them only after two more barriers.
+    for (int e = tid; e < 2 * N * 16 * (RTp - RT); e += kNTL) {
+        const int pad = RTp - RT;
+        const int r = e / pad, k = RT + e % pad;
+        const int at = (r >= N * 16 ? gPlane - gStrideRi : 0) + r * RTp + k;
+        Gh[at] = 0;
+        if constexpr (L::split) Gl[at] = 0;
+    }
 
-    for (int kx = 0; kx < KH; kx++) {
+    auto kstep = [&](const int kx) {
         if constexpr (FIX) {
             // ---- pass A on the matrix cores: 16 staged rows x 32 samples times the 32 x 16
             // operand of this kx (columns cos|sin x window column); the il pairs of the result
@@ -551,6 +576,37 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
             if ((S > 0 && (S & 1) == 0) || (ts & 1) == 0) run_slots(std::false_type{});
             else run_slots(std::true_type{});
         }
+    };
+    if constexpr (lowp_prefetch<N, S, PREC, CTW, FIX>()) {
+        for (int kx = 0; kx + 1 < KH; kx++) kstep(kx);
+        // the last kx step reads the staged planes in pass A only; the next region's loads
+        // are in flight meanwhile and are stored after the step
+        constexpr int NPF = lowp_prefetch_planes<N, S, PREC, CTW, FIX>();
+        float pf[NPF];
+        if (has_next) {
+            const LowpParams& q = pn ? *pn : p;
+            const int64_t nx = next % q.tilesX, ni = (next / q.tilesX) % q.tilesI, nt = next / (q.tilesX * q.tilesI);
+            stage_issue<kNTL, NPF>(pf, q.V, q.T, q.IL, q.XL, nt * CT * s - N / 2, ni * 4 * s - N / 2,
+                                   nx * 4 * s - N / 2, RT, RI, RX);
+        }
+        kstep(KH - 1);
+        if (has_next) {
+            const StageLane sl = stage_lane<kNTL>(RI, RX);
+            if (sl.g < sl.G) {
+#pragma unroll
+                for (int u = 0; u < NPF; u++) {
+                    const int rt = sl.g + u * sl.G;
+                    if (rt < RT && sl.act) {
+                        const int at = (rt * FG.RIE + sl.ri) * FG.XP + sl.rx;
+                        const uint16_t h = L::hi(pf[u]);
+                        Vb[at] = h;
+                        if constexpr (L::split) Vb[FG.VP + at] = L::lo(pf[u], h);
+                    }
+                }
+            }
+        }
+    } else {
+        for (int kx = 0; kx < KH; kx++) kstep(kx);
     }
 
     // reduce over the 16 bins of a lane group, then over the two halves of the ki slots
@@ -600,6 +656,15 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
 template <int N, int S, int PREC, int CTW, bool FIX>
 __global__ __launch_bounds__(kNTL) void k_project_lowp(LowpParams p) {
     extern __shared__ float lds[];
+    if constexpr (lowp_prefetch<N, S, PREC, CTW, FIX>()) {
+        // persistent: workgroup b of XCD b % 8 walks that XCD's contiguous share of the tiles
+        const int64_t per = (p.ntiles + 7) / 8, stride = gridDim.x / 8;
+        const int64_t lo = (int64_t)(blockIdx.x % 8) * per, hi = lo + per < p.ntiles ? lo + per : p.ntiles;
+        for (int64_t g = lo + blockIdx.x / 8; g < hi; g += stride)
+            project_tile_lowp<N, S, PREC, CTW, FIX>(p, g, lds, g != lo + blockIdx.x / 8, g + stride < hi,
+                                                    g + stride);
+        return;
+    }
     const int64_t tile = xcd_block(p.ntiles);
     if (tile >= p.ntiles) return;
     project_tile_lowp<N, S, PREC, CTW, FIX>(p, tile, lds);
@@ -613,12 +678,30 @@ __global__ __launch_bounds__(kNTL) void k_project_lowp_batch(const LowpParams* _
     const int64_t per = (total + 7) / 8;
     const int64_t xcd = blockIdx.x % 8, local = blockIdx.x / 8, stride = gridDim.x / 8;
     const int64_t lo = xcd * per, hi = lo + per < total ? lo + per : total;
-    for (int64_t g = lo + local; g < hi; g += stride) {
+    auto item_of = [&](int64_t g) {  // last item with prefix[item] <= g
         int a = 0, b = nitems - 1;
         while (a < b) {
             const int m = (a + b + 1) / 2;
             if (prefix[m] <= g) a = m; else b = m - 1;
         }
+        return a;
+    };
+    if constexpr (lowp_prefetch<N, S, PREC, CTW, FIX>()) {
+        // each next region (possibly of the next member) is fetched during the current tile
+        int64_t g = lo + local;
+        if (g >= hi) return;
+        int a = item_of(g);
+        for (bool staged = false; g < hi; g += stride, staged = true) {
+            const bool more = g + stride < hi;
+            const int an = more ? item_of(g + stride) : a;
+            project_tile_lowp<N, S, PREC, CTW, FIX>(items[a], g - prefix[a], lds, staged, more,
+                                                    g + stride - prefix[an], &items[an]);
+            a = an;
+        }
+        return;
+    }
+    for (int64_t g = lo + local; g < hi; g += stride) {
+        const int a = item_of(g);
         __syncthreads();
         project_tile_lowp<N, S, PREC, CTW, FIX>(items[a], g - prefix[a], lds);
     }
@@ -716,7 +799,20 @@ static sal_status launch_lowp_k(const LowpParams& p, size_t lds, hipStream_t str
     sal_status st = lds_limit_once((const void*)k_project_lowp<N, S, PREC, CTW, FIX>, (int)kLdsMaxL, attr,
                                    "hipFuncSetAttribute(project lowp)");
     if (st) return st;
-    const int64_t grid = xcd_grid(p.ntiles);
+    int64_t grid = xcd_grid(p.ntiles);
+    if constexpr (lowp_prefetch<N, S, PREC, CTW, FIX>()) {
+        // as many workgroups as are resident at once, a multiple of 8 (one share per XCD)
+        int dev = 0, cus = 0, per_cu = 0;
+        if ((st = check_hip(hipGetDevice(&dev), "hipGetDevice"))) return st;
+        if ((st = check_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev),
+                            "hipDeviceGetAttribute")))
+            return st;
+        if ((st = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                &per_cu, k_project_lowp<N, S, PREC, CTW, FIX>, kNTL, lds),
+                            "hipOccupancyMaxActiveBlocksPerMultiprocessor")))
+            return st;
+        grid = std::min<int64_t>(grid, std::max<int64_t>(8, (int64_t)cus * std::max(per_cu, 1) / 8 * 8));
+    }
     if (!wide_grid_fits(grid, kNTL)) return fail(SAL_ERR_SHAPE, "volume too large for one launch");
     hipLaunchKernelGGL((k_project_lowp<N, S, PREC, CTW, FIX>), wide_grid(grid, kNTL), dim3(kNTL), lds, stream, p);
     return check_hip(hipGetLastError(), "launch k_project_lowp");
