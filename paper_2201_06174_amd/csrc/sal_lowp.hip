@@ -217,18 +217,18 @@ __host__ __device__ constexpr FixGeom fix_geom(int n, int s, int CT) {
 // cores, and the bin weights are read from the (cached) global table.
 // Persistent form with a prefetched region (fixed tile, n >= 12, at most 16 t planes per
 // lane): during the last kx step of a tile, when pass A no longer reads the staged planes,
-// the next tile's region is loaded into registers, then rounded and stored over them.  FP16
-// only: the split form already uses all 128 registers, and the prefetch registers' spills
-// cost more than the hidden staging saves (measured).
+// the next tile's region is loaded into registers and its rounded samples are stored after
+// the step.  FP16 only: the split form already uses all 128 registers, and neither the
+// registers' spills nor loading the fp32 region straight into LDS (whose wait then lands
+// on the first weight load of pass C) cost less than the staging they hide (measured).
 template <int N, int S, int PREC, int CTW, bool FIX>
 constexpr int lowp_prefetch_planes() {
-    return FIX && PREC == SAL_PREC_FP16 && N >= 12 && S > 0 && CTW == 1
-               ? stage_planes<kNTL>(7 * S + N, 3 * S + N, 3 * S + N)
-               : 0;
+    return FIX && N >= 12 && S > 0 && CTW == 1 ? stage_planes<kNTL>(7 * S + N, 3 * S + N, 3 * S + N) : 0;
 }
 template <int N, int S, int PREC, int CTW, bool FIX>
 constexpr bool lowp_prefetch() {
-    return lowp_prefetch_planes<N, S, PREC, CTW, FIX>() > 0 && lowp_prefetch_planes<N, S, PREC, CTW, FIX>() <= 16;
+    return PREC == SAL_PREC_FP16 && lowp_prefetch_planes<N, S, PREC, CTW, FIX>() > 0 &&
+           lowp_prefetch_planes<N, S, PREC, CTW, FIX>() <= 16;
 }
 
 // One tile.  With `staged` the region (and the constant pads) are already in LDS; with
@@ -279,6 +279,30 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
     float4* Wl = (float4*)(Gl + (L::split ? (size_t)gPlane + gStrideRi : 0));  // [N][16] weights of this kx
     const int gRow = RTp;  // one (ri, u, col) sample row; RTp is even, rows stay 4-byte aligned
 
+    // zero the pads the operand reads cover (disjoint from the staged samples): columns
+    // [RX, XP) of every row, the odd il row of each rt, and the rows from rt = RT on
+    auto zero_vb_pads = [&]() {
+        if constexpr (FIX) {
+            constexpr int XPAD = FG.XP - FG.RX;
+            if constexpr (XPAD > 0)
+                for (int e = tid; e < FG.VROWS * XPAD; e += kNTL) {
+                    const int at = (e / XPAD) * FG.XP + FG.RX + e % XPAD;
+                    Vb[at] = 0;
+                    if constexpr (L::split) Vb[FG.VP + at] = 0;
+                }
+            if constexpr (FG.RIE > FG.RI)
+                for (int e = tid; e < FG.RT * FG.RX; e += kNTL) {
+                    const int at = ((e / FG.RX) * FG.RIE + FG.RI) * FG.XP + e % FG.RX;
+                    Vb[at] = 0;
+                    if constexpr (L::split) Vb[FG.VP + at] = 0;
+                }
+            for (int e = tid; e < (FG.VROWS - FG.RT * FG.RIE) * FG.RX; e += kNTL) {
+                const int at = (FG.RT * FG.RIE + e / FG.RX) * FG.XP + e % FG.RX;
+                Vb[at] = 0;
+                if constexpr (L::split) Vb[FG.VP + at] = 0;
+            }
+        }
+    };
     const int64_t t0 = tt * CT * s - N / 2, i0 = ti * 4 * s - N / 2, x0 = tx * 4 * s - N / 2;
     if (staged) {
         // region and pads are in place (the pads are never overwritten)
@@ -289,26 +313,7 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
             Vb[at] = h;
             if constexpr (L::split) Vb[FG.VP + at] = L::lo(v, h);
         });
-        // zero the pads the operand reads cover (disjoint from the staged samples): columns
-        // [RX, XP) of every row, the odd il row of each rt, and the rows from rt = RT on
-        constexpr int XPAD = FG.XP - FG.RX;
-        if constexpr (XPAD > 0)
-            for (int e = tid; e < FG.VROWS * XPAD; e += kNTL) {
-                const int at = (e / XPAD) * FG.XP + FG.RX + e % XPAD;
-                Vb[at] = 0;
-                if constexpr (L::split) Vb[FG.VP + at] = 0;
-            }
-        if constexpr (FG.RIE > FG.RI)
-            for (int e = tid; e < FG.RT * FG.RX; e += kNTL) {
-                const int at = ((e / FG.RX) * FG.RIE + FG.RI) * FG.XP + e % FG.RX;
-                Vb[at] = 0;
-                if constexpr (L::split) Vb[FG.VP + at] = 0;
-            }
-        for (int e = tid; e < (FG.VROWS - FG.RT * FG.RIE) * FG.RX; e += kNTL) {
-            const int at = (FG.RT * FG.RIE + e / FG.RX) * FG.XP + e % FG.RX;
-            Vb[at] = 0;
-            if constexpr (L::split) Vb[FG.VP + at] = 0;
-        }
+        zero_vb_pads();
         // Ab columns il/2 in [RIE/2, IQ2) are read by pass B but never written by pass A
         constexpr int CPAD = ab_iq2(S > 0 ? S : 1) - FG.RIE / 2;
         if constexpr (CPAD > 0)
