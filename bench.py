@@ -351,7 +351,7 @@ def cpu_baseline(V, w, seconds):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (requested --gpus %d)" % args.gpus)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (requested --gpus %d)" % args.gpus)
         sys.exit(2)
     import torch
     from paper_2201_06174_amd import _lib, synth

@@ -32,7 +32,7 @@ sal_status check_spec(const sal_spec* spec, int64_t T, int64_t IL, int64_t XL) {
     const int n = spec->n, s = spec->s;
     if (n < 2 || (n & 1)) return fail(SAL_ERR_ARG, "window side n must be even and >= 2");
     if (n != 4 && n != 8 && n != 12 && n != 16)
-        return fail(SAL_ERR_UNSUPPORTED, "window side n must be 4, 8, 12 or 16 in this build");
+        return fail(SAL_ERR_UNSUPPORTED, "window side n must be 4, 8, 12 or 16 (the sides with kernels)");
     if (s < 1 || 2 * s >= n) return fail(SAL_ERR_ARG, "stride must satisfy 1 <= s < n/2 (more than 50% overlap)");
     if (spec->window != SAL_WINDOW_HANN && spec->window != SAL_WINDOW_RECT) return fail(SAL_ERR_ARG, "unknown window");
     if (spec->precision != SAL_PREC_FP32 && spec->precision != SAL_PREC_SPLIT_BF16 && spec->precision != SAL_PREC_FP16)
