@@ -27,6 +27,7 @@ if ROOT not in sys.path:
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
+PEAK_FP32_VALU_TFLOPS = 78.6   # unpacked v_fma_f32 (the kernels are built without packed fp32 forms)
 
 
 def algorithmic_flops_per_window(n: int) -> float:
@@ -59,9 +60,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--part", choices=["fwd_bwd", "batch"], default=None,
-                    help="time only the forward + adjoint on the gradient workload, or only the batch, "
-                         "and print that object (the commands profiled for those parts)")
+    ap.add_argument("--part", choices=["fwd_bwd", "batch", "peaks"], default=None,
+                    help="time only the forward + adjoint on the gradient workload, only the batch, or only "
+                         "the device-peak microbenchmarks, and print that object")
     ap.add_argument("--traffic-pass", action="store_true",
                     help="launch a %d-byte device copy, then the feature kernel twice, and exit "
                          "(the command profiled with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)" % COPY_BYTES)
@@ -139,7 +140,7 @@ def progress(msg):
     print("[bench] %s" % msg, file=sys.stderr, flush=True)
 
 
-def precision_forms(torch, lib, Vd, w, fusion, Dd, Md, steps, done):
+def precision_forms(torch, lib, Vd, w, fusion, Dd, Md, steps, done, peaks=None):
     """The forward step in FP32, split-BF16 and FP16 on one volume; `done` holds (ms per step,
     kernel ms) of a precision already timed."""
     nvox = int(np.prod(Vd.shape))
@@ -154,14 +155,14 @@ def precision_forms(torch, lib, Vd, w, fusion, Dd, Md, steps, done):
             del pp
         nwin = int(np.prod([-(-N // w.s) for N in Vd.shape]))
         forms[prec] = {"ms_per_step": round(m2, 4), "kernel_ms": round(k2, 4),
-                       "mvoxel_s": round(nvox / (m2 * 1e-3) / 1e6, 3), "graded": graded(w, nwin, prec, k2),
+                       "mvoxel_s": round(nvox / (m2 * 1e-3) / 1e6, 3), "graded": graded(w, nwin, prec, k2, peaks),
                        "mfma_counted": feature_mfma(w.name, prec, k2)}
     for prec in ("fp32", "split_bf16", "fp16"):
         forms[prec]["speedup_vs_fp32"] = round(forms["fp32"]["ms_per_step"] / forms[prec]["ms_per_step"], 3)
     return forms
 
 
-def time_fwd_bwd(torch, w_name, steps, warmup):
+def time_fwd_bwd(torch, w_name, steps, warmup, peaks=None):
     """Forward plus the hand-written adjoint on one workload (equal fusion)."""
     import paper_2201_06174_amd as sal
     from paper_2201_06174_amd import synth
@@ -193,17 +194,21 @@ def time_fwd_bwd(torch, w_name, steps, warmup):
     nwin = int(np.prod([-(-N // w.s) for N in V.shape]))
     # forward, recomputed spectra and the adjoint synthesis: three dense-DFT passes of FP32 work
     t_roof = 3 * dense_dft_flops_per_window(w.n, w.s) * nwin / (PEAK_FP32_MFMA_TFLOPS * 1e12) * 1e3
+    roof = {"bound": "mfma", "t_roof_ms": round(t_roof, 4), "frac": round(t_roof / (fwd + bwd), 4),
+            "peak_tflops": PEAK_FP32_MFMA_TFLOPS,
+            # matrix-core work of the forward feature kernel and the spectral adjoint
+            # counted by rocprofv3, over the whole forward + backward time
+            "mfma_counted": stored_mfma("k_spectral_adjoint_grad_mfma.txt",
+                                        ["k_project_fp32<8, 1, 1>", "k_spectral_adjoint<8, 1>"], "adjoint",
+                                        fwd + bwd, PEAK_FP32_MFMA_TFLOPS)}
+    if peaks:
+        t_meas = t_roof * PEAK_FP32_MFMA_TFLOPS / peaks["mfma_f32"]["tflops"]
+        roof["t_roof_measured_peak_ms"] = round(t_meas, 4)
+        roof["frac_measured_peak"] = round(t_meas / (fwd + bwd), 4)
     return {"workload": "%s: %s, window %d^3, stride %d, loss sum(S * U(0,1))" % (
         w_name, "x".join(str(v) for v in V.shape), w.n, w.s),
         "fwd_ms": round(fwd, 4), "bwd_ms": round(bwd, 4),
-        "fwd_bwd_mvoxel_s": round(nvox / ((fwd + bwd) * 1e-3) / 1e6, 3),
-        "roofline": {"bound": "mfma", "t_roof_ms": round(t_roof, 4), "frac": round(t_roof / (fwd + bwd), 4),
-                     "peak_tflops": PEAK_FP32_MFMA_TFLOPS,
-                     # matrix-core work of the forward feature kernel and the spectral adjoint
-                     # counted by rocprofv3, over the whole forward + backward time
-                     "mfma_counted": stored_mfma("k_spectral_adjoint_grad_mfma.txt",
-                                                 ["k_project_fp32<8, 1, 1>", "k_spectral_adjoint<8, 1>"], "adjoint",
-                                                 fwd + bwd, PEAK_FP32_MFMA_TFLOPS)}}
+        "fwd_bwd_mvoxel_s": round(nvox / ((fwd + bwd) * 1e-3) / 1e6, 3), "roofline": roof}
 
 
 def time_batch(torch, lib, steps, count=96):
@@ -252,14 +257,85 @@ def time_batch(torch, lib, steps, count=96):
     return out
 
 
-def graded(w, nwin, precision, kern_ms):
+# (name, sal_peak_kind, published peak in TFLOP/s, per-thread checksum per iteration)
+PEAK_KINDS = (("mfma_f32", 0, PEAK_FP32_MFMA_TFLOPS, 64), ("mfma_bf16", 1, PEAK_BF16_MFMA_TFLOPS, 1024),
+              ("mfma_f16", 2, PEAK_BF16_MFMA_TFLOPS, 1024), ("valu_f32", 3, PEAK_FP32_VALU_TFLOPS, 8))
+
+
+def measure_peaks(torch, lib, reps=5):
+    """The device's own sustained rates (sal_peak_* microbenchmarks, HIP events on the launch
+    stream, best of `reps`): matrix-core and unpacked-VALU TFLOP/s with 8 workgroups of 4 waves per
+    CU, and HBM GB/s of a 4 GiB read and a 2 GiB copy at the best of three grid sizes.  Each
+    kernel's output is checked against its closed form, so a launch that did not do its work
+    cannot report a rate."""
+    from paper_2201_06174_amd import _lib
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def best_ms(launch):
+        launch()
+        best = math.inf
+        for _ in range(reps):
+            ev[0].record()
+            launch()
+            ev[1].record()
+            torch.cuda.synchronize()
+            best = min(best, ev[0].elapsed_time(ev[1]))
+        return best
+
+    res = {"cus": cus}
+    blocks, iters = cus * 8, 16384
+    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    for name, kind, vendor, per_iter in PEAK_KINDS:
+        flops = lib.sal_peak_compute_flops(kind, iters, blocks)
+        ms = best_ms(lambda: _lib.check(lib.sal_peak_compute(kind, iters, blocks, ctypes.c_void_p(out.data_ptr()),
+                                                             st)))
+        assert bool((out == float(per_iter * iters)).all()), name
+        tf = flops / (ms * 1e-3) / 1e12
+        res[name] = {"tflops": round(tf, 2), "published": vendor, "ratio": round(tf / vendor, 4)}
+    del out
+    nbytes = 4 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty(nbytes // 8, dtype=torch.float32, device="cuda")
+    for name, kind, moved in (("hbm_read", 0, nbytes), ("hbm_copy", 1, nbytes)):
+        n = nbytes if kind == 0 else nbytes // 2
+        best = None
+        for per_cu in (4, 8, 16):
+            blocks = cus * per_cu
+            out = torch.zeros(blocks * 256, dtype=torch.float32, device="cuda")
+            ms = best_ms(lambda: _lib.check(lib.sal_peak_stream(kind, ctypes.c_void_p(src.data_ptr()),
+                                                                ctypes.c_void_p(dst.data_ptr()), n,
+                                                                ctypes.c_void_p(out.data_ptr()), blocks, st)))
+            if kind == 0:
+                assert float(out.double().sum()) == nbytes // 4, name
+            else:
+                assert bool((dst == 1.0).all()), name
+            gbs = moved / (ms * 1e-3) / 1e9
+            if best is None or gbs > best[0]:
+                best = (gbs, blocks)
+        res[name] = {"gbs": round(best[0], 1), "published": PEAK_HBM_GBS, "ratio": round(best[0] / PEAK_HBM_GBS, 4),
+                     "blocks": best[1]}
+    del src, dst
+    torch.cuda.empty_cache()
+    return res
+
+
+def graded(w, nwin, precision, kern_ms, peaks=None):
     """Graded roofline of the feature kernel: the dense-DFT contraction count of the
-    launch over the matrix-core peak of its precision, against the measured time."""
+    launch over the matrix-core peak of its precision, against the measured time; with
+    measured peaks, the same against the device's own matrix-core rate."""
     flops = dense_dft_flops_per_window(w.n, w.s) * nwin * (3 if precision == "split_bf16" else 1)
     peak = PEAK_FP32_MFMA_TFLOPS if precision == "fp32" else PEAK_BF16_MFMA_TFLOPS
     t_roof = flops / (peak * 1e12) * 1e3
-    return {"t_roof_ms": round(t_roof, 4), "frac": round(t_roof / kern_ms, 4),
-            "executed_flops_per_window": dense_dft_flops_per_window(w.n, w.s)}
+    g = {"t_roof_ms": round(t_roof, 4), "frac": round(t_roof / kern_ms, 4),
+         "executed_flops_per_window": dense_dft_flops_per_window(w.n, w.s)}
+    if peaks:
+        key = {"fp32": "mfma_f32", "split_bf16": "mfma_bf16", "fp16": "mfma_f16"}[precision]
+        t_meas = flops / (peaks[key]["tflops"] * 1e12) * 1e3
+        g["t_roof_measured_peak_ms"] = round(t_meas, 4)
+        g["frac_measured_peak"] = round(t_meas / kern_ms, 4)
+    return g
 
 
 def stored_traffic(workload, precision):
@@ -363,6 +439,9 @@ def main():
     if args.part == "batch":
         print(json.dumps(time_batch(torch, lib, max(args.steps, 1))), flush=True)
         return
+    if args.part == "peaks":
+        print(json.dumps(measure_peaks(torch, lib)), flush=True)
+        return
     w = synth.workload(args.workload)
     V, M = synth.make_volume(w.spec, w.seed, with_mask=True)
     D, mask = synth.desired_map(M, w.s)
@@ -383,6 +462,10 @@ def main():
     achieved = alg / (kern_ms * 1e-3) / 1e12
     peak = PEAK_FP32_MFMA_TFLOPS if args.precision == "fp32" else PEAK_BF16_MFMA_TFLOPS
     kname = "k_project_fp32" if args.precision == "fp32" else "k_project_lowp"
+    peaks = None
+    if not args.no_extra:
+        progress("device peak microbenchmarks")
+        peaks = measure_peaks(torch, lib)
     out = {
         "metric": "Mvoxel/s saliency fwd (FP32 vs split-BF16 @<=1e-3 rel) and fwd+bwd on 1 GPU",
         "value": round(value, 3),
@@ -403,14 +486,18 @@ def main():
                      "frac": round(achieved / peak, 4), "traffic": stored_traffic(args.workload, args.precision),
                      "kernel": "%s (sal_project)" % kname, "kernel_ms": round(kern_ms, 4),
                      "flops_per_window": algorithmic_flops_per_window(w.n),
-                     "graded": graded(w, nwin, args.precision, kern_ms),
+                     "graded": graded(w, nwin, args.precision, kern_ms, peaks),
                      "mfma_counted": feature_mfma(args.workload, args.precision, kern_ms)},
     }
+    if peaks:
+        mkey = "mfma_f32" if args.precision == "fp32" else "mfma_bf16"
+        out["roofline"]["measured_peak"] = {"peak": peaks[mkey]["tflops"],
+                                            "frac": round(achieved / peaks[mkey]["tflops"], 4)}
     if not args.no_extra:
-        extra = {}
+        extra = {"measured_peaks": peaks}
         done = {args.precision: (ms, kern_ms)}
         extra["precision_forms"] = precision_forms(torch, lib, Vd, w, args.fusion, Dd, Md, max(3, args.steps // 2),
-                                                   done)
+                                                   done, peaks)
         if args.workload != "salt":
             # the precision form's own configuration: the 512^3 salt-dome volume
             del pipe
@@ -420,14 +507,14 @@ def main():
             Ds, masks = synth.desired_map(Ms, ws_.s)
             Vsd, Dsd, Msd = (torch.from_numpy(a).to(dev) for a in (Vs, Ds, masks))
             del Vs, Ms, Ds, masks
-            forms = precision_forms(torch, lib, Vsd, ws_, args.fusion, Dsd, Msd, 3, {})
+            forms = precision_forms(torch, lib, Vsd, ws_, args.fusion, Dsd, Msd, 3, {}, peaks)
             forms["workload"] = "salt: %s volume, window %d^3 Hann, stride %d, %d neighbours, %s fusion" % (
                 "x".join(str(v) for v in Vsd.shape), ws_.n, ws_.s, len(ws_.offsets), args.fusion)
             extra["precision_forms_salt"] = forms
             del Vsd, Dsd, Msd
             torch.cuda.empty_cache()
         progress("forward + adjoint on grad")
-        extra["fwd_bwd"] = time_fwd_bwd(torch, "grad", 5, 2)
+        extra["fwd_bwd"] = time_fwd_bwd(torch, "grad", 5, 2, peaks)
         progress("batch plan")
         extra["batch"] = time_batch(torch, lib, 5)
         out["extra"] = extra

@@ -70,6 +70,10 @@ SIGNATURES = {
     "sal_plan_launch": (c_int32, [c_void_p, c_void_p]),
     "sal_plan_describe": (c_char_p, [c_void_p]),
     "sal_plan_destroy": (c_int32, [c_void_p]),
+    # device throughput microbenchmarks (include/sal_peak.h)
+    "sal_peak_compute_flops": (c_int64, [c_int32, c_int64, c_int64]),
+    "sal_peak_compute": (c_int32, [c_int32, c_int64, c_int64, c_void_p, c_void_p]),
+    "sal_peak_stream": (c_int32, [c_int32, c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_void_p]),
 }
 
 _lib = None

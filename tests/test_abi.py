@@ -116,3 +116,22 @@ def test_python_binding_refuses_cpu_tensors():
     import paper_2201_06174_amd as sal
     with pytest.raises(TypeError):
         sal.project(torch.zeros(8, 8, 8), 8, 1)
+
+
+def test_peak_microbenchmark_arguments():
+    lib = _lib.load()
+    # flops of one launch: waves x iters x chains x flops per instruction
+    assert lib.sal_peak_compute_flops(0, 100, 10) == 10 * 4 * 100 * 4 * 2048
+    assert lib.sal_peak_compute_flops(1, 100, 10) == 10 * 4 * 100 * 4 * 32768
+    assert lib.sal_peak_compute_flops(2, 100, 10) == 10 * 4 * 100 * 4 * 32768
+    assert lib.sal_peak_compute_flops(3, 100, 10) == 10 * 256 * 100 * 8 * 2
+    assert lib.sal_peak_compute_flops(4, 100, 10) == 0 and lib.sal_peak_compute_flops(0, 16385, 10) == 0
+    fake = ctypes.c_void_p(256)
+    for kind, iters, blocks in [(4, 10, 10), (-1, 10, 10), (0, 0, 10), (0, 16385, 10), (0, 10, 0), (0, 10, 1 << 21)]:
+        assert _err(lib.sal_peak_compute(kind, iters, blocks, fake, None)) == "SAL_ERR_ARG"
+    assert _err(lib.sal_peak_compute(0, 10, 10, None, None)) == "SAL_ERR_ARG"
+    big = ctypes.c_void_p(1 << 20)
+    for kind, src, dst, nbytes in [(2, fake, big, 1024), (0, fake, None, 1000), (0, fake, None, 0),
+                                   (0, ctypes.c_void_p(264), None, 1024), (1, fake, None, 1024),
+                                   (1, fake, ctypes.c_void_p(256 + 512), 1024)]:
+        assert _err(lib.sal_peak_stream(kind, src, dst, nbytes, fake, 16, None)) == "SAL_ERR_ARG"
