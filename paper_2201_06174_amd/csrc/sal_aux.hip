@@ -213,8 +213,9 @@ __global__ __launch_bounds__(64) void k_fuse_solve(const double* __restrict__ pa
 
 // S(v) = sum_m W_m S_m(g(v)) (same arithmetic as combine_row): kCombineRows (t, il) rows per
 // block, each thread writing four consecutive xl samples with one 16-byte store (XL % 4 == 0
-// and a 16-byte aligned S),
-// the stride fixed at compile time (SS > 0) so the nearest-centre division is a constant one.
+// and a 16-byte aligned S), the stride fixed at compile time (SS > 0) so the nearest-centre
+// division is a constant one.  The block's rows are resolved once (one division, then a step
+// along il), and an element finds its row by comparisons, so the loop has no 64-bit division.
 constexpr int kCombineRows = 4;
 
 template <int SS>
@@ -226,21 +227,52 @@ __global__ __launch_bounds__(256) void k_combine4(const float* __restrict__ Sm, 
     const double W0 = W[0], W1 = W[1], W2 = W[2];
     const int sh = (s - 1) / 2;
     const int64_t q = XL / 4;
-    for (int64_t e = threadIdx.x; e < kCombineRows * q; e += blockDim.x) {
-        const int64_t row = block_id() * kCombineRows + e / q;
-        if (row >= T * IL) break;
-        const int64_t t = row / IL, i = row % IL;
-        const int64_t base = (cell_of(t, s, Tg) * ILg + cell_of(i, s, ILg)) * XLg;
-        const int x0 = (int)(e % q) * 4;
-        float o[4];
+    const int64_t row0 = block_id() * kCombineRows;
+    const int64_t nrow = T * IL - row0 < kCombineRows ? T * IL - row0 : kCombineRows;
+    int64_t base[kCombineRows], orow[kCombineRows];
+    {
+        int64_t t = row0 / IL, i = row0 - t * IL;
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
-            int gx = (x0 + k + sh) / s;
-            gx = gx < XLg - 1 ? gx : (int)XLg - 1;
-            const int64_t j = base + gx;
-            o[k] = (float)(W0 * (double)Sm[j] + W1 * (double)Sm[G + j] + W2 * (double)Sm[2 * G + j]);
+        for (int r = 0; r < kCombineRows; r++) {
+            base[r] = (cell_of(t, s, Tg) * ILg + cell_of(i, s, ILg)) * XLg;
+            orow[r] = (row0 + r) * XL;
+            if (++i == IL) {
+                i = 0;
+                t++;
+            }
         }
-        *(float4*)&S[row * XL + x0] = make_float4(o[0], o[1], o[2], o[3]);
+    }
+    for (int64_t e = threadIdx.x; e < nrow * q; e += blockDim.x) {
+        int r = 0;
+#pragma unroll
+        for (int k = 1; k < kCombineRows; k++) r += e >= k * q;
+        int64_t b = base[0], ob = orow[0];
+#pragma unroll
+        for (int k = 1; k < kCombineRows; k++)
+            if (r == k) {
+                b = base[k];
+                ob = orow[k];
+            }
+        const int x0 = (int)(e - r * q) * 4;
+        auto value = [&](int gx) {
+            const int64_t j = b + gx;
+            return (float)(W0 * (double)Sm[j] + W1 * (double)Sm[G + j] + W2 * (double)Sm[2 * G + j]);
+        };
+        float4 o;
+        if constexpr (SS == 2) {
+            // x0 = 4u: samples x0, x0 + 1 take centre 2u, the next two 2u + 1 (< XLg as XL % 4 == 0)
+            const float a0 = value(x0 / 2), a1 = value(x0 / 2 + 1);
+            o = make_float4(a0, a0, a1, a1);
+        } else {
+            float v[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const int gx = (x0 + k + sh) / s;
+                v[k] = value(gx < XLg - 1 ? gx : (int)XLg - 1);
+            }
+            o = make_float4(v[0], v[1], v[2], v[3]);
+        }
+        *(float4*)&S[ob + x0] = o;
     }
 }
 
