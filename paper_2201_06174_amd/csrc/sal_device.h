@@ -2,6 +2,8 @@
 // center-surround and fusion steps (not part of the ABI).
 #pragma once
 
+#include <type_traits>
+
 #include "sal_aux.h"
 #include "sal_grid.h"
 
@@ -57,14 +59,44 @@ __device__ __forceinline__ void fuse_stats_block(const float* __restrict__ Sm, c
                                                  int64_t stride, double* __restrict__ out, double* red) {
     double st[kStats];
     for (int k = 0; k < kStats; k++) st[k] = 0.0;
-    for (int64_t j = first + threadIdx.x; j < G; j += stride) {
-        if (mask && !mask[j]) continue;
-        const double u0 = Sm[j], u1 = Sm[G + j], u2 = Sm[2 * G + j], d = D[j];
+    auto add = [&](float f0, float f1, float f2, float fd) {
+        const double u0 = f0, u1 = f1, u2 = f2, d = fd;
         st[0] += u0 * u0; st[1] += u0 * u1; st[2] += u0 * u2;
         st[3] += u1 * u1; st[4] += u1 * u2; st[5] += u2 * u2;
         st[6] += u0 * d; st[7] += u1 * d; st[8] += u2 * d;
         st[9] += d * d; st[10] += 1.0;
-    }
+    };
+    // Four of a thread's points at a time: their loads are issued together, the sums still
+    // taken point by point in increasing j (the same order, so the same result, as one at a time).
+    auto sweep = [&](auto masked) {
+        constexpr bool MASKED = decltype(masked)::value;
+        int64_t j = first + threadIdx.x;
+        for (; j + 3 * stride < G; j += 4 * stride) {
+            bool in[4];
+            float v[4][4];
+#pragma unroll
+            for (int p = 0; p < 4; p++) in[p] = MASKED ? mask[j + p * stride] != 0 : true;
+#pragma unroll
+            for (int p = 0; p < 4; p++) {
+                const int64_t jp = j + p * stride;
+                if (in[p]) {
+                    v[p][0] = Sm[jp];
+                    v[p][1] = Sm[G + jp];
+                    v[p][2] = Sm[2 * G + jp];
+                    v[p][3] = D[jp];
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < 4; p++)
+                if (in[p]) add(v[p][0], v[p][1], v[p][2], v[p][3]);
+        }
+        for (; j < G; j += stride)
+            if (!MASKED || mask[j]) add(Sm[j], Sm[G + j], Sm[2 * G + j], D[j]);
+    };
+    if (mask)
+        sweep(std::true_type{});
+    else
+        sweep(std::false_type{});
     for (int k = 0; k < kStats; k++) {
         red[threadIdx.x] = st[k];
         __syncthreads();
