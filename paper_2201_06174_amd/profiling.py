@@ -1,6 +1,6 @@
 """Summaries of rocprofv3 results for the committed profiles (text only).
 
-    python -m paper_2201_06174_amd.profiling stats DB TITLE COMMAND > profiles/NAME.md
+    python -m paper_2201_06174_amd.profiling stats DB TITLE COMMAND [TOP] > profiles/NAME.md
     python -m paper_2201_06174_amd.profiling traffic FETCH_DB WRITE_DB KERNEL COPY_BYTES COMMAND > profiles/NAME.txt
     python -m paper_2201_06174_amd.profiling mfma DB SOURCES KERNEL [KERNEL ...] -- COMMAND > profiles/NAME.txt
 
@@ -73,14 +73,15 @@ def launches_by_grid(db):
     return sorted(out, key=lambda r: -r[3] * r[4])
 
 
-def stats_markdown(db, title, command, top=16) -> str:
+def stats_markdown(db, title, command, top=30) -> str:
+    """Every kernel of the run, then its `top` launch-size groups with the largest total time."""
     out = ["# %s" % title, "", "Command (from the repository root, on one MI355X):", "", "```", command, "```", "",
            "rocprofv3 kernel-trace statistics (durations in microseconds):", "",
            "| kernel | calls | total us | average us | % |", "|---|---|---|---|---|"]
-    for name, calls, total, avg, pct in stats_rows(db)[:top]:
+    for name, calls, total, avg, pct in stats_rows(db):
         out.append("| `%s` | %d | %.1f | %.2f | %.2f |" % (name, calls, total, avg, pct))
-    out += ["", "The same dispatches by launch size (grid in work-items):", "",
-            "| kernel | grid | workgroup | calls | average us |", "|---|---|---|---|---|"]
+    out += ["", "The same dispatches by launch size (grid in work-items; the %d with the largest total time):" % top,
+            "", "| kernel | grid | workgroup | calls | average us |", "|---|---|---|---|---|"]
     for name, gx, wx, calls, avg in launches_by_grid(db)[:top]:
         out.append("| `%s` | %d | %d | %d | %.2f |" % (name, gx, wx, calls, avg))
     return "\n".join(out) + "\n"
@@ -191,7 +192,7 @@ def read_traffic(path):
 
 def main(argv):
     if len(argv) >= 4 and argv[0] == "stats":
-        sys.stdout.write(stats_markdown(argv[1], argv[2], argv[3]))
+        sys.stdout.write(stats_markdown(argv[1], argv[2], argv[3], *(int(a) for a in argv[4:5])))
         return 0
     if len(argv) >= 5 and argv[0] == "mfma" and "--" in argv:
         cut = argv.index("--")
