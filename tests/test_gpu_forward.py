@@ -122,6 +122,26 @@ def test_fuse_matches_oracle(torch_sal, mode, s):
     assert _rel(S.cpu().numpy(), ref) < TOL_FP32
 
 
+@pytest.mark.parametrize("shape,s", [((64, 80, 64), 1), ((128, 192, 128), 2), ((96, 60, 36), 3)])
+def test_fuse_large_grid_matches_oracle(torch_sal, shape, s):
+    """Grids with several points per statistics thread (the four-point loads and the tail) and
+    xl extents that are multiples of 4 (the 16-byte combine at each stride form)."""
+    torch, sal = torch_sal
+    gs = orc.grid_shape(shape, s)
+    print("fuse shape=%s s=%d grid=%s" % (shape, s, gs), flush=True)
+    rng = np.random.default_rng(60 + s)
+    Sm = rng.uniform(size=(3,) + gs).astype(np.float32)
+    D = (0.5 * Sm[0] + 0.25 * Sm[2] + 0.1 * rng.uniform(size=gs)).astype(np.float32)
+    mask = (rng.uniform(size=gs) < 0.3).astype(np.uint8)
+    S, W = sal.fuse(_dev(torch, Sm), shape, s, "adapt_ls", None, 1e-6, _dev(torch, D), _dev(torch, mask))
+    Wr, fb, _ = orc.fusion_weights(Sm.astype(np.float64), D, mask, "adapt_ls", None, 1e-6)
+    W = W.cpu().numpy()
+    assert W[3] == fb == 0
+    assert np.max(np.abs(W[:3] - Wr)) < 1e-9 * max(1.0, np.abs(Wr).max())
+    ref = orc.combine(Sm.astype(np.float64), Wr, shape, s)
+    assert _rel(S.cpu().numpy(), ref) < TOL_FP32
+
+
 def test_fuse_fallback_flag(torch_sal):
     torch, sal = torch_sal
     Sm = np.ones((3, 4, 4, 4), np.float32)
