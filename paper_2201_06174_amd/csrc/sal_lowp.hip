@@ -539,8 +539,13 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
                     if constexpr (L::split) load8_u16<ODD>(glb + u * 16 * gRow, ts, wl);
                     const vec vh = vec_from_words<PREC>(wh);
                     const vec vl = L::split ? vec_from_words<PREC>(wl) : vh;
+                    // split form: the wave issuing its six products goes first, so the matrix
+                    // cores are fed while the other waves run their epilogues (about 1 % faster;
+                    // the single-product FP16 form is not helped)
+                    if constexpr (L::split) __builtin_amdgcn_s_setprio(1);
                     dre = contract<PREC>(vh, vl, are_h, are_l, f4{0.f, 0.f, 0.f, 0.f});
                     dim = contract<PREC>(vh, vl, aim_h, aim_l, f4{0.f, 0.f, 0.f, 0.f});
+                    if constexpr (L::split) __builtin_amdgcn_s_setprio(0);
                 };
                 // weights of bin (kt = col, ki = u): from LDS, or on the fixed tile straight
                 // from the global table, fetched one slot ahead
