@@ -218,7 +218,7 @@ __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_
             for (int rt = wave; rt < RT; rt += 8) {
                 f4 dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};
                 // raised issue priority while a wave issues a run of products (here and in the
-                // banded inverse t-DFT below): about 1 % off the adjoint in an A/B run
+                // banded inverse t- and il-DFTs below): about 1.5 % off the adjoint in A/B runs
                 __builtin_amdgcn_s_setprio(1);
 #pragma unroll
                 for (int ks = 0; ks < NK; ks++) {
@@ -448,12 +448,14 @@ __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_
             for (int item = wave; item < 2 * ((RT + 3) / 4); item += 8) {
                 const int ch = item & 1, rt = 4 * (item >> 1) + rtp;
                 f4 z = {0.f, 0.f, 0.f, 0.f};
+                __builtin_amdgcn_s_setprio(1);
 #pragma unroll
                 for (int k = 0; k < 8; k++) {
                     const int K = 4 * k + grp;
                     const float x = rt < RT ? packed_x(K & 7, rt, (K >> 3) * 4 + xc, ch) : 0.f;
                     z = mfma4b(btab[k * 64 + lane], x, z);
                 }
+                __builtin_amdgcn_s_setprio(0);
                 if (rt < RT) {
 #pragma unroll
                     for (int j = 0; j < 4; j++) {
