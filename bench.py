@@ -1,11 +1,13 @@
 """Benchmark of the saliency hot path on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload survey|salt|small|grad]
+    python bench.py [--steps K] [--warmup W] [--workload salt|survey|small|grad]
                     [--precision fp32|split_bf16|fp16] [--no-cpu-baseline] [--no-extra]
 
 One step = one whole forward pass (local spectra + projection features,
 directional center-surround, adapted fusion and the full-resolution combine)
-over one synthetic volume already resident in HBM.  Prints ONE JSON line.
+over one synthetic volume already resident in HBM; by default the 512^3
+salt-dome volume (window 16^3 Hann, stride 2, 26 neighbours), the largest
+single-GPU configuration.  Prints ONE JSON line.
 """
 from __future__ import annotations
 
@@ -36,11 +38,12 @@ def algorithmic_flops_per_window(n: int) -> float:
 
 
 def dense_dft_flops_per_window(n: int, s: int) -> float:
-    """Flops of the separable dense-DFT contractions of one window in the sliding tile
-    design (real pass along xl at n/2+1 bins, then the two complex passes):
+    """Reference count of the separable dense complex-DFT contractions of one window in a
+    sliding tile design (real pass along xl at n/2+1 bins, then the two complex passes):
     8 n^3 K + 8 n^2 K s + 4 n K s^2 with K = n/2 + 1.  The graded roofline time of a
     launch is this count over the matrix-core peak of the precision (three products
-    for split-bf16)."""
+    for split-bf16).  The FP32 kernel's packed real cos/sin rows execute about half of
+    it (the hardware-counted figure is reported beside it as `mfma_counted`)."""
     K = n // 2 + 1
     return 8.0 * n ** 3 * K + 8.0 * n ** 2 * K * s + 4.0 * n * K * s * s
 
@@ -53,13 +56,15 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="survey")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="salt")
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--fusion", default="adapt_ls")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-errors", action="store_true", help="skip the per-output errors against the oracle")
+    ap.add_argument("--fwd-bwd-workload", default="grad", help="workload of --part fwd_bwd (grad or salt)")
     ap.add_argument("--part", choices=["fwd_bwd", "batch", "peaks"], default=None,
                     help="time only the forward + adjoint on the gradient workload, only the batch, or only "
                          "the device-peak microbenchmarks, and print that object")
@@ -83,7 +88,7 @@ class Pipeline:
         self.Sm = torch.empty_like(self.E)
         self.S = torch.empty(self.shape, dtype=torch.float32, device=dev)
         self.W = torch.empty(4, dtype=torch.float64, device=dev)
-        nb = int(lib.sal_fuse_workspace_size(*self.grid))
+        nb = int(lib.sal_fuse_workspace_size(self.grid[0], self.grid[1], self.grid[2], None))
         self.ws = torch.empty(nb, dtype=torch.uint8, device=dev)
         self.spec = _lib.make_spec(w.n, w.s, "hann", precision)
         self.stencil, self._keep = _lib.make_stencil(w.offsets)
@@ -140,34 +145,98 @@ def progress(msg):
     print("[bench] %s" % msg, file=sys.stderr, flush=True)
 
 
-def precision_forms(torch, lib, Vd, w, fusion, Dd, Md, steps, done, peaks=None):
+class OracleSection:
+    """The FP64 oracle's E, S_m and W on the grid's middle inline section, where the adapted
+    weights are fitted (the desired map's mask holds that section only, so the oracle's W
+    there is its W for the whole volume), plus E and S_m at 192 sampled grid points with the
+    corners among them, and sampled voxels whose nearest centre lies on that section.  The
+    per-output errors of a forward are taken against these (measurement only, outside the
+    timed region)."""
+
+    def __init__(self, V, w, D, mask, delta):
+        from oracle import oracle as orc
+        self.gs = orc.grid_shape(V.shape, w.s)
+        self.mid = self.gs[1] // 2
+        if int(mask.sum()) != int(mask[:, self.mid, :].sum()):
+            raise ValueError("the fit mask must hold the middle inline section only")
+        t0 = time.perf_counter()
+        self.E, self.Sm = orc.saliency_inline_plane(V, w.n, w.s, "hann", w.offsets, None, False, self.mid)
+        self.W, fb, _ = orc.fusion_weights(self.Sm, D[:, self.mid, :], mask[:, self.mid, :], "adapt_ls", delta=delta)
+        rng = np.random.default_rng(11)
+        g = np.stack([rng.integers(0, N, 192) for N in self.gs], 1).astype(np.int64)
+        g[:8] = [[a, b, c] for a in (0, self.gs[0] - 1) for b in (0, self.gs[1] - 1) for c in (0, self.gs[2] - 1)]
+        self.g = g
+        self.Sg, self.Eg = orc.saliency_at(V, w.n, w.s, "hann", w.offsets, None, False, g)
+        self.v = np.stack([rng.integers(0, V.shape[0], 4096), np.full(4096, self.mid * w.s),
+                           rng.integers(0, V.shape[2], 4096)], 1)
+        gv = np.minimum(self.v // w.s, np.array(self.gs) - 1)
+        self.S = (self.W[:, None] * self.Sm[:, gv[:, 0], gv[:, 2]]).sum(0)
+        self.seconds = time.perf_counter() - t0
+        self.fallback = int(fb)
+
+    @staticmethod
+    def _rel(x, ref):
+        x, ref = np.asarray(x, np.float64), np.asarray(ref, np.float64)
+        return float(np.max(np.abs(x - ref)) / max(np.max(np.abs(ref)), 1e-30))
+
+    def errors(self, pipe):
+        """max |x - ref| / max |ref| per output of the pipeline's last forward."""
+        g = self.g
+        E = pipe.E[:, :, self.mid, :].cpu().numpy()
+        Sm = pipe.Sm[:, :, self.mid, :].cpu().numpy()
+        gi = [pipe.torch.from_numpy(g[:, a]).to(pipe.E.device) for a in range(3)]
+        Eg = pipe.E[:, gi[0], gi[1], gi[2]].T.cpu().numpy()
+        Sg = pipe.Sm[:, gi[0], gi[1], gi[2]].T.cpu().numpy()
+        W = pipe.W.cpu().numpy()
+        vi = [pipe.torch.from_numpy(self.v[:, a]).to(pipe.E.device) for a in range(3)]
+        S = pipe.S[vi[0], vi[1], vi[2]].cpu().numpy()
+        return {"E": round(max(self._rel(E, self.E), self._rel(Eg, self.Eg)), 9),
+                "Sm": round(max(self._rel(Sm, self.Sm), self._rel(Sg, self.Sg)), 9),
+                "W": round(self._rel(W[:3], self.W), 9), "S": round(self._rel(S, self.S), 9),
+                "fallback": int(W[3])}
+
+
+def precision_forms(torch, lib, Vd, w, fusion, Dd, Md, steps, done, peaks=None, oracle=None, first=None):
     """The forward step in FP32, split-BF16 and FP16 on one volume; `done` holds (ms per step,
-    kernel ms) of a precision already timed."""
+    kernel ms) of a precision already timed, `first` its pipeline (outputs still in place).
+    With `oracle` (an OracleSection) each form carries its per-output errors."""
     nvox = int(np.prod(Vd.shape))
     forms = {}
     for prec in ("fp32", "split_bf16", "fp16"):
+        pp = first if prec in done else None
         if prec in done:
             m2, k2 = done[prec]
         else:
             progress("%s forward on %s" % (prec, "x".join(str(v) for v in Vd.shape)))
             pp = Pipeline(torch, lib, Vd, w, prec, fusion, Dd, Md)
             m2, k2, _ = time_forward(torch, pp, steps, 2)
-            del pp
         nwin = int(np.prod([-(-N // w.s) for N in Vd.shape]))
         forms[prec] = {"ms_per_step": round(m2, 4), "kernel_ms": round(k2, 4),
                        "mvoxel_s": round(nvox / (m2 * 1e-3) / 1e6, 3), "graded": graded(w, nwin, prec, k2, peaks),
                        "mfma_counted": feature_mfma(w.name, prec, k2)}
+        if oracle is not None and pp is not None:
+            forms[prec]["err_vs_oracle"] = oracle.errors(pp)
+        if pp is not first:
+            del pp
     for prec in ("fp32", "split_bf16", "fp16"):
         forms[prec]["speedup_vs_fp32"] = round(forms["fp32"]["ms_per_step"] / forms[prec]["ms_per_step"], 3)
+    if oracle is not None:
+        forms["err_vs_oracle_definition"] = (
+            "max|x - ref| / max|ref| per output against the FP64 oracle: E and S_m on the middle inline section of "
+            "the grid and at 192 sampled grid points (corners included), W against the oracle's fit (the fit mask "
+            "holds that section only), S at 4096 sampled voxels whose nearest centre lies on it; oracle %.1f s" %
+            oracle.seconds)
     return forms
 
 
-def time_fwd_bwd(torch, w_name, steps, warmup, peaks=None):
-    """Forward plus the hand-written adjoint on one workload (equal fusion)."""
+def time_fwd_bwd(torch, w_name, steps, warmup, peaks=None, V=None):
+    """Forward plus the hand-written adjoint on one workload (equal fusion); V: the workload's
+    volume if already generated."""
     import paper_2201_06174_amd as sal
     from paper_2201_06174_amd import synth
     w = synth.workload(w_name)
-    V = synth.make_volume(w.spec, w.seed)
+    if V is None:
+        V = synth.make_volume(w.spec, w.seed)
     Vd = torch.from_numpy(V).cuda()
     gS = torch.from_numpy(synth.loss_weights(V.shape, 5001)).cuda()
     cfg = sal.Config(n=w.n, s=w.s, offsets=w.offsets, fusion="equal")
@@ -194,13 +263,18 @@ def time_fwd_bwd(torch, w_name, steps, warmup, peaks=None):
     nwin = int(np.prod([-(-N // w.s) for N in V.shape]))
     # forward, recomputed spectra and the adjoint synthesis: three dense-DFT passes of FP32 work
     t_roof = 3 * dense_dft_flops_per_window(w.n, w.s) * nwin / (PEAK_FP32_MFMA_TFLOPS * 1e12) * 1e3
+    # the algorithmic count: three real-input 3D FFTs of each local cube (forward, recomputed,
+    # adjoint synthesis)
+    alg = 3 * algorithmic_flops_per_window(w.n) * nwin / ((fwd + bwd) * 1e-3) / 1e12
+    kern = {"grad": ["k_project_fp32<8, 1, 1>", "k_spectral_adjoint<8, 1>"],
+            "salt": ["k_project_fp32<16, 2, 1>", "k_spectral_adjoint<16, 2>"]}.get(w_name)
     roof = {"bound": "mfma", "t_roof_ms": round(t_roof, 4), "frac": round(t_roof / (fwd + bwd), 4),
             "peak_tflops": PEAK_FP32_MFMA_TFLOPS,
+            "algorithmic_tflops": round(alg, 3), "algorithmic_frac": round(alg / PEAK_FP32_MFMA_TFLOPS, 4),
             # matrix-core work of the forward feature kernel and the spectral adjoint
             # counted by rocprofv3, over the whole forward + backward time
-            "mfma_counted": stored_mfma("k_spectral_adjoint_grad_mfma.txt",
-                                        ["k_project_fp32<8, 1, 1>", "k_spectral_adjoint<8, 1>"], "adjoint",
-                                        fwd + bwd, PEAK_FP32_MFMA_TFLOPS)}
+            "mfma_counted": stored_mfma("k_spectral_adjoint_%s_mfma.txt" % w_name, kern, "adjoint",
+                                        fwd + bwd, PEAK_FP32_MFMA_TFLOPS) if kern else None}
     if peaks:
         t_meas = t_roof * PEAK_FP32_MFMA_TFLOPS / peaks["mfma_f32"]["tflops"]
         roof["t_roof_measured_peak_ms"] = round(t_meas, 4)
@@ -329,7 +403,7 @@ def graded(w, nwin, precision, kern_ms, peaks=None):
     peak = PEAK_FP32_MFMA_TFLOPS if precision == "fp32" else PEAK_BF16_MFMA_TFLOPS
     t_roof = flops / (peak * 1e12) * 1e3
     g = {"t_roof_ms": round(t_roof, 4), "frac": round(t_roof / kern_ms, 4),
-         "executed_flops_per_window": dense_dft_flops_per_window(w.n, w.s)}
+         "dense_complex_dft_flops_per_window": dense_dft_flops_per_window(w.n, w.s)}
     if peaks:
         key = {"fp32": "mfma_f32", "split_bf16": "mfma_bf16", "fp16": "mfma_f16"}[precision]
         t_meas = flops / (peaks[key]["tflops"] * 1e12) * 1e3
@@ -352,12 +426,13 @@ def stored_traffic(workload, precision):
 
 # committed rocprofv3 MFMA-counter summaries of the feature kernel: (workload, precision) ->
 # (file, kernel, source set)
-MFMA_PROFILES = {
-    ("survey", "fp32"): ("k_project_fp32_survey_mfma.txt", "k_project_fp32<16, 2, 1>", "fp32"),
-    ("survey", "split_bf16"): ("k_project_lowp_survey_split_bf16_mfma.txt", "k_project_lowp<16, 2, 1, 1, true>",
-                               "lowp"),
-    ("survey", "fp16"): ("k_project_lowp_survey_fp16_mfma.txt", "k_project_lowp<16, 2, 2, 1, true>", "lowp"),
-}
+MFMA_PROFILES = {}
+for _wl in ("salt", "survey"):
+    MFMA_PROFILES[(_wl, "fp32")] = ("k_project_fp32_%s_mfma.txt" % _wl, "k_project_fp32<16, 2, 1>", "fp32")
+    MFMA_PROFILES[(_wl, "split_bf16")] = ("k_project_lowp_%s_split_bf16_mfma.txt" % _wl,
+                                          "k_project_lowp<16, 2, 1, 1, true>", "lowp")
+    MFMA_PROFILES[(_wl, "fp16")] = ("k_project_lowp_%s_fp16_mfma.txt" % _wl, "k_project_lowp<16, 2, 2, 1, true>",
+                                    "lowp")
 
 
 def feature_mfma(workload, precision, kern_ms):
@@ -397,12 +472,39 @@ def traffic_pass(torch, pipe):
     print("traffic pass done", flush=True)
 
 
+def cpu_model():
+    """The host CPU's model name and logical core count (from /proc/cpuinfo)."""
+    name, count = "unknown", 0
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    count += 1
+    except OSError:
+        pass
+    return name, count
+
+
 def cpu_baseline(V, w, seconds):
-    """The FP64 oracle on a bounded sample of windows of the same volume, on all host cores."""
+    """The FP64 oracle's feature step on bounded samples of windows of the same volume: on
+    all host cores (the OpenMP threads of the process), then on one core."""
+    from oracle import oracle as orc
+    nth = orc.max_threads()
+    out = oracle_rate(V, w, seconds, nth)
+    one = oracle_rate(V, w, max(2.0, seconds / 4), 1)
+    model, logical = cpu_model()
+    out["single_core"] = {"value": one["value"], "unit": one["unit"], "cores": 1, "sample": one["sample"]}
+    out["cpu_model"] = model
+    out["logical_cpus"] = logical or os.cpu_count()
+    out["parallel_speedup"] = round(out["value"] / one["value"], 2) if one["value"] else None
+    return out
+
+
+def oracle_rate(V, w, seconds, nth):
     from oracle import oracle as orc
     gs = orc.grid_shape(V.shape, w.s)
     rng = np.random.default_rng(123)
-    nth = orc.max_threads()
     cnt = 64
     elapsed = 0.0
     total_windows = 0
@@ -434,7 +536,7 @@ def main():
     lib = _lib.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.part == "fwd_bwd":
-        print(json.dumps(time_fwd_bwd(torch, "grad", max(args.steps, 1), args.warmup)), flush=True)
+        print(json.dumps(time_fwd_bwd(torch, args.fwd_bwd_workload, max(args.steps, 1), args.warmup)), flush=True)
         return
     if args.part == "batch":
         print(json.dumps(time_batch(torch, lib, max(args.steps, 1))), flush=True)
@@ -496,25 +598,34 @@ def main():
     if not args.no_extra:
         extra = {"measured_peaks": peaks}
         done = {args.precision: (ms, kern_ms)}
+        errs = not args.no_errors and args.fusion == "adapt_ls"
+        orc_sec = None
+        if errs:
+            progress("oracle on the middle inline section of %s" % args.workload)
+            orc_sec = OracleSection(V, w, D, mask, 1e-6)
         extra["precision_forms"] = precision_forms(torch, lib, Vd, w, args.fusion, Dd, Md, max(3, args.steps // 2),
-                                                   done, peaks)
-        if args.workload != "salt":
-            # the precision form's own configuration: the 512^3 salt-dome volume
-            del pipe
-            progress("generating the salt volume")
-            ws_ = synth.workload("salt")
-            Vs, Ms = synth.make_volume(ws_.spec, ws_.seed, with_mask=True)
-            Ds, masks = synth.desired_map(Ms, ws_.s)
-            Vsd, Dsd, Msd = (torch.from_numpy(a).to(dev) for a in (Vs, Ds, masks))
-            del Vs, Ms, Ds, masks
-            forms = precision_forms(torch, lib, Vsd, ws_, args.fusion, Dsd, Msd, 3, {}, peaks)
-            forms["workload"] = "salt: %s volume, window %d^3 Hann, stride %d, %d neighbours, %s fusion" % (
-                "x".join(str(v) for v in Vsd.shape), ws_.n, ws_.s, len(ws_.offsets), args.fusion)
-            extra["precision_forms_salt"] = forms
-            del Vsd, Dsd, Msd
-            torch.cuda.empty_cache()
+                                                   done, peaks, orc_sec, pipe)
+        del pipe
+        torch.cuda.empty_cache()
+        # the other full-volume configuration: the survey volume (or the salt dome)
+        other = "survey" if args.workload != "survey" else "salt"
+        progress("generating the %s volume" % other)
+        wo = synth.workload(other)
+        Vo, Mo = synth.make_volume(wo.spec, wo.seed, with_mask=True)
+        Do, masko = synth.desired_map(Mo, wo.s)
+        Vod, Dod, Mod = (torch.from_numpy(a).to(dev) for a in (Vo, Do, masko))
+        orc_o = OracleSection(Vo, wo, Do, masko, 1e-6) if errs else None
+        forms = precision_forms(torch, lib, Vod, wo, args.fusion, Dod, Mod, max(3, args.steps // 2), {}, peaks, orc_o)
+        forms["workload"] = "%s: %s volume, window %d^3 Hann, stride %d, %d neighbours, %s fusion" % (
+            other, "x".join(str(v) for v in Vod.shape), wo.n, wo.s, len(wo.offsets), args.fusion)
+        extra["precision_forms_" + other] = forms
+        del Vod, Dod, Mod, Vo, Mo, Do, masko
+        torch.cuda.empty_cache()
         progress("forward + adjoint on grad")
         extra["fwd_bwd"] = time_fwd_bwd(torch, "grad", 5, 2, peaks)
+        progress("forward + adjoint on salt")
+        extra["fwd_bwd_salt"] = time_fwd_bwd(torch, "salt", 3, 1, peaks, V if args.workload == "salt" else None)
+        torch.cuda.empty_cache()
         progress("batch plan")
         extra["batch"] = time_batch(torch, lib, 5)
         out["extra"] = extra

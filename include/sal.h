@@ -19,9 +19,16 @@
  *   be device memory of the current HIP device, host pointers are read during
  *   the call only.  No call keeps a pointer past its return (plans excepted,
  *   see sal_plan_create).
- * Execution: all device work is enqueued on the given stream; no call
- *   synchronises the host with the device, so every call can be captured
- *   in a HIP graph.  Results are bitwise identical run to run.
+ * Execution: all device work is enqueued on the given stream, and no call but
+ *   sal_plan_create allocates device memory.  The constant tables the kernels read live in
+ *   static device memory and are uploaded once per device: by sal_init(), or
+ *   else by the first call on that device that needs them, which then blocks
+ *   the host until the upload is done.  After sal_init() on a device no call
+ *   synchronises the host with it (sal_plan_create and sal_plan_status
+ *   excepted, as documented there), so every call can be captured in a HIP
+ *   graph; a first call inside a capture before sal_init() returns
+ *   SAL_ERR_STATE without enqueueing anything.  Results are bitwise identical
+ *   run to run.
  * Errors: every call validates its arguments on the host before launching
  *   anything and returns a sal_status; sal_last_error() then gives a message
  *   (thread-local).  NaN/Inf inputs propagate without a check.
@@ -45,7 +52,9 @@ typedef enum {
                                 than one launch holds (about 2^47 work-items: far beyond HBM) */
     SAL_ERR_UNSUPPORTED = 3, /* valid for the method, not built into this library (e.g. n = 10) */
     SAL_ERR_NOMEM = 4,       /* workspace too small or allocation failed */
-    SAL_ERR_DEVICE = 5       /* a HIP runtime call failed */
+    SAL_ERR_DEVICE = 5,      /* a HIP runtime call failed */
+    SAL_ERR_STATE = 6        /* the call needs sal_init() on this device first (a first call inside a
+                                stream capture) */
 } sal_status;
 
 typedef enum { SAL_WINDOW_HANN = 0, SAL_WINDOW_RECT = 1 } sal_window;
@@ -71,14 +80,35 @@ typedef struct {
  * not all zero; 1 <= q <= SAL_MAX_STENCIL.  weights: host float [q], or NULL
  * for Gaussian weights exp(-|o|^2 / 2d^2) (d = the stencil's Chebyshev reach)
  * scaled to mean 1.  literal = 0 puts the weight outside the modulus,
- * w |E(c) - E(c+o)|; literal = 1 keeps Eq. 3 as printed, |E(c) - w E(c+o)|. */
+ * w |E(c) - E(c+o)|; literal = 1 keeps Eq. 3 as printed, |E(c) - w E(c+o)|.
+ * per_plane: NULL, or a host array of three stencils, one per projection
+ * plane (t, x, y), for the step's "different directional filters" per
+ * spectral projection; each is resolved on its own (its own Gaussian default
+ * and neighbour count Q), their union may hold at most SAL_MAX_STENCIL
+ * distinct offsets, and q, offsets and weights of the outer stencil are then
+ * ignored (its literal flag applies to all three; their per_plane must be
+ * NULL). */
 #define SAL_MAX_STENCIL 64
-typedef struct {
+typedef struct sal_stencil {
     int32_t q;
     const int32_t* offsets;
     const float* weights;
     int32_t literal;
+    const struct sal_stencil* per_plane;
 } sal_stencil;
+
+/*
+ * sal_line_template -- a graded directional line template (Sec. 2 step 4,
+ * Fig. 4: comparisons along t, x or t-x with weights that fall off away from
+ * the centre).  Offsets j * dir for j = +-1 .. +-length (dir: host int32 [3],
+ * in voxels, a multiple of the stride, not zero), weights
+ * exp(-j^2 / (2 sigma^2)) scaled to mean 1 over the 2 * length offsets.
+ *   offsets_out  host int32 [2 * length][3], ordered j = -length .. -1, 1 .. length
+ *   weights_out  host float [2 * length]
+ * 1 <= length <= SAL_MAX_STENCIL / 2, sigma > 0.  Host only.
+ */
+sal_status sal_line_template(const int32_t* dir, int32_t length, double sigma, int32_t* offsets_out,
+                             float* weights_out);
 
 typedef enum { SAL_FUSE_EQUAL = 0, SAL_FUSE_FIXED = 1, SAL_FUSE_ADAPT_LS = 2 } sal_fusion_mode;
 
@@ -88,12 +118,27 @@ typedef enum { SAL_FUSE_EQUAL = 0, SAL_FUSE_FIXED = 1, SAL_FUSE_ADAPT_LS = 2 } s
  * over the masked grid points, u = (S_t, S_x, S_y) -- the fixed point the
  * paper's LMS/NLMS/RLS adaptation converges to.  A Gram matrix that is not
  * numerically positive definite falls back to EQUAL and raises the status
- * word (see sal_fuse). */
+ * word (see sal_fuse).
+ * sections: 0 fits one W for the whole volume; N > 0 re-adapts every N
+ * inline sections (Sec. 2, last paragraph): the grid's inline planes are cut
+ * into K = ceil(ILg / N) groups [kN, kN + N), each with its own W fitted on
+ * its own masked points, and every voxel takes the W of its grid cell's
+ * group.  sal_fuse_groups() gives K. */
 typedef struct {
     int32_t mode;
     double w_fixed[3];
-    double delta; /* >= 0 */
+    double delta;     /* >= 0 */
+    int64_t sections; /* >= 0 */
 } sal_fusion;
+
+/* Number of weight groups K of a fusion over a grid with ILg inline planes
+ * (1 without sections); 0 for a NULL fusion or negative sizes. */
+int64_t sal_fuse_groups(const sal_fusion* fusion, int64_t ILg);
+
+/* Uploads the constant tables of the current device and resolves its static
+ * scratch (idempotent, blocking).  Call it once per device before capturing
+ * any call in a HIP graph. */
+sal_status sal_init(void);
 
 /* Human-readable message of the last failed call on this thread. */
 const char* sal_last_error(void);
@@ -145,12 +190,12 @@ sal_status sal_center_surround(const float* E, int64_t Tg, int64_t ILg, int64_t 
  *   Sm      device float [3][Tg][ILg][XLg]
  *   D       device float [Tg][ILg][XLg] desired map (ADAPT_LS only, else ignored)
  *   mask    device uint8 [Tg][ILg][XLg] points used for the fit, or NULL for all
- *   W_out   device double [4]: W_t, W_x, W_y, then the status word (0, or 1 if
- *           ADAPT_LS fell back to equal weights)
+ *   W_out   device double [K][4], K = sal_fuse_groups(): per group W_t, W_x, W_y,
+ *           then the status word (0, or 1 if ADAPT_LS fell back to equal weights)
  *   S_out   device float [T][IL][XL]
  *   ws      device workspace of at least sal_fuse_workspace_size() bytes (ADAPT_LS)
  */
-size_t sal_fuse_workspace_size(int64_t Tg, int64_t ILg, int64_t XLg);
+size_t sal_fuse_workspace_size(int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion* fusion);
 sal_status sal_fuse(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion* fusion, const float* D,
                     const uint8_t* mask, int64_t T, int64_t IL, int64_t XL, int32_t s, double* W_out, float* S_out,
                     void* ws, size_t ws_bytes, sal_stream stream);
@@ -162,13 +207,15 @@ sal_status sal_fuse(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const
  * dependence on the maps is differentiated (D is held fixed); where a |.| or
  * |F| has a kink the subgradient 0 is used.
  *   V, E, Sm     the forward's inputs and outputs (device)
- *   W            device double [4] from sal_fuse
+ *   W            device double [K][4] from sal_fuse
  *   D, mask      as given to sal_fuse
  *   gS           device float [T][IL][XL]
  *   gV_out       device float [T][IL][XL]
  *   ws           device workspace of at least sal_backward_workspace_size() bytes
+ * spec->precision must be FP32 (the adjoint runs in fp32).
  */
-size_t sal_backward_workspace_size(int64_t T, int64_t IL, int64_t XL, const sal_spec* spec);
+size_t sal_backward_workspace_size(int64_t T, int64_t IL, int64_t XL, const sal_spec* spec,
+                                   const sal_fusion* fusion);
 sal_status sal_backward(const float* V, int64_t T, int64_t IL, int64_t XL, const sal_spec* spec,
                         const sal_stencil* stencil, const sal_fusion* fusion, const float* E, const float* Sm,
                         const double* W, const float* D, const uint8_t* mask, const float* gS, float* gV_out,
@@ -186,7 +233,7 @@ typedef struct {
     int64_t T, IL, XL;
     sal_spec spec;        /* n, s, window, precision of this member */
     sal_stencil stencil;  /* host arrays, copied by sal_plan_create */
-    sal_fusion fusion;
+    sal_fusion fusion;    /* sections must be 0 */
     const float* D;       /* device [Tg][ILg][XLg], ADAPT_LS only */
     const uint8_t* mask;  /* device [Tg][ILg][XLg] or NULL */
     float* E_out;         /* device [3][Tg][ILg][XLg] */
@@ -215,6 +262,12 @@ sal_status sal_plan_create(const sal_batch_item* items, int64_t count, uint32_t 
 
 /* Enqueues one run of the whole batch on the stream (graph replay). */
 sal_status sal_plan_launch(sal_plan* plan, sal_stream stream);
+
+/* Reads the plan's device status word, written by the last launch enqueued on
+ * `stream`: the number of members whose ADAPT_LS fit fell back to equal weights
+ * and the lowest such member index (-1 if none).  Waits for `stream`. */
+sal_status sal_plan_status(const sal_plan* plan, sal_stream stream, int64_t* fallback_count,
+                           int64_t* first_fallback);
 
 /* Human-readable description of the classes, tile depths and timings (owned by the plan). */
 const char* sal_plan_describe(const sal_plan* plan);

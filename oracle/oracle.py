@@ -11,7 +11,11 @@ Shafiq, Long, Di, AlRegib (ACI 2021), Section 2:
 * spectral projection and features E_m (Eq. 1, third step) -- ``features``;
 * directional center-surround S_m (Eq. 3) -- ``dcs``, ``saliency_at``;
 * fusion weights and the combined map S (Eq. 4) -- ``fusion_weights``,
-  ``combine``; the adjoint of the whole chain -- ``backward``.
+  ``combine``, and with re-adaptation every N inline sections
+  ``fusion_weights_sections``, ``combine_sections``;
+* per-plane stencils and graded line templates (Sec. 2 step 4, Fig. 4) --
+  ``dcs_planes``, ``line_template``;
+* the adjoint of the whole chain -- ``backward``.
 """
 from __future__ import annotations
 
@@ -150,6 +154,75 @@ def dcs(E, s: int, offsets, weights=None, literal=False) -> np.ndarray:
     return S
 
 
+def line_template(direction, length: int, sigma: float):
+    """(offsets[2L][3], weights[2L]): graded line template along `direction`."""
+    d = np.ascontiguousarray(direction, dtype=np.int32).reshape(3)
+    off = np.zeros((2 * length, 3), np.int32)
+    w = np.zeros(2 * length, np.float64)
+    _check(_load().orc_line_template(_p(d), ctypes.c_int(int(length)), ctypes.c_double(sigma), _p(off), _p(w)),
+           "line_template")
+    return off, w
+
+
+def _planes(planes):
+    """Per-plane stencils [(offsets, weights|None)] * 3 -> (q3, offsets, weights) concatenated."""
+    if len(planes) != 3:
+        raise ValueError("one stencil per plane (t, x, y)")
+    offs, ws = [], []
+    for off, w in planes:
+        o, ww = _stencil(off, w)
+        offs.append(o)
+        ws.append(ww)
+    q3 = np.array([o.shape[0] for o in offs], np.int32)
+    return q3, np.ascontiguousarray(np.concatenate(offs), np.int32), np.ascontiguousarray(np.concatenate(ws))
+
+
+def dcs_planes(E, s: int, planes, literal=False) -> np.ndarray:
+    """S_m with a stencil per plane: planes = [(offsets, weights or None)] for t, x, y."""
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    q3, off, w = _planes(planes)
+    S = np.zeros_like(E)
+    rc = _load().orc_dcs_planes(_p(E), _i64(E.shape[1]), _i64(E.shape[2]), _i64(E.shape[3]), ctypes.c_int(s),
+                                _p(q3), _p(off), _p(w), ctypes.c_int(int(bool(literal))), _p(S))
+    _check(rc, "dcs_planes")
+    return S
+
+
+def fuse_groups(ILg: int, sections: int) -> int:
+    f = _load().orc_fuse_groups
+    f.restype = ctypes.c_int64
+    return int(f(_i64(ILg), _i64(sections)))
+
+
+def fusion_weights_sections(Sm, sections: int, D=None, mask=None, mode="equal", wfix=None, delta=0.0):
+    """(W[K][3], fallback[K], stats[K][11]) with re-adaptation every `sections` inline sections."""
+    Sm = np.ascontiguousarray(Sm, dtype=np.float64)
+    _, Tg, ILg, XLg = Sm.shape
+    K = fuse_groups(ILg, sections)
+    Dp = None if D is None else np.ascontiguousarray(D, dtype=np.float32).reshape(-1)
+    Mp = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
+    wf = None if wfix is None else np.ascontiguousarray(wfix, dtype=np.float64)
+    W = np.zeros((K, 3), np.float64)
+    fb = np.zeros(K, np.int32)
+    st = np.zeros((K, 11), np.float64)
+    rc = _load().orc_fusion_weights_sections(_p(Sm), _i64(Tg), _i64(ILg), _i64(XLg), _p(Dp), _p(Mp),
+                                             ctypes.c_int(FUSION_MODES.get(mode, mode)), _p(wf),
+                                             ctypes.c_double(delta), _i64(sections), _p(W), _p(fb), _p(st))
+    _check(rc, "fusion_weights_sections")
+    return W, fb, st
+
+
+def combine_sections(Sm, W, sections: int, shape, s: int) -> np.ndarray:
+    Sm = np.ascontiguousarray(Sm, dtype=np.float64)
+    W = np.ascontiguousarray(W, dtype=np.float64).reshape(-1, 3)
+    T, IL, XL = shape
+    S = np.zeros((T, IL, XL), np.float64)
+    rc = _load().orc_combine_sections(_p(Sm), _i64(Sm.shape[1]), _i64(Sm.shape[2]), _i64(Sm.shape[3]), _p(W),
+                                      _i64(sections), _i64(T), _i64(IL), _i64(XL), ctypes.c_int(s), _p(S))
+    _check(rc, "combine_sections")
+    return S
+
+
 def saliency_at(V, n, s, kind, offsets, weights, literal, g, nthreads=None):
     """(S_m[cnt][3], E[cnt][3]) at grid points g, features recomputed from V."""
     V = _vol(V)
@@ -163,6 +236,23 @@ def saliency_at(V, n, s, kind, offsets, weights, literal, g, nthreads=None):
                                  _p(E), _nthreads(nthreads))
     _check(rc, "saliency_at")
     return Sm, E
+
+
+def saliency_inline_plane(V, n, s, kind, offsets, weights, literal, il_g, nthreads=None):
+    """(E, S_m) on one grid inline plane il_g, both [3][Tg][XLg], for volumes too large for
+    the full-grid oracle: E on the grid planes within the stencil's inline reach (features_at)
+    and the center-surround of that sub-grid (dcs).  A neighbour of plane il_g lies inside
+    the sub-grid exactly when it lies inside the full grid, so S_m on il_g is exact."""
+    V = _vol(V)
+    off, w = _stencil(offsets, weights)
+    Tg, ILg, XLg = grid_shape(V.shape, s)
+    r = int(np.max(np.abs(off[:, 1]))) // s
+    lo, hi = max(0, il_g - r), min(ILg, il_g + r + 1)
+    t, i, x = np.meshgrid(np.arange(Tg), np.arange(lo, hi), np.arange(XLg), indexing="ij")
+    g = np.stack([t.ravel(), i.ravel(), x.ravel()], 1).astype(np.int64)
+    E = features_at(V, n, s, kind, g, nthreads).T.reshape(3, Tg, hi - lo, XLg)
+    Sm = dcs(E, s, off, w, literal)
+    return np.ascontiguousarray(E[:, :, il_g - lo, :]), np.ascontiguousarray(Sm[:, :, il_g - lo, :])
 
 
 def fusion_weights(Sm, D=None, mask=None, mode="equal", wfix=None, delta=0.0):
@@ -206,38 +296,63 @@ class Params:
     delta: float = 0.0
     D: Optional[np.ndarray] = None
     mask: Optional[np.ndarray] = None
+    # per-plane stencils [(offsets, weights or None)] for t, x, y (replace offsets/weights)
+    planes: Optional[list] = None
+    # re-adaptation every `sections` grid inline sections (0: one fit)
+    sections: int = 0
+
+
+def _plane_stencils(p: Params):
+    if p.planes is not None:
+        return _planes(p.planes)
+    off, w = _stencil(p.offsets, p.weights)
+    return (np.array([off.shape[0]] * 3, np.int32), np.ascontiguousarray(np.concatenate([off] * 3), np.int32),
+            np.ascontiguousarray(np.concatenate([w] * 3)))
 
 
 def forward(V, p: Params, nthreads=None) -> dict:
-    """E, S_m, W, fallback flag and S for the whole volume."""
+    """E, S_m, W, fallback flag and S for the whole volume (W [3] and an int flag without
+    sections, W [K][3] and flags [K] with them)."""
     V = _vol(V)
     E = features(V, p.n, p.s, p.window, nthreads)
-    Sm = dcs(E, p.s, p.offsets, p.weights, p.literal)
-    W, fb, st = fusion_weights(Sm, p.D, p.mask, p.fusion, p.wfix, p.delta)
-    S = combine(Sm, W, V.shape, p.s)
+    if p.planes is not None:
+        Sm = dcs_planes(E, p.s, p.planes, p.literal)
+    else:
+        Sm = dcs(E, p.s, p.offsets, p.weights, p.literal)
+    if p.sections:
+        W, fb, st = fusion_weights_sections(Sm, p.sections, p.D, p.mask, p.fusion, p.wfix, p.delta)
+        S = combine_sections(Sm, W, p.sections, V.shape, p.s)
+    else:
+        W, fb, st = fusion_weights(Sm, p.D, p.mask, p.fusion, p.wfix, p.delta)
+        S = combine(Sm, W, V.shape, p.s)
     return {"E": E, "Sm": Sm, "W": W, "fallback": fb, "stats": st, "S": S}
 
 
 def backward(V, p: Params, gS, nthreads=None):
-    """(gV, W, fallback): gradient of sum(gS * S) with respect to V."""
+    """(gV, W, fallback): gradient of sum(gS * S) with respect to V (W and fallback shaped as
+    in forward)."""
     V = _vol(V)
-    off, w = _stencil(p.offsets, p.weights)
+    q3, off, w = _plane_stencils(p)
     gS = np.ascontiguousarray(gS, dtype=np.float32)
     if gS.shape != V.shape:
         raise ValueError("gS must match V")
     Dp = None if p.D is None else np.ascontiguousarray(p.D, dtype=np.float32).reshape(-1)
     Mp = None if p.mask is None else np.ascontiguousarray(p.mask, dtype=np.uint8).reshape(-1)
     wf = None if p.wfix is None else np.ascontiguousarray(p.wfix, dtype=np.float64)
+    K = fuse_groups(grid_shape(V.shape, p.s)[1], p.sections)
     gV = np.zeros(V.shape, np.float64)
-    W = np.zeros(3, np.float64)
-    fb = ctypes.c_int(0)
-    rc = _load().orc_backward(_p(V), _i64(V.shape[0]), _i64(V.shape[1]), _i64(V.shape[2]), ctypes.c_int(p.n),
-                              ctypes.c_int(p.s), ctypes.c_int(WINDOWS.get(p.window, p.window)),
-                              ctypes.c_int(off.shape[0]), _p(off), _p(w), ctypes.c_int(int(bool(p.literal))),
-                              ctypes.c_int(FUSION_MODES.get(p.fusion, p.fusion)), _p(wf), ctypes.c_double(p.delta),
-                              _p(Dp), _p(Mp), _p(gS), _p(gV), _p(W), ctypes.byref(fb), _nthreads(nthreads))
+    W = np.zeros((K, 3), np.float64)
+    fb = np.zeros(K, np.int32)
+    rc = _load().orc_backward_ex(_p(V), _i64(V.shape[0]), _i64(V.shape[1]), _i64(V.shape[2]), ctypes.c_int(p.n),
+                                 ctypes.c_int(p.s), ctypes.c_int(WINDOWS.get(p.window, p.window)), _p(q3), _p(off),
+                                 _p(w), ctypes.c_int(int(bool(p.literal))),
+                                 ctypes.c_int(FUSION_MODES.get(p.fusion, p.fusion)), _p(wf), ctypes.c_double(p.delta),
+                                 _p(Dp), _p(Mp), _i64(p.sections), _p(gS), _p(gV), _p(W), _p(fb),
+                                 _nthreads(nthreads))
     _check(rc, "backward")
-    return gV, W, int(fb.value)
+    if p.sections:
+        return gV, W, fb
+    return gV, W[0], int(fb[0])
 
 
 def backward_at(V, p: Params, gS, pts, nthreads=None) -> np.ndarray:

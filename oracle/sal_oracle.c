@@ -15,10 +15,13 @@
  *          D_t (x) D_il (x) D_xl applied axis by axis);
  *   step 2 (Sec. 2, Eq. 1): projection F_m = F * P_m / |k|, DC bin excluded;
  *   step 3 (Sec. 2, third step): feature E_m = mean over the n^3 cube of |F_m|;
- *   step 4 (Sec. 2, Eq. 3): directional center-surround S_m;
+ *   step 4 (Sec. 2, Eq. 3): directional center-surround S_m, with one
+ *          stencil for all planes or a stencil per plane, and graded line
+ *          templates along a direction (Fig. 4);
  *   step 5 (Sec. 2, Eq. 4): S = W_t S_t + W_x S_x + W_y S_y with equal, fixed
  *          or least-squares-adapted weights (the fixed point of the LMS/NLMS
- *          and the exact result of RLS with unit forgetting factor).
+ *          and the exact result of RLS with unit forgetting factor), fitted
+ *          once or again every N inline sections (last paragraph of Sec. 2).
  *
  * Readings taken where the paper is silent (each is listed in the design doc):
  *   - volume V is float32 [T][IL][XL] (XL fastest); feature/saliency planes
@@ -38,7 +41,10 @@
  *     with sigma = the stencil's Chebyshev reach, scaled to mean 1;
  *   - adapted weights: W = (G + delta I)^{-1} p with G = sum u u^T and
  *     p = sum u D over the mask, u = (S_t, S_x, S_y); a Gram matrix that is
- *     not positive definite falls back to equal weights;
+ *     not positive definite falls back to equal weights; with re-adaptation
+ *     every N sections, one such fit per group of N grid inline planes;
+ *   - a line template holds the offsets j * dir, j = +-1 .. +-L, with
+ *     weights exp(-j^2 / 2 sigma^2) scaled to mean 1;
  *   - S at full resolution takes the nearest grid centre, ties to the lower.
  */
 #include <math.h>
@@ -400,6 +406,47 @@ int orc_dcs(const double* E, int64_t Tg, int64_t ILg, int64_t XLg, int s, int q,
     return ORC_OK;
 }
 
+/* Graded directional line template (Sec. 2 step 4 and Fig. 4: comparisons
+ * along a direction with weights that are largest next to the centre and fall
+ * off with distance).  Reading: offsets j * dir for j = -L .. -1, 1 .. L in
+ * that order, weights exp(-j^2 / (2 sigma^2)) scaled to mean 1 over the 2L
+ * offsets.  off: [2L][3], w: [2L]. */
+int orc_line_template(const int32_t* dir, int L, double sigma, int32_t* off, double* w) {
+    if (L < 1 || !(sigma > 0.0) || (dir[0] == 0 && dir[1] == 0 && dir[2] == 0)) return ORC_EARG;
+    int k = 0;
+    double sum = 0.0;
+    for (int j = -L; j <= L; j++) {
+        if (j == 0) continue;
+        for (int a = 0; a < 3; a++) off[3 * k + a] = j * dir[a];
+        w[k] = exp(-(double)j * j / (2.0 * sigma * sigma));
+        sum += w[k];
+        k++;
+    }
+    for (int e = 0; e < k; e++) w[e] *= (double)k / sum;
+    return ORC_OK;
+}
+
+/* S_m with a stencil of its own for every plane (Sec. 2 step 4: different
+ * directional filters per spectral projection).  Plane m uses the q3[m]
+ * offsets and weights that follow those of the planes before it in off_all
+ * ([sum q3][3]) and w_all ([sum q3]). */
+int orc_dcs_planes(const double* E, int64_t Tg, int64_t ILg, int64_t XLg, int s, const int* q3,
+                   const int32_t* off_all, const double* w_all, int literal, double* S) {
+    int64_t G = Tg * ILg * XLg;
+    int base = 0;
+    for (int m = 0; m < 3; m++) {
+        const int32_t* off = off_all + 3 * base;
+        const double* w = w_all + base;
+        if (check_stencil(s, q3[m], off)) return ORC_EARG;
+        for (int64_t j = 0; j < G; j++) {
+            int64_t gt = j / (ILg * XLg), gi = (j / XLg) % ILg, gx = j % XLg;
+            S[m * G + j] = dcs_point(E + m * G, Tg, ILg, XLg, s, q3[m], off, w, literal, gt, gi, gx);
+        }
+        base += q3[m];
+    }
+    return ORC_OK;
+}
+
 /* S_m (and E) at a list of grid points, computing E at each point and at its
  * in-volume stencil neighbours directly from V.  Sm, E: [cnt][3]. */
 int orc_saliency_at(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s, int window, int q,
@@ -543,6 +590,50 @@ int orc_combine(const double* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const do
     return ORC_OK;
 }
 
+/* Re-adaptation every N inline sections (Sec. 2, last paragraph).  Reading:
+ * the grid's inline planes are cut into K = ceil(ILg / N) groups
+ * [kN, kN + N) (N = 0: one group), and group k's weights are those of Eq. 4
+ * fitted on the masked points of that group alone.  W: [K][3], fallback: [K],
+ * stats: [K][11] or NULL. */
+int64_t orc_fuse_groups(int64_t ILg, int64_t N) { return N > 0 ? ceil_div(ILg, N) : 1; }
+
+int orc_fusion_weights_sections(const double* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const float* D,
+                                const uint8_t* mask, int mode, const double* wfix, double delta, int64_t N,
+                                double* W, int* fallback, double* stats) {
+    if (N < 0) return ORC_EARG;
+    int64_t G = Tg * ILg * XLg, K = orc_fuse_groups(ILg, N);
+    uint8_t* mk = (uint8_t*)malloc((size_t)(G > 0 ? G : 1));
+    if (!mk) return ORC_ENOMEM;
+    int rc = ORC_OK;
+    for (int64_t k = 0; k < K && rc == ORC_OK; k++) {
+        for (int64_t j = 0; j < G; j++) {
+            int64_t gi = (j / XLg) % ILg;
+            int in = N > 0 ? (gi >= k * N && gi < (k + 1) * N) : 1;
+            mk[j] = (uint8_t)(in && (!mask || mask[j]));
+        }
+        rc = orc_fusion_weights(Sm, G, D, mk, mode, wfix, delta, W + 3 * k, fallback + k,
+                                stats ? stats + 11 * k : NULL);
+    }
+    free(mk);
+    return rc;
+}
+
+/* S(v) = sum_m W_m S_m(g(v)) with the weights of g(v)'s group. */
+int orc_combine_sections(const double* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const double* W, int64_t N,
+                         int64_t T, int64_t IL, int64_t XL, int s, double* S) {
+    if (s < 1 || N < 0 || ceil_div(T, s) != Tg || ceil_div(IL, s) != ILg || ceil_div(XL, s) != XLg) return ORC_EARG;
+    int64_t G = Tg * ILg * XLg;
+    for (int64_t t = 0; t < T; t++)
+        for (int64_t i = 0; i < IL; i++)
+            for (int64_t x = 0; x < XL; x++) {
+                int64_t gi = cell_of(i, s, ILg);
+                const double* Wk = W + 3 * (N > 0 ? gi / N : 0);
+                int64_t j = (cell_of(t, s, Tg) * ILg + gi) * XLg + cell_of(x, s, XLg);
+                S[(t * IL + i) * XL + x] = Wk[0] * Sm[j] + Wk[1] * Sm[G + j] + Wk[2] * Sm[2 * G + j];
+            }
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Adjoint.  Loss L = sum_v gS(v) S(v); all routines return dL/d(input).    */
 /* ------------------------------------------------------------------------ */
@@ -578,12 +669,18 @@ static void window_adjoint(const orc_tables* tb, const double gE[3], orc_work* w
             }
 }
 
-/* Adjoint of the center-surround: gE from gSm (both planar on the grid). */
-static void dcs_adjoint(const double* E, const double* gSm, int64_t Tg, int64_t ILg, int64_t XLg, int s, int q,
-                        const int32_t* off, const double* w, int literal, double* gE) {
+/* Adjoint of the center-surround: gE from gSm (both planar on the grid);
+ * plane m's stencil as in orc_dcs_planes. */
+static void dcs_adjoint(const double* E, const double* gSm, int64_t Tg, int64_t ILg, int64_t XLg, int s,
+                        const int* q3, const int32_t* off_all, const double* w_all, int literal, double* gE) {
     int64_t G = Tg * ILg * XLg;
     memset(gE, 0, sizeof(double) * 3 * G);
     for (int m = 0; m < 3; m++) {
+        int base = 0;
+        for (int l = 0; l < m; l++) base += q3[l];
+        const int q = q3[m];
+        const int32_t* off = off_all + 3 * base;
+        const double* w = w_all + base;
         const double* Em = E + m * G;
         double* gEm = gE + m * G;
         for (int64_t j = 0; j < G; j++) {
@@ -615,61 +712,76 @@ static void dcs_adjoint(const double* E, const double* gSm, int64_t Tg, int64_t 
 }
 
 /* Full backward: gV = dL/dV for L = sum gS * S, recomputing every forward
- * quantity from V.  Also returns W and the fallback flag of the forward. */
-int orc_backward(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s, int window, int q,
-                 const int32_t* off, const double* w, int literal, int mode, const double* wfix, double delta,
-                 const float* D, const uint8_t* mask, const float* gS, double* gV, double* W_out,
-                 int* fallback_out, int nthreads) {
+ * quantity from V, with a stencil per plane (as in orc_dcs_planes) and the
+ * weights re-adapted every N inline sections (as in
+ * orc_fusion_weights_sections; N = 0: one fit).  Also returns the forward's
+ * W [K][3] and fallback flags [K]. */
+int orc_backward_ex(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s, int window, const int* q3,
+                    const int32_t* off_all, const double* w_all, int literal, int mode, const double* wfix,
+                    double delta, const float* D, const uint8_t* mask, int64_t N, const float* gS, double* gV,
+                    double* W_out, int* fallback_out, int nthreads) {
     int rc = check_spec(T, IL, XL, n, s, window);
     if (rc) return rc;
-    if (check_stencil(s, q, off)) return ORC_EARG;
+    if (N < 0) return ORC_EARG;
+    {
+        int base = 0;
+        for (int m = 0; m < 3; m++) {
+            if (check_stencil(s, q3[m], off_all + 3 * base)) return ORC_EARG;
+            base += q3[m];
+        }
+    }
     int64_t Tg = ceil_div(T, s), ILg = ceil_div(IL, s), XLg = ceil_div(XL, s);
-    int64_t G = Tg * ILg * XLg, NV = T * IL * XL;
+    int64_t G = Tg * ILg * XLg, NV = T * IL * XL, K = orc_fuse_groups(ILg, N);
     double* E = (double*)malloc(sizeof(double) * 3 * G);
     double* Sm = (double*)malloc(sizeof(double) * 3 * G);
     double* gSm = (double*)malloc(sizeof(double) * 3 * G);
     double* gE = (double*)malloc(sizeof(double) * 3 * G);
     double* cell = (double*)calloc((size_t)G, sizeof(double));
-    if (!E || !Sm || !gSm || !gE || !cell) { rc = ORC_ENOMEM; goto done; }
+    double* W = (double*)malloc(sizeof(double) * 3 * K);
+    double* st = (double*)malloc(sizeof(double) * 11 * K);
+    double* gW = (double*)calloc((size_t)(3 * K), sizeof(double));
+    int* fb = (int*)malloc(sizeof(int) * K);
+    if (!E || !Sm || !gSm || !gE || !cell || !W || !st || !gW || !fb) { rc = ORC_ENOMEM; goto done; }
     rc = orc_features(V, T, IL, XL, n, s, window, E, nthreads);
     if (rc) goto done;
-    orc_dcs(E, Tg, ILg, XLg, s, q, off, w, literal, Sm);
-    double W[3];
-    int fb = 0;
-    rc = orc_fusion_weights(Sm, G, D, mask, mode, wfix, delta, W, &fb, NULL);
+    orc_dcs_planes(E, Tg, ILg, XLg, s, q3, off_all, w_all, literal, Sm);
+    rc = orc_fusion_weights_sections(Sm, Tg, ILg, XLg, D, mask, mode, wfix, delta, N, W, fb, st);
     if (rc) goto done;
-    if (W_out) { W_out[0] = W[0]; W_out[1] = W[1]; W_out[2] = W[2]; }
-    if (fallback_out) *fallback_out = fb;
+    if (W_out) memcpy(W_out, W, sizeof(double) * 3 * K);
+    if (fallback_out) memcpy(fallback_out, fb, sizeof(int) * K);
     /* adjoint of the combine step: per-cell sums of gS */
     for (int64_t t = 0; t < T; t++)
         for (int64_t i = 0; i < IL; i++)
             for (int64_t x = 0; x < XL; x++)
                 cell[(cell_of(t, s, Tg) * ILg + cell_of(i, s, ILg)) * XLg + cell_of(x, s, XLg)] +=
                     (double)gS[(t * IL + i) * XL + x];
-    double gW[3] = {0, 0, 0};
     for (int m = 0; m < 3; m++)
         for (int64_t j = 0; j < G; j++) {
-            gSm[m * G + j] = W[m] * cell[j];
-            gW[m] += Sm[m * G + j] * cell[j];
+            int64_t k = N > 0 ? ((j / XLg) % ILg) / N : 0;
+            gSm[m * G + j] = W[3 * k + m] * cell[j];
+            gW[3 * k + m] += Sm[m * G + j] * cell[j];
         }
-    if (mode == 2 && !fb) {
-        /* adjoint of W = (G + delta I)^{-1} p through G and p (D held fixed) */
-        double st[11];
-        int fb2;
-        double Wtmp[3];
-        orc_fusion_weights(Sm, G, D, mask, 2, NULL, delta, Wtmp, &fb2, st);
-        double A[9] = {st[0] + delta, st[1], st[2], st[1], st[3] + delta, st[4], st[2], st[4], st[5] + delta};
-        double lam[3];
-        chol3_solve(A, gW, lam);
-        for (int64_t j = 0; j < G; j++) {
-            if (mask && !mask[j]) continue;
-            double u[3] = {Sm[j], Sm[G + j], Sm[2 * G + j]};
-            double r = (double)D[j] - (W[0] * u[0] + W[1] * u[1] + W[2] * u[2]);
-            double lu = lam[0] * u[0] + lam[1] * u[1] + lam[2] * u[2];
-            for (int m = 0; m < 3; m++) gSm[m * G + j] += lam[m] * r - W[m] * lu;
+    if (mode == 2) {
+        /* adjoint of each group's W = (G + delta I)^{-1} p through G and p (D held fixed) */
+        for (int64_t k = 0; k < K; k++) {
+            if (fb[k]) continue;
+            const double* a = st + 11 * k;
+            double A[9] = {a[0] + delta, a[1], a[2], a[1], a[3] + delta, a[4], a[2], a[4], a[5] + delta};
+            double lam[3];
+            chol3_solve(A, gW + 3 * k, lam);
+            const double* Wk = W + 3 * k;
+            for (int64_t j = 0; j < G; j++) {
+                int64_t gi = (j / XLg) % ILg;
+                if (N > 0 && (gi < k * N || gi >= (k + 1) * N)) continue;
+                if (mask && !mask[j]) continue;
+                double u[3] = {Sm[j], Sm[G + j], Sm[2 * G + j]};
+                double r = (double)D[j] - (Wk[0] * u[0] + Wk[1] * u[1] + Wk[2] * u[2]);
+                double lu = lam[0] * u[0] + lam[1] * u[1] + lam[2] * u[2];
+                for (int m = 0; m < 3; m++) gSm[m * G + j] += lam[m] * r - Wk[m] * lu;
+            }
         }
     }
-    dcs_adjoint(E, gSm, Tg, ILg, XLg, s, q, off, w, literal, gE);
+    dcs_adjoint(E, gSm, Tg, ILg, XLg, s, q3, off_all, w_all, literal, gE);
     /* spectral adjoint with overlap-add into per-thread copies of gV */
     {
         orc_tables tb;
@@ -727,7 +839,28 @@ int orc_backward(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s
         if (fail) rc = ORC_ENOMEM;
     }
 done:
-    free(E); free(Sm); free(gSm); free(gE); free(cell);
+    free(E); free(Sm); free(gSm); free(gE); free(cell); free(W); free(st); free(gW); free(fb);
+    return rc;
+}
+
+/* orc_backward_ex with one stencil shared by the three planes and one fit. */
+int orc_backward(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s, int window, int q,
+                 const int32_t* off, const double* w, int literal, int mode, const double* wfix, double delta,
+                 const float* D, const uint8_t* mask, const float* gS, double* gV, double* W_out,
+                 int* fallback_out, int nthreads) {
+    if (q <= 0) return ORC_EARG;
+    int q3[3] = {q, q, q};
+    int32_t* off3 = (int32_t*)malloc(sizeof(int32_t) * 9 * q);
+    double* w3 = (double*)malloc(sizeof(double) * 3 * q);
+    if (!off3 || !w3) { free(off3); free(w3); return ORC_ENOMEM; }
+    for (int m = 0; m < 3; m++) {
+        memcpy(off3 + 3 * q * m, off, sizeof(int32_t) * 3 * q);
+        memcpy(w3 + q * m, w, sizeof(double) * q);
+    }
+    int rc = orc_backward_ex(V, T, IL, XL, n, s, window, q3, off3, w3, literal, mode, wfix, delta, D, mask, 0, gS,
+                             gV, W_out, fallback_out, nthreads);
+    free(off3);
+    free(w3);
     return rc;
 }
 

@@ -14,8 +14,9 @@ import numpy as np
 
 from . import _lib
 
-__all__ = ["Config", "local_spectra", "project", "center_surround", "fuse", "saliency", "backward", "SaliencyFn",
-           "grid_shape", "fuse_workspace_size", "backward_workspace_size", "Plan"]
+__all__ = ["Config", "init", "local_spectra", "project", "center_surround", "fuse", "saliency", "backward",
+           "SaliencyFn", "grid_shape", "fuse_groups", "fuse_workspace_size", "backward_workspace_size",
+           "line_template", "Plan"]
 
 
 def _torch():
@@ -27,8 +28,26 @@ def grid_shape(shape, s):
     return tuple(-(-int(N) // int(s)) for N in shape)
 
 
+_ready = set()
+
+
+def init():
+    """Upload libsal's constant tables to the current device (sal_init); needed once per
+    device before any call is captured in a graph.  The operations below call it by
+    themselves outside a capture."""
+    torch = _torch()
+    dev = torch.cuda.current_device()
+    if dev not in _ready:
+        _lib.check(_lib.load().sal_init())
+        _ready.add(dev)
+
+
 def _stream():
     torch = _torch()
+    if torch.cuda.current_device() not in _ready:
+        if torch.cuda.is_current_stream_capturing():
+            raise RuntimeError("call paper_2201_06174_amd.init() on this device before capturing a graph")
+        init()
     return ctypes_void(torch.cuda.current_stream().cuda_stream)
 
 
@@ -67,6 +86,21 @@ class Config:
     fusion: str = "equal"
     wfix: Optional[tuple] = None
     delta: float = 0.0
+    # per-plane stencils [(offsets, weights or None)] for t, x, y (replace offsets/weights)
+    planes: Optional[list] = None
+    # re-adapt the fusion weights every `sections` grid inline sections (0: one fit)
+    sections: int = 0
+
+
+def line_template(direction, length, sigma):
+    """Graded directional line template (offsets [2L][3], weights [2L]) for Config.offsets or
+    one entry of Config.planes."""
+    return _lib.line_template(direction, length, sigma)
+
+
+def fuse_groups(ILg, sections=0):
+    """Number of weight groups of the fusion over ILg grid inline planes."""
+    return int(_lib.load().sal_fuse_groups(_lib.make_fusion("equal", None, 0.0, sections), int(ILg)))
 
 
 def local_spectra(V, centers, n, window="hann"):
@@ -74,6 +108,10 @@ def local_spectra(V, centers, n, window="hann"):
     torch = _torch()
     _need(V, torch.float32, "V")
     _need(centers, torch.int32, "centers")
+    if V.dim() != 3:
+        raise ValueError("V must be [T][IL][XL]")
+    if centers.dim() != 2 or centers.shape[1] != 3:
+        raise ValueError("centers must be [cnt][3], got %s" % (tuple(centers.shape),))
     cnt = centers.shape[0]
     F = torch.empty((cnt, n, n, n, 2), dtype=torch.float32, device=V.device)
     spec = _lib.make_spec(n, 1, window)
@@ -95,39 +133,46 @@ def project(V, n, s, window="hann", precision="fp32"):
     return E
 
 
-def center_surround(E, s, offsets, weights=None, literal=False):
+def center_surround(E, s, offsets, weights=None, literal=False, planes=None):
     torch = _torch()
     _need(E, torch.float32, "E")
     if E.dim() != 4 or E.shape[0] != 3:
         raise ValueError("E must be [3][Tg][ILg][XLg]")
     Sm = torch.empty_like(E)
-    st, keep = _lib.make_stencil(offsets, weights, literal)
+    st, keep = _lib.make_stencil(offsets, weights, literal, planes)
     _lib.check(_lib.load().sal_center_surround(_ptr(E), E.shape[1], E.shape[2], E.shape[3], s, st, _ptr(Sm),
                                                _stream()))
     del keep
     return Sm
 
 
-def fuse_workspace_size(grid):
-    return int(_lib.load().sal_fuse_workspace_size(*grid))
+def fuse_workspace_size(grid, sections=0):
+    f = _lib.make_fusion("equal", None, 0.0, sections)
+    return int(_lib.load().sal_fuse_workspace_size(grid[0], grid[1], grid[2], f))
 
 
-def fuse(Sm, shape, s, mode="equal", wfix=None, delta=0.0, D=None, mask=None, ws=None):
-    """(S[T][IL][XL], W[4] float64: W_t, W_x, W_y, fallback flag)."""
+def fuse(Sm, shape, s, mode="equal", wfix=None, delta=0.0, D=None, mask=None, ws=None, sections=0):
+    """(S[T][IL][XL], W float64: W_t, W_x, W_y, fallback flag -- shape [4] without sections,
+    [K][4] with re-adaptation every `sections` inline sections)."""
     torch = _torch()
     _need(Sm, torch.float32, "Sm")
+    if Sm.dim() != 4 or Sm.shape[0] != 3:
+        raise ValueError("Sm must be [3][Tg][ILg][XLg], got %s" % (tuple(Sm.shape),))
     grid = tuple(Sm.shape[1:])
+    if grid != grid_shape(shape, s):
+        raise ValueError("Sm grid %s does not match ceil(%s / %d)" % (grid, tuple(shape), s))
     if D is not None:
         _need(D, torch.float32, "D", grid)
     if mask is not None:
         _need(mask, torch.uint8, "mask", grid)
     T, IL, XL = shape
     S = torch.empty((T, IL, XL), dtype=torch.float32, device=Sm.device)
-    W = torch.empty(4, dtype=torch.float64, device=Sm.device)
-    nbytes = fuse_workspace_size(grid)
+    f = _lib.make_fusion(mode, wfix, delta, sections)
+    K = int(_lib.load().sal_fuse_groups(f, grid[1]))
+    W = torch.empty((K, 4) if sections else (4,), dtype=torch.float64, device=Sm.device)
+    nbytes = fuse_workspace_size(grid, sections)
     if ws is None:
         ws = torch.empty(nbytes, dtype=torch.uint8, device=Sm.device)
-    f = _lib.make_fusion(mode, wfix, delta)
     _lib.check(_lib.load().sal_fuse(_ptr(Sm), grid[0], grid[1], grid[2], f, _ptr(D), _ptr(mask), T, IL, XL, s,
                                     _ptr(W), _ptr(S), _ptr(ws), ws.numel(), _stream()))
     return S, W
@@ -136,30 +181,39 @@ def fuse(Sm, shape, s, mode="equal", wfix=None, delta=0.0, D=None, mask=None, ws
 def saliency(V, cfg: Config, D=None, mask=None):
     """Whole forward path: returns dict(E, Sm, S, W)."""
     E = project(V, cfg.n, cfg.s, cfg.window, cfg.precision)
-    Sm = center_surround(E, cfg.s, cfg.offsets, cfg.weights, cfg.literal)
-    S, W = fuse(Sm, tuple(V.shape), cfg.s, cfg.fusion, cfg.wfix, cfg.delta, D, mask)
+    Sm = center_surround(E, cfg.s, cfg.offsets, cfg.weights, cfg.literal, cfg.planes)
+    S, W = fuse(Sm, tuple(V.shape), cfg.s, cfg.fusion, cfg.wfix, cfg.delta, D, mask, sections=cfg.sections)
     return {"E": E, "Sm": Sm, "S": S, "W": W}
 
 
-def backward_workspace_size(shape, n, s, window="hann", precision="fp32"):
+def backward_workspace_size(shape, n, s, window="hann", precision="fp32", sections=0):
     spec = _lib.make_spec(n, s, window, precision)
-    return int(_lib.load().sal_backward_workspace_size(shape[0], shape[1], shape[2], spec))
+    f = _lib.make_fusion("equal", None, 0.0, sections)
+    return int(_lib.load().sal_backward_workspace_size(shape[0], shape[1], shape[2], spec, f))
 
 
 def backward(V, cfg: Config, E, Sm, W, gS, D=None, mask=None):
     """gV = d(sum gS * S)/dV through the hand-written adjoint (spectra recomputed)."""
     torch = _torch()
     _need(V, torch.float32, "V")
+    if V.dim() != 3:
+        raise ValueError("V must be [T][IL][XL]")
+    grid = grid_shape(V.shape, cfg.s)
     _need(gS, torch.float32, "gS", tuple(V.shape))
-    _need(E, torch.float32, "E")
-    _need(Sm, torch.float32, "Sm")
-    _need(W, torch.float64, "W")
+    _need(E, torch.float32, "E", (3,) + grid)
+    _need(Sm, torch.float32, "Sm", (3,) + grid)
+    K = fuse_groups(grid[1], cfg.sections)
+    _need(W, torch.float64, "W", (K, 4) if cfg.sections else (4,))
+    if D is not None:
+        _need(D, torch.float32, "D", grid)
+    if mask is not None:
+        _need(mask, torch.uint8, "mask", grid)
     T, IL, XL = V.shape
     gV = torch.empty_like(V)
     spec = _lib.make_spec(cfg.n, cfg.s, cfg.window, cfg.precision)
-    st, keep = _lib.make_stencil(cfg.offsets, cfg.weights, cfg.literal)
-    f = _lib.make_fusion(cfg.fusion, cfg.wfix, cfg.delta)
-    nbytes = backward_workspace_size(V.shape, cfg.n, cfg.s, cfg.window, cfg.precision)
+    st, keep = _lib.make_stencil(cfg.offsets, cfg.weights, cfg.literal, cfg.planes)
+    f = _lib.make_fusion(cfg.fusion, cfg.wfix, cfg.delta, cfg.sections)
+    nbytes = backward_workspace_size(V.shape, cfg.n, cfg.s, cfg.window, cfg.precision, cfg.sections)
     ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=V.device)
     _lib.check(_lib.load().sal_backward(_ptr(V), T, IL, XL, spec, st, f, _ptr(E), _ptr(Sm), _ptr(W), _ptr(D),
                                         _ptr(mask), _ptr(gS), _ptr(gV), _ptr(ws), ws.numel(), _stream()))
@@ -225,20 +279,21 @@ class Plan:
                    "S": torch.empty(tuple(V.shape), dtype=torch.float32, device=V.device),
                    "W": torch.empty(4, dtype=torch.float64, device=V.device)}
             self._out.append(out)
-            st, keep = _lib.make_stencil(cfg.offsets, cfg.weights, cfg.literal)
+            st, keep = _lib.make_stencil(cfg.offsets, cfg.weights, cfg.literal, cfg.planes)
             self._keep.append((V, D, mask, keep))
             it = arr[i]
             it.V = V.data_ptr()
             it.T, it.IL, it.XL = V.shape
             it.spec = _lib.make_spec(cfg.n, cfg.s, cfg.window, cfg.precision)
             it.stencil = st
-            it.fusion = _lib.make_fusion(cfg.fusion, cfg.wfix, cfg.delta)
+            it.fusion = _lib.make_fusion(cfg.fusion, cfg.wfix, cfg.delta, cfg.sections)
             it.D = None if D is None else _need(D, torch.float32, "D", grid).data_ptr()
             it.mask = None if mask is None else _need(mask, torch.uint8, "mask", grid).data_ptr()
             it.E_out = out["E"].data_ptr()
             it.Sm_out = out["Sm"].data_ptr()
             it.W_out = out["W"].data_ptr()
             it.S_out = out["S"].data_ptr()
+        init()
         flags = (_lib.PLAN_AUTOTUNE if autotune else 0) | (0 if graph else _lib.PLAN_NO_GRAPH)
         h = ctypes.c_void_p()
         _lib.check(_lib.load().sal_plan_create(arr, len(members), flags, ctypes.byref(h)))
@@ -249,6 +304,14 @@ class Plan:
 
     def output(self, i):
         return self._out[i]
+
+    def status(self):
+        """(number of members whose adapted fit fell back to equal weights, lowest such member
+        or -1), after the launches enqueued so far (waits for the current stream)."""
+        import ctypes
+        c, f = ctypes.c_int64(), ctypes.c_int64()
+        _lib.check(_lib.load().sal_plan_status(self._h, _stream(), ctypes.byref(c), ctypes.byref(f)))
+        return int(c.value), int(f.value)
 
     def describe(self):
         return _lib.load().sal_plan_describe(self._h).decode()

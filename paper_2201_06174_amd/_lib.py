@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libsal.so")
 
 SAL_OK = 0
 STATUS_NAMES = {0: "SAL_OK", 1: "SAL_ERR_ARG", 2: "SAL_ERR_SHAPE", 3: "SAL_ERR_UNSUPPORTED", 4: "SAL_ERR_NOMEM",
-                5: "SAL_ERR_DEVICE"}
+                5: "SAL_ERR_DEVICE", 6: "SAL_ERR_STATE"}
 WINDOW = {"hann": 0, "rect": 1}
 PRECISION = {"fp32": 0, "split_bf16": 1, "fp16": 2}
 FUSION = {"equal": 0, "fixed": 1, "adapt_ls": 2}
@@ -26,11 +26,15 @@ class SalSpec(ctypes.Structure):
 
 
 class SalStencil(ctypes.Structure):
-    _fields_ = [("q", c_int32), ("offsets", POINTER(c_int32)), ("weights", POINTER(c_float)), ("literal", c_int32)]
+    pass
+
+
+SalStencil._fields_ = [("q", c_int32), ("offsets", POINTER(c_int32)), ("weights", POINTER(c_float)),
+                       ("literal", c_int32), ("per_plane", POINTER(SalStencil))]
 
 
 class SalFusion(ctypes.Structure):
-    _fields_ = [("mode", c_int32), ("w_fixed", c_double * 3), ("delta", c_double)]
+    _fields_ = [("mode", c_int32), ("w_fixed", c_double * 3), ("delta", c_double), ("sections", c_int64)]
 
 
 class SalBatchItem(ctypes.Structure):
@@ -51,6 +55,10 @@ class SalError(RuntimeError):
 
 # name -> (restype, argtypes); every entry point of include/sal.h
 SIGNATURES = {
+    "sal_init": (c_int32, []),
+    "sal_fuse_groups": (c_int64, [POINTER(SalFusion), c_int64]),
+    "sal_line_template": (c_int32, [POINTER(c_int32), c_int32, c_double, POINTER(c_int32), POINTER(c_float)]),
+    "sal_plan_status": (c_int32, [c_void_p, c_void_p, POINTER(c_int64), POINTER(c_int64)]),
     "sal_last_error": (c_char_p, []),
     "sal_version": (c_char_p, []),
     "sal_grid_extent": (c_int64, [c_int64, c_int32]),
@@ -59,10 +67,10 @@ SIGNATURES = {
     "sal_project": (c_int32, [c_void_p, c_int64, c_int64, c_int64, POINTER(SalSpec), c_void_p, c_void_p]),
     "sal_center_surround": (c_int32, [c_void_p, c_int64, c_int64, c_int64, c_int32, POINTER(SalStencil), c_void_p,
                                       c_void_p]),
-    "sal_fuse_workspace_size": (c_size_t, [c_int64, c_int64, c_int64]),
+    "sal_fuse_workspace_size": (c_size_t, [c_int64, c_int64, c_int64, POINTER(SalFusion)]),
     "sal_fuse": (c_int32, [c_void_p, c_int64, c_int64, c_int64, POINTER(SalFusion), c_void_p, c_void_p, c_int64,
                            c_int64, c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
-    "sal_backward_workspace_size": (c_size_t, [c_int64, c_int64, c_int64, POINTER(SalSpec)]),
+    "sal_backward_workspace_size": (c_size_t, [c_int64, c_int64, c_int64, POINTER(SalSpec), POINTER(SalFusion)]),
     "sal_backward": (c_int32, [c_void_p, c_int64, c_int64, c_int64, POINTER(SalSpec), POINTER(SalStencil),
                                POINTER(SalFusion), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                c_void_p, c_void_p, c_size_t, c_void_p]),
@@ -107,26 +115,59 @@ def check(rc):
         raise SalError(rc, msg.decode() if msg else "")
 
 
-def make_stencil(offsets, weights=None, literal=False):
-    """SalStencil plus the host arrays it points to (keep both alive)."""
+def _fill_stencil(st, offsets, weights, literal):
     import numpy as np
     off = np.ascontiguousarray(offsets, dtype=np.int32).reshape(-1, 3)
     w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float32).reshape(-1)
-    st = SalStencil()
+    if w is not None and w.shape[0] != off.shape[0]:
+        raise ValueError("one weight per offset: %d offsets, %d weights" % (off.shape[0], w.shape[0]))
     st.q = off.shape[0]
     st.offsets = off.ctypes.data_as(POINTER(c_int32))
     st.weights = w.ctypes.data_as(POINTER(c_float)) if w is not None else POINTER(c_float)()
     st.literal = 1 if literal else 0
-    return st, (off, w)
+    st.per_plane = POINTER(SalStencil)()
+    return (off, w)
 
 
-def make_fusion(mode="equal", wfix=None, delta=0.0):
+def make_stencil(offsets, weights=None, literal=False, planes=None):
+    """SalStencil plus the host arrays it points to (keep both alive).  planes: None, or
+    [(offsets, weights or None)] for the planes t, x, y (per-plane stencils)."""
+    st = SalStencil()
+    if planes is None:
+        return st, _fill_stencil(st, offsets, weights, literal)
+    if len(planes) != 3:
+        raise ValueError("one stencil per plane (t, x, y)")
+    arr = (SalStencil * 3)()
+    keep = [arr]
+    for m, (off, w) in enumerate(planes):
+        keep.append(_fill_stencil(arr[m], off, w, literal))
+    st.q = 0
+    st.offsets = POINTER(c_int32)()
+    st.weights = POINTER(c_float)()
+    st.literal = 1 if literal else 0
+    st.per_plane = ctypes.cast(arr, POINTER(SalStencil))
+    return st, keep
+
+
+def make_fusion(mode="equal", wfix=None, delta=0.0, sections=0):
     f = SalFusion()
     f.mode = FUSION[mode] if isinstance(mode, str) else int(mode)
     w = [0.0, 0.0, 0.0] if wfix is None else [float(v) for v in wfix]
     f.w_fixed = (c_double * 3)(*w)
     f.delta = float(delta)
+    f.sections = int(sections)
     return f
+
+
+def line_template(direction, length, sigma):
+    """(offsets [2L][3] int32, weights [2L] float32) of sal_line_template (host only)."""
+    import numpy as np
+    d = np.ascontiguousarray(direction, dtype=np.int32).reshape(3)
+    off = np.zeros((2 * int(length), 3), np.int32)
+    w = np.zeros(2 * int(length), np.float32)
+    check(load().sal_line_template(d.ctypes.data_as(POINTER(c_int32)), int(length), float(sigma),
+                                   off.ctypes.data_as(POINTER(c_int32)), w.ctypes.data_as(POINTER(c_float))))
+    return off, w
 
 
 def make_spec(n, s, window="hann", precision="fp32"):

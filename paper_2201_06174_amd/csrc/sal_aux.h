@@ -10,16 +10,28 @@ namespace sal {
 constexpr int kStats = 11;       // G00 G01 G02 G11 G12 G22 p0 p1 p2 sum(D^2) count
 constexpr int kFuseParts = 256;  // fixed number of partial-sum blocks (deterministic reduction)
 
-// Stencil in grid units, passed by value as a kernel argument.
+// Stencil in grid units, passed by value as a kernel argument.  With per-plane stencils
+// (planes = 1) the offsets are the union of the three planes' stencils: offset k belongs to
+// plane m's stencil when bit m of member[k] is set, with weight wp[k][m] there.
 struct DcsStencil {
     int q;
     int literal;
     int reach[3];  // largest |offset| per axis, in grid units
     int symmetric; // every offset has its negation in the stencil: mirror[] pairs them one to one
+                   // (with per-plane stencils, a pair also shares its planes)
+    int planes;    // 0: every offset on all three planes with weight w[k]; 1: member / wp
     int o[SAL_MAX_STENCIL][3];
     float w[SAL_MAX_STENCIL];
     int mirror[SAL_MAX_STENCIL];  // o[mirror[k]] == -o[k] (symmetric stencils only)
+    float wp[SAL_MAX_STENCIL][3];
+    unsigned char member[SAL_MAX_STENCIL];
 };
+
+// Weight groups of the fusion (re-adaptation every `sections` inline sections of the grid):
+// group k holds the inline planes [k N, k N + N) of the grid; N = 0 is one group.
+inline int64_t fuse_groups(int64_t sections, int64_t ILg) {
+    return sections > 0 ? (ILg + sections - 1) / sections : 1;
+}
 
 // Resolves a stencil (validation, Gaussian default weights) into grid units.
 sal_status make_stencil(const sal_stencil* st, int s, DcsStencil* out);
@@ -31,11 +43,13 @@ sal_status launch_dcs(const float* E, float* S, int64_t Tg, int64_t ILg, int64_t
 // gE from E and R = gS_m / Q (the output of launch_fuse_adjoint).
 sal_status launch_dcs_adjoint(const float* E, const float* R, float* gE, int64_t Tg, int64_t ILg, int64_t XLg,
                               const DcsStencil& st, hipStream_t stream);
-size_t fuse_workspace_bytes();
+// Workspace bytes of the fusion over K weight groups (ADAPT_LS partial sums and statistics).
+size_t fuse_workspace_bytes(int64_t K);
+// W: K x 4 doubles (sal_fuse's W_out).
 sal_status launch_fuse(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion& f, const float* D,
                        const uint8_t* mask, int64_t T, int64_t IL, int64_t XL, int s, double* W, float* S, double* ws,
                        hipStream_t stream);
-size_t fuse_adjoint_workspace_bytes();
+size_t fuse_adjoint_workspace_bytes(int64_t K);
 // Writes R_m(g) = gS_m(g) / Q(g), the fusion adjoint divided by the number Q(g) of stencil
 // neighbours of g inside the grid (0 where Q(g) = 0): the per-point factor of every term of
 // the center-surround adjoint.

@@ -115,7 +115,7 @@ sal_status launch_dcs(const float* E, float* S, int64_t Tg, int64_t ILg, int64_t
 // each point's neighbour count.  For a symmetric stencil the neighbour term of the mirrored
 // offset reads the same point g + o as the own term of o, so every neighbour is read once;
 // a point at least the stencil reach away from every border skips the bounds tests.
-template <typename I, bool SYM>
+template <typename I, bool SYM, bool PLANES>
 __device__ __forceinline__ void dcs_adjoint_point(const float* __restrict__ E, const float* __restrict__ R,
                                                   float* __restrict__ gE, I Tg, I ILg, I XLg, const DcsStencil& st,
                                                   I j) {
@@ -134,14 +134,17 @@ __device__ __forceinline__ void dcs_adjoint_point(const float* __restrict__ E, c
         const I nt = gt + st.o[k][0], ni = gi + st.o[k][1], nx = gx + st.o[k][2];
         if (!inner && !inside(nt, ni, nx)) continue;
         const I jn = (nt * ILg + ni) * XLg + nx;
-        const float wk = st.w[k];
 #pragma unroll
         for (int m = 0; m < 3; m++) {
+            // with per-plane stencils an offset outside plane m's stencil adds nothing there
+            // (a mirrored pair shares its planes)
+            if (PLANES && !((st.member[k] >> m) & 1u)) continue;
+            const float wk = PLANES ? st.wp[k][m] : st.w[k];
             const float e1 = E[m * G + jn];
             own[m] += st.literal ? sgn(e0[m] - wk * e1) : wk * sgn(e0[m] - e1);
             if (SYM) {
                 // g = (g + o_k) - o_mirror: the mirrored offset's neighbour term
-                const float wm = st.w[st.mirror[k]];
+                const float wm = PLANES ? st.wp[st.mirror[k]][m] : st.w[st.mirror[k]];
                 nbr[m] += R[m * G + jn] * wm * sgn(st.literal ? e1 - wm * e0[m] : e1 - e0[m]);
             }
         }
@@ -151,9 +154,10 @@ __device__ __forceinline__ void dcs_adjoint_point(const float* __restrict__ E, c
             const I pt = gt - st.o[k][0], pi = gi - st.o[k][1], px = gx - st.o[k][2];
             if (!inner && !inside(pt, pi, px)) continue;
             const I jp = (pt * ILg + pi) * XLg + px;
-            const float wk = st.w[k];
 #pragma unroll
             for (int m = 0; m < 3; m++) {
+                if (PLANES && !((st.member[k] >> m) & 1u)) continue;
+                const float wk = PLANES ? st.wp[k][m] : st.w[k];
                 const float ep = E[m * G + jp];
                 nbr[m] += R[m * G + jp] * wk * sgn(st.literal ? ep - wk * e0[m] : ep - e0[m]);
             }
@@ -163,7 +167,7 @@ __device__ __forceinline__ void dcs_adjoint_point(const float* __restrict__ E, c
     for (int m = 0; m < 3; m++) gE[m * G + j] = R[m * G + j] * own[m] - nbr[m];
 }
 
-template <bool SYM>
+template <bool SYM, bool PLANES>
 __global__ __launch_bounds__(256) void k_dcs_adjoint(const float* __restrict__ E, const float* __restrict__ R,
                                                      float* __restrict__ gE, int64_t Tg, int64_t ILg, int64_t XLg,
                                                      DcsStencil st) {
@@ -171,9 +175,9 @@ __global__ __launch_bounds__(256) void k_dcs_adjoint(const float* __restrict__ E
     const int64_t j = xcd_block((G + 255) / 256) * 256 + threadIdx.x;
     if (j >= G) return;
     if (3 * G < (int64_t(1) << 31))
-        dcs_adjoint_point<int32_t, SYM>(E, R, gE, (int32_t)Tg, (int32_t)ILg, (int32_t)XLg, st, (int32_t)j);
+        dcs_adjoint_point<int32_t, SYM, PLANES>(E, R, gE, (int32_t)Tg, (int32_t)ILg, (int32_t)XLg, st, (int32_t)j);
     else
-        dcs_adjoint_point<int64_t, SYM>(E, R, gE, Tg, ILg, XLg, st, j);
+        dcs_adjoint_point<int64_t, SYM, PLANES>(E, R, gE, Tg, ILg, XLg, st, j);
 }
 
 sal_status launch_dcs_adjoint(const float* E, const float* R, float* gE, int64_t Tg, int64_t ILg, int64_t XLg,
@@ -183,32 +187,47 @@ sal_status launch_dcs_adjoint(const float* E, const float* R, float* gE, int64_t
     const int64_t blocks = xcd_grid((G + 255) / 256);
     if (!wide_grid_fits(blocks, 256)) return fail(SAL_ERR_SHAPE, "grid too large for one launch");
     const dim3 grid = wide_grid(blocks, 256);
-    if (st.symmetric)
-        hipLaunchKernelGGL(k_dcs_adjoint<true>, grid, dim3(256), 0, stream, E, R, gE, Tg, ILg, XLg, st);
+    if (st.symmetric && st.planes)
+        hipLaunchKernelGGL((k_dcs_adjoint<true, true>), grid, dim3(256), 0, stream, E, R, gE, Tg, ILg, XLg, st);
+    else if (st.symmetric)
+        hipLaunchKernelGGL((k_dcs_adjoint<true, false>), grid, dim3(256), 0, stream, E, R, gE, Tg, ILg, XLg, st);
+    else if (st.planes)
+        hipLaunchKernelGGL((k_dcs_adjoint<false, true>), grid, dim3(256), 0, stream, E, R, gE, Tg, ILg, XLg, st);
     else
-        hipLaunchKernelGGL(k_dcs_adjoint<false>, grid, dim3(256), 0, stream, E, R, gE, Tg, ILg, XLg, st);
+        hipLaunchKernelGGL((k_dcs_adjoint<false, false>), grid, dim3(256), 0, stream, E, R, gE, Tg, ILg, XLg, st);
     return check_hip(hipGetLastError(), "launch k_dcs_adjoint");
 }
 
 // ---------------------------------------------------------------- fusion (Eq. 4)
 
 // Per-block FP64 partial sums over the masked grid points of
-// u u^T (6), u D (3), D^2, count, in a fixed order (deterministic).
+// u u^T (6), u D (3), D^2, count, in a fixed order (deterministic).  Block (b, k) covers part
+// b of weight group k (part: [K][kFuseParts][kStats]); one group is the whole grid in memory
+// order.
 __global__ __launch_bounds__(256) void k_fuse_stats(const float* __restrict__ Sm, const float* __restrict__ D,
-                                                    const uint8_t* __restrict__ mask, int64_t G,
-                                                    double* __restrict__ part) {
+                                                    const uint8_t* __restrict__ mask, int64_t Tg, int64_t ILg,
+                                                    int64_t XLg, int64_t sections, double* __restrict__ part) {
     __shared__ double red[256];
-    fuse_stats_block(Sm, D, mask, G, (int64_t)blockIdx.x * blockDim.x, (int64_t)gridDim.x * blockDim.x,
-                     part + (int64_t)blockIdx.x * kStats, red);
+    const int64_t G = Tg * ILg * XLg;
+    const int64_t k = blockIdx.y;
+    double* out = part + (k * kFuseParts + blockIdx.x) * kStats;
+    const int64_t first = (int64_t)blockIdx.x * blockDim.x, stride = (int64_t)gridDim.x * blockDim.x;
+    if (sections > 0)
+        fuse_stats_group<true>(Sm, D, mask, G, group_map(Tg, ILg, XLg, sections, k), first, stride, out, red);
+    else
+        fuse_stats_block(Sm, D, mask, G, first, stride, out, red);
 }
 
-// One block: fixed-order reduction of the partials and the 3x3 solve.  Writes
-// W[0..2] and the status word W[3]; also the reduced statistics to stats_out.
+// One block per weight group: fixed-order reduction of the group's partials and the 3x3
+// solve.  Writes W[4k .. 4k+2] and the status word W[4k+3]; also the reduced statistics of
+// group k to stats_out[16k ..].
 __global__ __launch_bounds__(64) void k_fuse_solve(const double* __restrict__ part, int nparts, int mode,
                                                    double w0, double w1, double w2, double delta,
                                                    double* __restrict__ W, double* __restrict__ stats_out) {
     __shared__ double st[kStats];
-    solve_weights(part, nparts, mode, w0, w1, w2, delta, W, stats_out, st);
+    const int64_t k = blockIdx.x;
+    solve_weights(part + k * nparts * kStats, nparts, mode, w0, w1, w2, delta, W + 4 * k,
+                  stats_out ? stats_out + 16 * k : nullptr, st);
 }
 
 // S(v) = sum_m W_m S_m(g(v)) (same arithmetic as combine_row): kCombineRows (t, il) rows per
@@ -218,24 +237,28 @@ __global__ __launch_bounds__(64) void k_fuse_solve(const double* __restrict__ pa
 // along il), and an element finds its row by comparisons, so the loop has no 64-bit division.
 constexpr int kCombineRows = 4;
 
-template <int SS>
+// SECT: each row takes the weights of its grid cell's group (W: [K][4], `sections` inline
+// planes per group).
+template <int SS, bool SECT>
 __global__ __launch_bounds__(256) void k_combine4(const float* __restrict__ Sm, const double* __restrict__ W,
                                                   int64_t Tg, int64_t ILg, int64_t XLg, int64_t T, int64_t IL,
-                                                  int64_t XL, int s_rt, float* __restrict__ S) {
+                                                  int64_t XL, int s_rt, int64_t sections, float* __restrict__ S) {
     const int s = SS > 0 ? SS : s_rt;
     const int64_t G = Tg * ILg * XLg;
-    const double W0 = W[0], W1 = W[1], W2 = W[2];
+    double W0 = W[0], W1 = W[1], W2 = W[2];
     const int sh = (s - 1) / 2;
     const int64_t q = XL / 4;
     const int64_t row0 = block_id() * kCombineRows;
     const int64_t nrow = T * IL - row0 < kCombineRows ? T * IL - row0 : kCombineRows;
-    int64_t base[kCombineRows], orow[kCombineRows];
+    int64_t base[kCombineRows], orow[kCombineRows], wrow[kCombineRows];
     {
         int64_t t = row0 / IL, i = row0 - t * IL;
 #pragma unroll
         for (int r = 0; r < kCombineRows; r++) {
-            base[r] = (cell_of(t, s, Tg) * ILg + cell_of(i, s, ILg)) * XLg;
+            const int64_t gi = cell_of(i, s, ILg);
+            base[r] = (cell_of(t, s, Tg) * ILg + gi) * XLg;
             orow[r] = (row0 + r) * XL;
+            wrow[r] = SECT ? 4 * (gi / sections) : 0;
             if (++i == IL) {
                 i = 0;
                 t++;
@@ -246,13 +269,19 @@ __global__ __launch_bounds__(256) void k_combine4(const float* __restrict__ Sm, 
         int r = 0;
 #pragma unroll
         for (int k = 1; k < kCombineRows; k++) r += e >= k * q;
-        int64_t b = base[0], ob = orow[0];
+        int64_t b = base[0], ob = orow[0], wo = wrow[0];
 #pragma unroll
         for (int k = 1; k < kCombineRows; k++)
             if (r == k) {
                 b = base[k];
                 ob = orow[k];
+                wo = wrow[k];
             }
+        if constexpr (SECT) {
+            W0 = W[wo];
+            W1 = W[wo + 1];
+            W2 = W[wo + 2];
+        }
         const int x0 = (int)(e - r * q) * 4;
         auto value = [&](int gx) {
             const int64_t j = b + gx;
@@ -279,43 +308,59 @@ __global__ __launch_bounds__(256) void k_combine4(const float* __restrict__ Sm, 
 // S(v) = sum_m W_m S_m(g(v)); one block per (t, il) row (any XL).
 __global__ __launch_bounds__(256) void k_combine(const float* __restrict__ Sm, const double* __restrict__ W,
                                                  int64_t Tg, int64_t ILg, int64_t XLg, int64_t T, int64_t IL,
-                                                 int64_t XL, int s, float* __restrict__ S) {
+                                                 int64_t XL, int s, int64_t sections, float* __restrict__ S) {
     const int64_t row = block_id();  // one block per (t, il) row
     if (row >= T * IL) return;
-    combine_row(Sm, W, Tg, ILg, XLg, IL, XL, s, row, S);
+    combine_row(Sm, W, Tg, ILg, XLg, IL, XL, s, row, S, sections);
 }
 
-size_t fuse_workspace_bytes() { return sizeof(double) * (kFuseParts * kStats + 16); }
+// Forward workspace over K groups: partials [K][kFuseParts][kStats], then [K][16] reduced
+// statistics.
+size_t fuse_workspace_bytes(int64_t K) { return sizeof(double) * (size_t)K * (kFuseParts * kStats + 16); }
+
+template <int SS>
+static void launch_combine4(bool sect, dim3 grid, hipStream_t stream, const float* Sm, const double* W, int64_t Tg,
+                            int64_t ILg, int64_t XLg, int64_t T, int64_t IL, int64_t XL, int s, int64_t sections,
+                            float* S) {
+    if (sect)
+        hipLaunchKernelGGL((k_combine4<SS, true>), grid, dim3(256), 0, stream, Sm, W, Tg, ILg, XLg, T, IL, XL, s,
+                           sections, S);
+    else
+        hipLaunchKernelGGL((k_combine4<SS, false>), grid, dim3(256), 0, stream, Sm, W, Tg, ILg, XLg, T, IL, XL, s,
+                           sections, S);
+}
 
 sal_status launch_fuse(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion& f, const float* D,
                        const uint8_t* mask, int64_t T, int64_t IL, int64_t XL, int s, double* W, float* S, double* ws,
                        hipStream_t stream) {
-    const int64_t G = Tg * ILg * XLg;
+    const int64_t K = fuse_groups(f.sections, ILg);
+    const int64_t sections = K > 1 ? f.sections : 0;  // one group covers the grid: the plain path
+    if (K > 65535) return fail(SAL_ERR_SHAPE, "too many weight groups for one launch");
     if (f.mode == SAL_FUSE_ADAPT_LS) {
-        hipLaunchKernelGGL(k_fuse_stats, dim3(kFuseParts), dim3(256), 0, stream, Sm, D, mask, G, ws);
+        hipLaunchKernelGGL(k_fuse_stats, dim3(kFuseParts, (unsigned)K), dim3(256), 0, stream, Sm, D, mask, Tg, ILg,
+                           XLg, sections, ws);
         sal_status st = check_hip(hipGetLastError(), "launch k_fuse_stats");
         if (st) return st;
     }
-    hipLaunchKernelGGL(k_fuse_solve, dim3(1), dim3(64), 0, stream, ws, kFuseParts, f.mode, f.w_fixed[0], f.w_fixed[1],
-                       f.w_fixed[2], f.delta, W, f.mode == SAL_FUSE_ADAPT_LS ? ws + kFuseParts * kStats : nullptr);
+    hipLaunchKernelGGL(k_fuse_solve, dim3((unsigned)K), dim3(64), 0, stream, ws, kFuseParts, f.mode, f.w_fixed[0],
+                       f.w_fixed[1], f.w_fixed[2], f.delta, W,
+                       f.mode == SAL_FUSE_ADAPT_LS ? ws + K * kFuseParts * kStats : nullptr);
     sal_status st = check_hip(hipGetLastError(), "launch k_fuse_solve");
     if (st) return st;
     if (T * IL * XL == 0) return SAL_OK;
     if (!wide_grid_fits(T * IL, 256)) return fail(SAL_ERR_SHAPE, "volume too large for one launch");
     if (XL % 4 == 0 && reinterpret_cast<uintptr_t>(S) % 16 == 0) {
-        const int64_t blocks = (T * IL + kCombineRows - 1) / kCombineRows;
+        const dim3 grid = wide_grid((T * IL + kCombineRows - 1) / kCombineRows, 256);
+        const bool sect = sections > 0;
         if (s == 1)
-            hipLaunchKernelGGL(k_combine4<1>, wide_grid(blocks, 256), dim3(256), 0, stream, Sm, W, Tg, ILg, XLg, T, IL,
-                               XL, s, S);
+            launch_combine4<1>(sect, grid, stream, Sm, W, Tg, ILg, XLg, T, IL, XL, s, sections, S);
         else if (s == 2)
-            hipLaunchKernelGGL(k_combine4<2>, wide_grid(blocks, 256), dim3(256), 0, stream, Sm, W, Tg, ILg, XLg, T, IL,
-                               XL, s, S);
+            launch_combine4<2>(sect, grid, stream, Sm, W, Tg, ILg, XLg, T, IL, XL, s, sections, S);
         else
-            hipLaunchKernelGGL(k_combine4<0>, wide_grid(blocks, 256), dim3(256), 0, stream, Sm, W, Tg, ILg, XLg, T, IL,
-                               XL, s, S);
+            launch_combine4<0>(sect, grid, stream, Sm, W, Tg, ILg, XLg, T, IL, XL, s, sections, S);
     } else {
         hipLaunchKernelGGL(k_combine, wide_grid(T * IL, 256), dim3(256), 0, stream, Sm, W, Tg, ILg, XLg, T, IL, XL,
-                           s, S);
+                           s, sections, S);
     }
     return check_hip(hipGetLastError(), "launch k_combine");
 }
@@ -354,83 +399,115 @@ __global__ __launch_bounds__(256) void k_cell_sum(const float* __restrict__ gS, 
     cell[j] = cell_sum<I>(gS, (I)T, (I)IL, (I)XL, s, Tg, ILg, XLg, j / (XLg * ILg), (j / XLg) % ILg, j % XLg);
 }
 
-// Per-block FP64 partials of gW_m = sum_g S_m(g) c(g), and (ADAPT_LS) nothing else:
-// the lambda terms need the solved gW first.
+// Per-block FP64 partials of gW_m = sum_g S_m(g) c(g) over weight group blockIdx.y (part:
+// [K][kFuseParts][3]); the lambda terms need the solved gW first.
 __global__ __launch_bounds__(256) void k_gw_partials(const float* __restrict__ Sm, const float* __restrict__ cell,
-                                                     int64_t G, double* __restrict__ part) {
+                                                     int64_t Tg, int64_t ILg, int64_t XLg, int64_t sections,
+                                                     double* __restrict__ part) {
     __shared__ double red[256];
+    const int64_t G = Tg * ILg * XLg;
+    const int64_t k = blockIdx.y;
+    const GroupMap gm = group_map(Tg, ILg, XLg, sections, k);
+    const int64_t cnt = sections > 0 ? gm.count : G;
     double a[3] = {0.0, 0.0, 0.0};
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < G; j += stride) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += stride) {
+        const int64_t j = sections > 0 ? (e / gm.slab) * gm.plane + gm.first + e % gm.slab : e;
         const double c = cell[j];
         a[0] += (double)Sm[j] * c;
         a[1] += (double)Sm[G + j] * c;
         a[2] += (double)Sm[2 * G + j] * c;
     }
-    for (int k = 0; k < 3; k++) {
-        red[threadIdx.x] = a[k];
+    double* out = part + (k * gridDim.x + blockIdx.x) * 3;
+    for (int m = 0; m < 3; m++) {
+        red[threadIdx.x] = a[m];
         __syncthreads();
         for (int w = 128; w > 0; w >>= 1) {
             if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
             __syncthreads();
         }
-        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * 3 + k] = red[0];
+        if (threadIdx.x == 0) out[m] = red[0];
         __syncthreads();
     }
 }
 
-// lambda = (G + delta I)^-1 gW, from the reduced statistics of the forward.
+// One block per weight group k: lambda_k = (G_k + delta I)^-1 gW_k from the group's reduced
+// statistics of the forward (stats: [K][16], lambda written at stats[16k + 11 ..]).
 __global__ __launch_bounds__(64) void k_gw_solve(const double* __restrict__ part, int nparts,
-                                                 const double* __restrict__ stats, double delta,
-                                                 double* __restrict__ lam) {
+                                                 double* __restrict__ stats, double delta) {
     __shared__ double gw[3];
     __shared__ double red[16 * 64];
-    sum_columns64(part, nparts, 3, red, gw);
+    const int64_t k = blockIdx.x;
+    sum_columns64(part + k * nparts * 3, nparts, 3, red, gw);
     if (threadIdx.x != 0) return;
-    const double A[9] = {stats[0] + delta, stats[1], stats[2], stats[1], stats[3] + delta, stats[4],
-                         stats[2], stats[4], stats[5] + delta};
+    double* st = stats + 16 * k;
+    const double A[9] = {st[0] + delta, st[1], st[2], st[1], st[3] + delta, st[4], st[2], st[4], st[5] + delta};
     double x[3] = {0.0, 0.0, 0.0};
     if (chol3(A, gw, x)) x[0] = x[1] = x[2] = 0.0;
-    lam[0] = x[0]; lam[1] = x[1]; lam[2] = x[2];
+    st[11] = x[0]; st[12] = x[1]; st[13] = x[2];
 }
 
 // gS_m(g) = W_m c(g) (+ on the mask, ADAPT_LS: lambda_m (D - W.u) - W_m (lambda.u)), stored
-// divided by the neighbour count Q(g).  Without a cell-sum buffer (cell == nullptr) c(g) is
-// summed here from gS.
-// I = int32_t when the grid's three planes fit it.
+// divided by the neighbour count Q_m(g), with W and lambda of g's weight group (W: [K][4],
+// lambda at lam[16k ..]).  Without a cell-sum buffer (cell == nullptr) c(g) is summed here
+// from gS.  I = int32_t when the grid's three planes fit it.
 template <typename I>
 __global__ __launch_bounds__(256) void k_gsm(const float* __restrict__ Sm, const float* __restrict__ cell,
                                              const double* __restrict__ W, const double* __restrict__ lam,
                                              const float* __restrict__ D, const uint8_t* __restrict__ mask,
                                              int64_t Tg_, int64_t ILg_, int64_t XLg_, DcsStencil ds, int adapt,
-                                             const float* __restrict__ gS, int64_t T, int64_t IL, int64_t XL, int s,
-                                             float* __restrict__ R) {
+                                             int64_t sections, const float* __restrict__ gS, int64_t T, int64_t IL,
+                                             int64_t XL, int s, float* __restrict__ R) {
     const I Tg = (I)Tg_, ILg = (I)ILg_, XLg = (I)XLg_;
     const I G = Tg * ILg * XLg;
     const int64_t j64 = block_id() * blockDim.x + threadIdx.x;
     if (j64 >= (int64_t)G) return;
     const I j = (I)j64;
-    // neighbours of g inside the grid (all q of them away from the borders)
+    // neighbours of g inside the grid (all q of them away from the borders), per plane with
+    // per-plane stencils
     const I gx = j % XLg, gi = (j / XLg) % ILg, gt = j / (XLg * ILg);
-    int Q = ds.q;
-    if (!(gt >= ds.reach[0] && gt + ds.reach[0] < Tg && gi >= ds.reach[1] && gi + ds.reach[1] < ILg &&
-          gx >= ds.reach[2] && gx + ds.reach[2] < XLg)) {
-        Q = 0;
+    int Q[3];
+    if (!ds.planes) {
+        Q[0] = ds.q;
+        if (!(gt >= ds.reach[0] && gt + ds.reach[0] < Tg && gi >= ds.reach[1] && gi + ds.reach[1] < ILg &&
+              gx >= ds.reach[2] && gx + ds.reach[2] < XLg)) {
+            Q[0] = 0;
+            for (int k = 0; k < ds.q; k++) {
+                const I a = gt + ds.o[k][0], b = gi + ds.o[k][1], c = gx + ds.o[k][2];
+                Q[0] += a >= 0 && a < Tg && b >= 0 && b < ILg && c >= 0 && c < XLg;
+            }
+        }
+        Q[1] = Q[2] = Q[0];
+    } else {
+        Q[0] = Q[1] = Q[2] = 0;
         for (int k = 0; k < ds.q; k++) {
             const I a = gt + ds.o[k][0], b = gi + ds.o[k][1], c = gx + ds.o[k][2];
-            Q += a >= 0 && a < Tg && b >= 0 && b < ILg && c >= 0 && c < XLg;
+            if (!(a >= 0 && a < Tg && b >= 0 && b < ILg && c >= 0 && c < XLg)) continue;
+            const unsigned mb = ds.member[k];
+            Q[0] += mb & 1u;
+            Q[1] += (mb >> 1) & 1u;
+            Q[2] += (mb >> 2) & 1u;
         }
     }
+    const int64_t grp = sections > 0 ? (int64_t)gi / sections : 0;
+    const double* Wg = W + 4 * grp;
     const double c = cell ? cell[j] : cell_sum<I>(gS, (I)T, (I)IL, (I)XL, s, Tg, ILg, XLg, gt, gi, gx);
-    double g[3] = {W[0] * c, W[1] * c, W[2] * c};
-    if (adapt && W[3] == 0.0 && (!mask || mask[j])) {
+    double g[3] = {Wg[0] * c, Wg[1] * c, Wg[2] * c};
+    if (adapt && Wg[3] == 0.0 && (!mask || mask[j])) {
+        const double* lg = lam + 16 * grp;
         const double u0 = Sm[j], u1 = Sm[G + j], u2 = Sm[2 * G + j];
-        const double r = (double)D[j] - (W[0] * u0 + W[1] * u1 + W[2] * u2);
-        const double lu = lam[0] * u0 + lam[1] * u1 + lam[2] * u2;
-        for (int m = 0; m < 3; m++) g[m] += lam[m] * r - W[m] * lu;
+        const double r = (double)D[j] - (Wg[0] * u0 + Wg[1] * u1 + Wg[2] * u2);
+        const double lu = lg[0] * u0 + lg[1] * u1 + lg[2] * u2;
+        for (int m = 0; m < 3; m++) g[m] += lg[m] * r - Wg[m] * lu;
     }
 #pragma unroll
-    for (int m = 0; m < 3; m++) R[m * G + j] = Q ? (float)g[m] / (float)Q : 0.f;
+    for (int m = 0; m < 3; m++) R[m * G + j] = Q[m] ? (float)g[m] / (float)Q[m] : 0.f;
+}
+
+// Adjoint workspace over K groups (doubles): forward partials [K][P][kStats] | statistics
+// [K][16] (kStats values, lambda at +11) | gW partials [K][P][3] | the solve's weights [K][4].
+size_t fuse_adjoint_workspace_bytes(int64_t K) {
+    return sizeof(double) * (size_t)K * (kFuseParts * kStats + 16 + 3 * kFuseParts + 4);
 }
 
 sal_status launch_fuse_adjoint(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion& f,
@@ -439,6 +516,9 @@ sal_status launch_fuse_adjoint(const float* Sm, int64_t Tg, int64_t ILg, int64_t
                                hipStream_t stream) {
     const int64_t G = Tg * ILg * XLg;
     if (G == 0) return SAL_OK;
+    const int64_t K = fuse_groups(f.sections, ILg);
+    const int64_t sections = K > 1 ? f.sections : 0;
+    if (K > 65535) return fail(SAL_ERR_SHAPE, "too many weight groups for one launch");
     const int64_t nb = (G + 255) / 256;
     if (!wide_grid_fits(nb, 256)) return fail(SAL_ERR_SHAPE, "grid too large for one launch");
     const dim3 blocks = wide_grid(nb, 256);
@@ -457,33 +537,32 @@ sal_status launch_fuse_adjoint(const float* Sm, int64_t Tg, int64_t ILg, int64_t
         if ((st = check_hip(hipGetLastError(), "launch k_cell_sum"))) return st;
     }
     const float* cellp = adapt ? cell : nullptr;
-    double* lam = ws + kFuseParts * kStats + 11;  // after the forward's reduced statistics
+    double* part = ws;
+    double* stats = ws + K * kFuseParts * kStats;  // [K][16]: statistics, then lambda at +11
+    double* gwp = stats + 16 * K;
+    double* wtmp = gwp + 3 * K * kFuseParts;
     if (adapt) {
         // statistics of the forward, recomputed here so the adjoint does not depend on workspace state
-        hipLaunchKernelGGL(k_fuse_stats, dim3(kFuseParts), dim3(256), 0, stream, Sm, D, mask, G, ws);
+        hipLaunchKernelGGL(k_fuse_stats, dim3(kFuseParts, (unsigned)K), dim3(256), 0, stream, Sm, D, mask, Tg, ILg,
+                           XLg, sections, part);
         if ((st = check_hip(hipGetLastError(), "launch k_fuse_stats"))) return st;
-        hipLaunchKernelGGL(k_fuse_solve, dim3(1), dim3(64), 0, stream, ws, kFuseParts, (int)SAL_FUSE_ADAPT_LS, 0.0,
-                           0.0, 0.0, f.delta, ws + kFuseParts * kStats + 16 + 3 * kFuseParts,
-                           ws + kFuseParts * kStats);
+        hipLaunchKernelGGL(k_fuse_solve, dim3((unsigned)K), dim3(64), 0, stream, part, kFuseParts,
+                           (int)SAL_FUSE_ADAPT_LS, 0.0, 0.0, 0.0, f.delta, wtmp, stats);
         if ((st = check_hip(hipGetLastError(), "launch k_fuse_solve"))) return st;
-        double* gwp = ws + kFuseParts * kStats + 16;
-        hipLaunchKernelGGL(k_gw_partials, dim3(kFuseParts), dim3(256), 0, stream, Sm, cell, G, gwp);
+        hipLaunchKernelGGL(k_gw_partials, dim3(kFuseParts, (unsigned)K), dim3(256), 0, stream, Sm, cell, Tg, ILg,
+                           XLg, sections, gwp);
         if ((st = check_hip(hipGetLastError(), "launch k_gw_partials"))) return st;
-        hipLaunchKernelGGL(k_gw_solve, dim3(1), dim3(64), 0, stream, gwp, kFuseParts, ws + kFuseParts * kStats,
-                           f.delta, lam);
+        hipLaunchKernelGGL(k_gw_solve, dim3((unsigned)K), dim3(64), 0, stream, gwp, kFuseParts, stats, f.delta);
         if ((st = check_hip(hipGetLastError(), "launch k_gw_solve"))) return st;
     }
+    const double* lam = stats + 11;
     if (i32)
         hipLaunchKernelGGL(k_gsm<int32_t>, blocks, dim3(256), 0, stream, Sm, cellp, W, lam, D, mask, Tg, ILg,
-                           XLg, ds, adapt, gS, T, IL, XL, s, R);
+                           XLg, ds, adapt, sections, gS, T, IL, XL, s, R);
     else
         hipLaunchKernelGGL(k_gsm<int64_t>, blocks, dim3(256), 0, stream, Sm, cellp, W, lam, D, mask, Tg, ILg,
-                           XLg, ds, adapt, gS, T, IL, XL, s, R);
+                           XLg, ds, adapt, sections, gS, T, IL, XL, s, R);
     return check_hip(hipGetLastError(), "launch k_gsm");
-}
-
-size_t fuse_adjoint_workspace_bytes() {
-    return sizeof(double) * (kFuseParts * kStats + 16 + 3 * kFuseParts + 16);
 }
 
 }  // namespace sal

@@ -694,13 +694,13 @@ struct BwdWs {
 
 static size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 
-static BwdWs bwd_ws(int64_t G, const AdjLayout& L) {
+static BwdWs bwd_ws(int64_t G, const AdjLayout& L, int64_t K) {
     BwdWs w;
     w.cell = 0;
     w.gsm = w.cell + al256(sizeof(float) * G);
     w.ge = w.gsm + al256(sizeof(float) * 3 * G);
     w.fus = w.ge + al256(sizeof(float) * 3 * G);
-    w.part = w.fus + al256(fuse_adjoint_workspace_bytes());
+    w.part = w.fus + al256(fuse_adjoint_workspace_bytes(K));
     w.total = w.part + al256(L.part_bytes);
     return w;
 }
@@ -711,12 +711,15 @@ using namespace sal;
 
 extern "C" {
 
-size_t sal_backward_workspace_size(int64_t T, int64_t IL, int64_t XL, const sal_spec* spec) {
+size_t sal_backward_workspace_size(int64_t T, int64_t IL, int64_t XL, const sal_spec* spec,
+                                   const sal_fusion* fusion) {
     if (check_spec(spec, T, IL, XL) != SAL_OK) return 0;
     AdjLayout L;
     if (adj_layout_dispatch(spec->n, spec->s, T, IL, XL, &L) != SAL_OK) return 0;
-    const int64_t G = ceil_div(T, spec->s) * ceil_div(IL, spec->s) * ceil_div(XL, spec->s);
-    return bwd_ws(G, L).total;
+    const int64_t ILg = ceil_div(IL, spec->s);
+    const int64_t G = ceil_div(T, spec->s) * ILg * ceil_div(XL, spec->s);
+    const int64_t K = fusion && fusion->sections > 0 ? fuse_groups(fusion->sections, ILg) : 1;
+    return bwd_ws(G, L, K).total;
 }
 
 sal_status sal_backward(const float* V, int64_t T, int64_t IL, int64_t XL, const sal_spec* spec,
@@ -733,13 +736,14 @@ sal_status sal_backward(const float* V, int64_t T, int64_t IL, int64_t XL, const
         return fail(SAL_ERR_ARG, "unknown fusion mode");
     if (fusion->mode == SAL_FUSE_ADAPT_LS && (!D || !(fusion->delta >= 0.0)))
         return fail(SAL_ERR_ARG, "ADAPT_LS needs D and delta >= 0");
+    if (fusion->sections < 0) return fail(SAL_ERR_ARG, "sections must be >= 0");
     DcsStencil ds;
     if ((st = make_stencil(stencil, spec->s, &ds))) return st;
     AdjLayout L;
     if ((st = adj_layout_dispatch(spec->n, spec->s, T, IL, XL, &L))) return st;
     const int s = spec->s;
     const int64_t Tg = ceil_div(T, s), ILg = ceil_div(IL, s), XLg = ceil_div(XL, s), G = Tg * ILg * XLg;
-    const BwdWs lay = bwd_ws(G, L);
+    const BwdWs lay = bwd_ws(G, L, fuse_groups(fusion->sections, ILg));
     if (!ws || ws_bytes < lay.total) return fail(SAL_ERR_NOMEM, "workspace smaller than sal_backward_workspace_size()");
     char* base = (char*)ws;
     float* cell = (float*)(base + lay.cell);
@@ -748,7 +752,7 @@ sal_status sal_backward(const float* V, int64_t T, int64_t IL, int64_t XL, const
     double* fws = (double*)(base + lay.fus);
     float* part = (float*)(base + lay.part);
     const Tables* tb = nullptr;
-    if ((st = get_tables(spec->n, spec->window, &tb))) return st;
+    if ((st = get_tables(stream, spec->n, spec->window, &tb))) return st;
 
     if ((st = launch_fuse_adjoint(Sm, Tg, ILg, XLg, *fusion, D, mask, W, gS, T, IL, XL, s, ds, cell, fws, gSq,
                                   stream)))

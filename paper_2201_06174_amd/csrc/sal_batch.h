@@ -30,6 +30,9 @@ struct FuseItem {
 };
 
 sal_status launch_dcs_batch(const DcsItem* items, const int64_t* first, int n, int64_t blocks, hipStream_t stream);
+// The plan's status word: status[0] = members whose W[3] flags an equal-weight fallback,
+// status[1] = the lowest such member (-1 if none).
+sal_status launch_plan_status(const FuseItem* items, int n, int64_t* status, hipStream_t stream);
 sal_status launch_fuse_batch(const FuseItem* items, int n, const int* adapt_list, int nadapt, const int64_t* first,
                              int64_t rows, hipStream_t stream);
 

@@ -1,5 +1,7 @@
 // sal_batch.hip -- batched center-surround and fusion kernels: one launch covers every
 // volume of a plan, each block looking up the volume it serves in a small table.
+#include <cstdint>
+
 #include "sal_batch.h"
 #include "sal_device.h"
 
@@ -48,6 +50,38 @@ __global__ __launch_bounds__(256) void k_combine_batch(const FuseItem* __restric
     const int a = find_item(first, n, b);
     const FuseItem& it = items[a];
     combine_row(it.Sm, it.W, it.Tg, it.ILg, it.XLg, it.IL, it.XL, it.s, b - first[a], it.S);
+}
+
+// One block of 256 threads: counts the members whose status word W[3] is set and finds the
+// lowest of them (integer reductions in a fixed order).
+__global__ __launch_bounds__(256) void k_plan_status(const FuseItem* __restrict__ items, int n,
+                                                     int64_t* __restrict__ status) {
+    __shared__ int64_t cnt[256], low[256];
+    int64_t c = 0, l = INT64_MAX;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        if (items[i].W[3] != 0.0) {
+            c++;
+            l = l < i ? l : i;
+        }
+    cnt[threadIdx.x] = c;
+    low[threadIdx.x] = l;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            cnt[threadIdx.x] += cnt[threadIdx.x + w];
+            low[threadIdx.x] = low[threadIdx.x] < low[threadIdx.x + w] ? low[threadIdx.x] : low[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        status[0] = cnt[0];
+        status[1] = cnt[0] ? low[0] : -1;
+    }
+}
+
+sal_status launch_plan_status(const FuseItem* items, int n, int64_t* status, hipStream_t stream) {
+    hipLaunchKernelGGL(k_plan_status, dim3(1), dim3(256), 0, stream, items, n, status);
+    return check_hip(hipGetLastError(), "launch k_plan_status");
 }
 
 sal_status launch_dcs_batch(const DcsItem* items, const int64_t* first, int n, int64_t blocks, hipStream_t stream) {

@@ -11,8 +11,9 @@ namespace sal {
 
 // S_m at grid point j of one volume (Sec. 2, Eq. 3): (1/Q) sum over in-grid neighbours.
 // A point at least the stencil reach away from every border has all q neighbours in the
-// grid and skips the bounds tests (same terms, same order).
-template <typename I>
+// grid and skips the bounds tests (same terms, same order).  PLANES: per-plane stencils,
+// each plane summing over its own members with its own weights and its own count Q_m.
+template <typename I, bool PLANES>
 __device__ __forceinline__ void dcs_point_t(const float* __restrict__ E, float* __restrict__ S, I Tg, I ILg, I XLg,
                                             const DcsStencil& st, I j) {
     const I G = Tg * ILg * XLg;
@@ -21,42 +22,73 @@ __device__ __forceinline__ void dcs_point_t(const float* __restrict__ E, float* 
                        gx >= st.reach[2] && gx + st.reach[2] < XLg;
     float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
     const float e0 = E[j], e1 = E[G + j], e2 = E[2 * G + j];
-    int Q = 0;
+    int Q = 0, Q1 = 0, Q2 = 0;
+    auto term = [&](float ec, float en, float w) { return st.literal ? fabsf(ec - w * en) : w * fabsf(ec - en); };
     for (int k = 0; k < st.q; k++) {
         const I nt = gt + st.o[k][0], ni = gi + st.o[k][1], nx = gx + st.o[k][2];
         if (!inner && (nt < 0 || nt >= Tg || ni < 0 || ni >= ILg || nx < 0 || nx >= XLg)) continue;
         const I jn = (nt * ILg + ni) * XLg + nx;
-        const float w = st.w[k];
-        if (st.literal) {
-            acc0 += fabsf(e0 - w * E[jn]);
-            acc1 += fabsf(e1 - w * E[G + jn]);
-            acc2 += fabsf(e2 - w * E[2 * G + jn]);
+        if constexpr (PLANES) {
+            const unsigned mb = st.member[k];
+            if (mb & 1u) { acc0 += term(e0, E[jn], st.wp[k][0]); Q++; }
+            if (mb & 2u) { acc1 += term(e1, E[G + jn], st.wp[k][1]); Q1++; }
+            if (mb & 4u) { acc2 += term(e2, E[2 * G + jn], st.wp[k][2]); Q2++; }
         } else {
-            acc0 += w * fabsf(e0 - E[jn]);
-            acc1 += w * fabsf(e1 - E[G + jn]);
-            acc2 += w * fabsf(e2 - E[2 * G + jn]);
+            const float w = st.w[k];
+            acc0 += term(e0, E[jn], w);
+            acc1 += term(e1, E[G + jn], w);
+            acc2 += term(e2, E[2 * G + jn], w);
+            Q++;
         }
-        Q++;
     }
+    if constexpr (!PLANES) Q1 = Q2 = Q;
     S[j] = Q ? acc0 / (float)Q : 0.f;
-    S[G + j] = Q ? acc1 / (float)Q : 0.f;
-    S[2 * G + j] = Q ? acc2 / (float)Q : 0.f;
+    S[G + j] = Q1 ? acc1 / (float)Q1 : 0.f;
+    S[2 * G + j] = Q2 ? acc2 / (float)Q2 : 0.f;
 }
 
 // 32-bit index arithmetic whenever the grid's three planes fit it
 __device__ __forceinline__ void dcs_point(const float* __restrict__ E, float* __restrict__ S, int64_t Tg,
                                           int64_t ILg, int64_t XLg, const DcsStencil& st, int64_t j) {
-    if (3 * Tg * ILg * XLg < (int64_t(1) << 31))
-        dcs_point_t<int32_t>(E, S, (int32_t)Tg, (int32_t)ILg, (int32_t)XLg, st, (int32_t)j);
-    else
-        dcs_point_t<int64_t>(E, S, Tg, ILg, XLg, st, j);
+    const bool i32 = 3 * Tg * ILg * XLg < (int64_t(1) << 31);
+    if (st.planes) {
+        if (i32) dcs_point_t<int32_t, true>(E, S, (int32_t)Tg, (int32_t)ILg, (int32_t)XLg, st, (int32_t)j);
+        else dcs_point_t<int64_t, true>(E, S, Tg, ILg, XLg, st, j);
+    } else {
+        if (i32) dcs_point_t<int32_t, false>(E, S, (int32_t)Tg, (int32_t)ILg, (int32_t)XLg, st, (int32_t)j);
+        else dcs_point_t<int64_t, false>(E, S, Tg, ILg, XLg, st, j);
+    }
 }
 
-// One block's FP64 partial sums of u u^T, u D, D^2 and the count over the masked
-// points j = first, first + stride, ... (fixed order: deterministic).  256 threads.
-__device__ __forceinline__ void fuse_stats_block(const float* __restrict__ Sm, const float* __restrict__ D,
-                                                 const uint8_t* __restrict__ mask, int64_t G, int64_t first,
-                                                 int64_t stride, double* __restrict__ out, double* red) {
+// The grid points of one weight group (inline planes [k N, k N + N) of the grid), numbered
+// e = 0 .. count-1 in memory order: point e is j = (e / slab) * plane + first + e % slab.
+// Without sections the group is the whole grid and j = e.
+struct GroupMap {
+    int64_t count;  // points in the group
+    int64_t slab;   // points per t plane inside the group (its inline planes x XLg)
+    int64_t plane;  // ILg * XLg
+    int64_t first;  // k N XLg
+};
+
+__device__ __forceinline__ GroupMap group_map(int64_t Tg, int64_t ILg, int64_t XLg, int64_t sections, int64_t k) {
+    GroupMap g;
+    const int64_t il0 = sections > 0 ? k * sections : 0;
+    const int64_t nk = sections > 0 ? (ILg - il0 < sections ? ILg - il0 : sections) : ILg;
+    g.slab = nk * XLg;
+    g.plane = ILg * XLg;
+    g.first = il0 * XLg;
+    g.count = Tg * g.slab;
+    return g;
+}
+
+// One block's FP64 partial sums of u u^T, u D, D^2 and the count over the masked points
+// e = first, first + stride, ... of a weight group (fixed order: deterministic).  256 threads.
+// G is the size of a whole plane of Sm; SECT maps group positions to grid points.
+template <bool SECT>
+__device__ __forceinline__ void fuse_stats_group(const float* __restrict__ Sm, const float* __restrict__ D,
+                                                 const uint8_t* __restrict__ mask, int64_t G, const GroupMap gm,
+                                                 int64_t first, int64_t stride, double* __restrict__ out,
+                                                 double* red) {
     double st[kStats];
     for (int k = 0; k < kStats; k++) st[k] = 0.0;
     auto add = [&](float f0, float f1, float f2, float fd) {
@@ -66,32 +98,38 @@ __device__ __forceinline__ void fuse_stats_block(const float* __restrict__ Sm, c
         st[6] += u0 * d; st[7] += u1 * d; st[8] += u2 * d;
         st[9] += d * d; st[10] += 1.0;
     };
+    auto J = [&](int64_t e) -> int64_t { return SECT ? (e / gm.slab) * gm.plane + gm.first + e % gm.slab : e; };
+    const int64_t cnt = SECT ? gm.count : G;
     // Four of a thread's points at a time: their loads are issued together, the sums still
-    // taken point by point in increasing j (the same order, so the same result, as one at a time).
+    // taken point by point in increasing e (the same order, so the same result, as one at a time).
     auto sweep = [&](auto masked) {
         constexpr bool MASKED = decltype(masked)::value;
-        int64_t j = first + threadIdx.x;
-        for (; j + 3 * stride < G; j += 4 * stride) {
+        int64_t e = first + threadIdx.x;
+        for (; e + 3 * stride < cnt; e += 4 * stride) {
             bool in[4];
             float v[4][4];
+            int64_t jp[4];
 #pragma unroll
-            for (int p = 0; p < 4; p++) in[p] = MASKED ? mask[j + p * stride] != 0 : true;
+            for (int p = 0; p < 4; p++) jp[p] = J(e + p * stride);
+#pragma unroll
+            for (int p = 0; p < 4; p++) in[p] = MASKED ? mask[jp[p]] != 0 : true;
 #pragma unroll
             for (int p = 0; p < 4; p++) {
-                const int64_t jp = j + p * stride;
                 if (in[p]) {
-                    v[p][0] = Sm[jp];
-                    v[p][1] = Sm[G + jp];
-                    v[p][2] = Sm[2 * G + jp];
-                    v[p][3] = D[jp];
+                    v[p][0] = Sm[jp[p]];
+                    v[p][1] = Sm[G + jp[p]];
+                    v[p][2] = Sm[2 * G + jp[p]];
+                    v[p][3] = D[jp[p]];
                 }
             }
 #pragma unroll
             for (int p = 0; p < 4; p++)
                 if (in[p]) add(v[p][0], v[p][1], v[p][2], v[p][3]);
         }
-        for (; j < G; j += stride)
+        for (; e < cnt; e += stride) {
+            const int64_t j = J(e);
             if (!MASKED || mask[j]) add(Sm[j], Sm[G + j], Sm[2 * G + j], D[j]);
+        }
     };
     if (mask)
         sweep(std::true_type{});
@@ -107,6 +145,13 @@ __device__ __forceinline__ void fuse_stats_block(const float* __restrict__ Sm, c
         if (threadIdx.x == 0) out[k] = red[0];
         __syncthreads();
     }
+}
+
+// The whole grid as one group.
+__device__ __forceinline__ void fuse_stats_block(const float* __restrict__ Sm, const float* __restrict__ D,
+                                                 const uint8_t* __restrict__ mask, int64_t G, int64_t first,
+                                                 int64_t stride, double* __restrict__ out, double* red) {
+    fuse_stats_group<false>(Sm, D, mask, G, GroupMap{}, first, stride, out, red);
 }
 
 // 3x3 Cholesky solve; 1 if A is not numerically positive definite.
@@ -204,14 +249,17 @@ __device__ __forceinline__ int64_t cell_of(int64_t v, int s, int64_t Ng) {
     return g < Ng - 1 ? g : Ng - 1;
 }
 
-// One (t, il) row of S(v) = sum_m W_m S_m(g(v)) (Eq. 4), threads striding along xl.
+// One (t, il) row of S(v) = sum_m W_m S_m(g(v)) (Eq. 4), threads striding along xl; with
+// sections > 0 the row takes the weights of its grid cell's group (W: [K][4]).
 __device__ __forceinline__ void combine_row(const float* __restrict__ Sm, const double* __restrict__ W, int64_t Tg,
                                             int64_t ILg, int64_t XLg, int64_t IL, int64_t XL, int s, int64_t row,
-                                            float* __restrict__ S) {
+                                            float* __restrict__ S, int64_t sections = 0) {
     const int64_t t = row / IL, i = row % IL;
     const int64_t G = Tg * ILg * XLg;
-    const int64_t base = (cell_of(t, s, Tg) * ILg + cell_of(i, s, ILg)) * XLg;
-    const double W0 = W[0], W1 = W[1], W2 = W[2];
+    const int64_t gi = cell_of(i, s, ILg);
+    const int64_t base = (cell_of(t, s, Tg) * ILg + gi) * XLg;
+    const double* Wr = W + 4 * (sections > 0 ? gi / sections : 0);
+    const double W0 = Wr[0], W1 = Wr[1], W2 = Wr[2];
     const int sh = (s - 1) / 2;
     for (int x = threadIdx.x; x < XL; x += blockDim.x) {
         int gx = (x + sh) / s;

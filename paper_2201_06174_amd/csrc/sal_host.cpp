@@ -1,12 +1,13 @@
 // sal_host.cpp -- error state, argument checks and the constant tables of libsal.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+#include <climits>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
-#include <map>
 #include <mutex>
 #include <string>
-#include <tuple>
 #include <vector>
 
 #include "sal_internal.h"
@@ -89,25 +90,37 @@ static uint16_t to_f16(float f) {
     return r;
 }
 
-struct DevTables {
-    Tables t;
-    void* base = nullptr;
-};
+// ---------------------------------------------------------------- device-resident tables
 
-static std::mutex g_mu;
-static std::map<std::tuple<int, int, int>, DevTables> g_tables;
+// Every constant table the kernels read lives in static device memory, one slot per
+// (n, window) and one per (n, s, window) for the reduced-precision pass-A operands, so no
+// call ever allocates for them.  They are built on the host in double and uploaded once per
+// device, by sal_init() or by the first call on the device that needs them (which must then
+// not be inside a stream capture).
+constexpr int kSides[4] = {4, 8, 12, 16};
+constexpr int kTableSlots = 4 * 2;                  // (n, window)
+constexpr size_t kTableSlotBytes = 128 * 1024;      // 122,880 B at n = 16
+constexpr int kStridesPerWindow = 1 + 3 + 5 + 7;    // 1 <= s < n/2 for n = 4, 8, 12, 16
+constexpr int kPassASlots = kStridesPerWindow * 2;  // (n, s, window)
+constexpr size_t kPassASlotBytes = 27648;           // (n/2 + 1) x 3 x 16 x 32 x 2 B at n = 16
 
-sal_status get_tables(int n, int window, const Tables** out) {
-    int dev = 0;
-    sal_status st = check_hip(hipGetDevice(&dev), "hipGetDevice");
-    if (st) return st;
-    std::lock_guard<std::mutex> lock(g_mu);
-    auto key = std::make_tuple(dev, n, window);
-    auto it = g_tables.find(key);
-    if (it != g_tables.end()) {
-        *out = &it->second.t;
-        return SAL_OK;
-    }
+__device__ __align__(256) unsigned char g_const_tables[kTableSlots * kTableSlotBytes];
+__device__ __align__(256) unsigned char g_pass_a_tables[kPassASlots * kPassASlotBytes];
+
+static int side_index(int n) {
+    for (int k = 0; k < 4; k++)
+        if (kSides[k] == n) return k;
+    return -1;
+}
+static int table_slot(int n, int window) { return side_index(n) * 2 + window; }
+static int pass_a_slot(int n, int s, int window) {
+    int base = 0;
+    for (int k = 0; k < 4 && kSides[k] != n; k++) base += kSides[k] / 2 - 1;
+    return window * kStridesPerWindow + base + (s - 1);
+}
+
+// Host image of one (n, window) table slot; fills `t` with offsets relative to the slot start.
+static std::vector<unsigned char> build_table_slot(int n, int window, Tables* t) {
     const int KH = n / 2 + 1;
     std::vector<float> passA(size_t(KH) * n * 2), mat(16 * size_t(n)), wts(size_t(KH) * n * 16 * 4, 0.f),
         inv(16 * 16, 0.f);
@@ -197,54 +210,46 @@ sal_status get_tables(int n, int window, const Tables** out) {
                 clo[(c * 16 + r) * 32 + k] = to_bf16(f - from_bf16(bh));
                 ch16[(c * 16 + r) * 32 + k] = to_f16(f);
             }
-    size_t bytes = (passA.size() + mat.size() + wts.size() + inv.size() + 2 * wnat.size()) * 4 + 3 * 1024 * 2 + 11 * 256;
-    void* base = nullptr;
-    st = check_hip(hipMalloc(&base, bytes), "hipMalloc(tables)");
-    if (st) return st;
-    char* p = (char*)base;
-    auto put = [&](const void* src, size_t nb) -> char* {
-        char* dst = p;
-        p += (nb + 255) / 256 * 256;  // keep every table 256-byte aligned
-        return (hipMemcpy(dst, src, nb, hipMemcpyHostToDevice) == hipSuccess) ? dst : nullptr;
+    std::vector<unsigned char> img(kTableSlotBytes, 0);
+    size_t off = 0;
+    auto put = [&](const void* src, size_t nb) -> size_t {
+        const size_t at = off;
+        if (at + nb > img.size()) return SIZE_MAX;
+        std::memcpy(img.data() + at, src, nb);
+        off += (nb + 255) / 256 * 256;  // keep every table 256-byte aligned
+        return at;
     };
-    DevTables dt;
-    dt.base = base;
-    dt.t.n = n;
-    dt.t.window = window;
-    dt.t.passA = (const float*)put(passA.data(), passA.size() * 4);
-    dt.t.mat = (const float*)put(mat.data(), mat.size() * 4);
-    dt.t.wts = (const float*)put(wts.data(), wts.size() * 4);
-    dt.t.inv = (const float*)put(inv.data(), inv.size() * 4);
-    dt.t.wts_nat = (const float*)put(wnat.data(), wnat.size() * 4);
-    dt.t.wts_nat_h = (const float*)put(wnat_h.data(), wnat_h.size() * 4);
-    dt.t.cpx_hi = (const uint16_t*)put(chi.data(), chi.size() * 2);
-    dt.t.cpx_lo = (const uint16_t*)put(clo.data(), clo.size() * 2);
-    dt.t.cpx_h16 = (const uint16_t*)put(ch16.data(), ch16.size() * 2);
-    if (!dt.t.passA || !dt.t.mat || !dt.t.wts || !dt.t.inv || !dt.t.wts_nat || !dt.t.wts_nat_h || !dt.t.cpx_hi ||
-        !dt.t.cpx_lo || !dt.t.cpx_h16) {
-        (void)hipFree(base);  // already failing; the upload error is the one reported
-        return fail(SAL_ERR_DEVICE, "uploading constant tables failed");
-    }
-    auto res = g_tables.emplace(key, dt);
-    *out = &res.first->second.t;
-    return SAL_OK;
+    size_t o[9];
+    o[0] = put(passA.data(), passA.size() * 4);
+    o[1] = put(mat.data(), mat.size() * 4);
+    o[2] = put(wts.data(), wts.size() * 4);
+    o[3] = put(inv.data(), inv.size() * 4);
+    o[4] = put(wnat.data(), wnat.size() * 4);
+    o[5] = put(wnat_h.data(), wnat_h.size() * 4);
+    o[6] = put(chi.data(), chi.size() * 2);
+    o[7] = put(clo.data(), clo.size() * 2);
+    o[8] = put(ch16.data(), ch16.size() * 2);
+    for (size_t v : o)
+        if (v == SIZE_MAX) return {};  // cannot happen for n <= 16 (the slot is sized for n = 16)
+    t->n = n;
+    t->window = window;
+    // offsets for now; rebased onto the device slot by the caller
+    t->passA = (const float*)o[0];
+    t->mat = (const float*)o[1];
+    t->wts = (const float*)o[2];
+    t->inv = (const float*)o[3];
+    t->wts_nat = (const float*)o[4];
+    t->wts_nat_h = (const float*)o[5];
+    t->cpx_hi = (const uint16_t*)o[6];
+    t->cpx_lo = (const uint16_t*)o[7];
+    t->cpx_h16 = (const uint16_t*)o[8];
+    return img;
 }
 
-static std::map<std::tuple<int, int, int, int>, void*> g_pa_ops;
-
-sal_status get_pass_a_ops(int n, int s, int window, const uint16_t** out) {
-    int dev = 0;
-    sal_status st = check_hip(hipGetDevice(&dev), "hipGetDevice");
-    if (st) return st;
-    std::lock_guard<std::mutex> lock(g_mu);
-    auto key = std::make_tuple(dev, n, s, window);
-    auto it = g_pa_ops.find(key);
-    if (it != g_pa_ops.end()) {
-        *out = (const uint16_t*)it->second;
-        return SAL_OK;
-    }
+// Host image of the reduced-precision pass-A operands of one (n, s, window).
+static void build_pass_a_slot(int n, int s, int window, uint16_t* ops) {
     const int KH = n / 2 + 1;
-    std::vector<uint16_t> ops(size_t(KH) * 3 * 16 * 32, 0);
+    std::memset(ops, 0, kPassASlotBytes);
     for (int kx = 0; kx < KH; kx++)
         for (int c = 0; c < 8; c++) {
             const int h = c >> 2, xc = c & 3;
@@ -260,20 +265,120 @@ sal_status get_pass_a_ops(int n, int s, int window, const uint16_t** out) {
                 o[2 * 16 * 32] = to_f16(f);
             }
         }
-    void* d = nullptr;
-    if ((st = check_hip(hipMalloc(&d, ops.size() * 2), "hipMalloc(pass A operands)"))) return st;
-    if ((st = check_hip(hipMemcpy(d, ops.data(), ops.size() * 2, hipMemcpyHostToDevice), "hipMemcpy(pass A operands)"))) {
-        (void)hipFree(d);  // already failing; the copy error is the one reported
-        return st;
+}
+
+constexpr int kMaxDevices = 64;
+
+struct DeviceTables {
+    std::atomic<bool> ready{false};
+    Tables t[kTableSlots];
+    const uint16_t* pa[kPassASlots] = {};
+};
+
+static std::mutex g_mu;
+static DeviceTables g_dev[kMaxDevices];
+
+// Builds and uploads every table for device `dev` (current); idempotent.
+static sal_status init_device_tables(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(SAL_ERR_DEVICE, "device id out of range");
+    std::lock_guard<std::mutex> lock(g_mu);
+    DeviceTables& d = g_dev[dev];
+    if (d.ready.load(std::memory_order_acquire)) return SAL_OK;
+    unsigned char* tab = nullptr;
+    unsigned char* pas = nullptr;
+    sal_status st = check_hip(hipGetSymbolAddress((void**)&tab, HIP_SYMBOL(g_const_tables)),
+                              "hipGetSymbolAddress(constant tables)");
+    if (!st) st = check_hip(hipGetSymbolAddress((void**)&pas, HIP_SYMBOL(g_pass_a_tables)),
+                            "hipGetSymbolAddress(pass A operands)");
+    if (st) return st;
+    std::vector<unsigned char> img(size_t(kTableSlots) * kTableSlotBytes);
+    for (int k = 0; k < 4; k++)
+        for (int w = 0; w < 2; w++) {
+            const int n = kSides[k], slot = table_slot(n, w);
+            Tables t;
+            std::vector<unsigned char> one = build_table_slot(n, w, &t);
+            if (one.empty()) return fail(SAL_ERR_DEVICE, "constant table slot too small");
+            std::memcpy(img.data() + size_t(slot) * kTableSlotBytes, one.data(), kTableSlotBytes);
+            unsigned char* b = tab + size_t(slot) * kTableSlotBytes;
+            t.passA = (const float*)(b + (size_t)t.passA);
+            t.mat = (const float*)(b + (size_t)t.mat);
+            t.wts = (const float*)(b + (size_t)t.wts);
+            t.inv = (const float*)(b + (size_t)t.inv);
+            t.wts_nat = (const float*)(b + (size_t)t.wts_nat);
+            t.wts_nat_h = (const float*)(b + (size_t)t.wts_nat_h);
+            t.cpx_hi = (const uint16_t*)(b + (size_t)t.cpx_hi);
+            t.cpx_lo = (const uint16_t*)(b + (size_t)t.cpx_lo);
+            t.cpx_h16 = (const uint16_t*)(b + (size_t)t.cpx_h16);
+            d.t[slot] = t;
+        }
+    std::vector<uint16_t> pimg(size_t(kPassASlots) * kPassASlotBytes / 2);
+    for (int w = 0; w < 2; w++)
+        for (int k = 0; k < 4; k++)
+            for (int s = 1; 2 * s < kSides[k]; s++) {
+                const int slot = pass_a_slot(kSides[k], s, w);
+                build_pass_a_slot(kSides[k], s, w, pimg.data() + size_t(slot) * kPassASlotBytes / 2);
+                d.pa[slot] = (const uint16_t*)(pas + size_t(slot) * kPassASlotBytes);
+            }
+    // blocking uploads: nothing reads these slots before `ready` is published below
+    st = check_hip(hipMemcpy(tab, img.data(), img.size(), hipMemcpyHostToDevice), "hipMemcpy(constant tables)");
+    if (!st) st = check_hip(hipMemcpy(pas, pimg.data(), pimg.size() * 2, hipMemcpyHostToDevice),
+                            "hipMemcpy(pass A operands)");
+    if (st) return st;
+    d.ready.store(true, std::memory_order_release);
+    return SAL_OK;
+}
+
+sal_status init_device(int dev) { return init_device_tables(dev); }
+
+// The tables of the current device, uploading them first if `stream` is not capturing.
+static sal_status device_tables(hipStream_t stream, DeviceTables** out) {
+    int dev = 0;
+    sal_status st = check_hip(hipGetDevice(&dev), "hipGetDevice");
+    if (st) return st;
+    if (dev < 0 || dev >= kMaxDevices) return fail(SAL_ERR_DEVICE, "device id out of range");
+    DeviceTables& d = g_dev[dev];
+    if (!d.ready.load(std::memory_order_acquire)) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        const hipError_t e = hipStreamIsCapturing(stream, &cs);
+        if (e != hipSuccess || cs != hipStreamCaptureStatusNone)
+            return fail(SAL_ERR_STATE, "the constant tables of this device are not uploaded yet and the stream is "
+                                       "being captured: call sal_init() on the device before capturing");
+        if ((st = init_device(dev))) return st;
     }
-    g_pa_ops.emplace(key, d);
-    *out = (const uint16_t*)d;
+    *out = &d;
+    return SAL_OK;
+}
+
+sal_status get_tables(hipStream_t stream, int n, int window, const Tables** out) {
+    if (side_index(n) < 0 || (window != SAL_WINDOW_HANN && window != SAL_WINDOW_RECT))
+        return fail(SAL_ERR_UNSUPPORTED, "no tables for this window side");
+    DeviceTables* d = nullptr;
+    sal_status st = device_tables(stream, &d);
+    if (st) return st;
+    *out = &d->t[table_slot(n, window)];
+    return SAL_OK;
+}
+
+sal_status get_pass_a_ops(hipStream_t stream, int n, int s, int window, const uint16_t** out) {
+    if (side_index(n) < 0 || s < 1 || 2 * s >= n || (window != SAL_WINDOW_HANN && window != SAL_WINDOW_RECT))
+        return fail(SAL_ERR_UNSUPPORTED, "no pass A operands for this window side and stride");
+    DeviceTables* d = nullptr;
+    sal_status st = device_tables(stream, &d);
+    if (st) return st;
+    *out = d->pa[pass_a_slot(n, s, window)];
     return SAL_OK;
 }
 
 }  // namespace sal
 
 extern "C" {
+
+sal_status sal_init(void) {
+    int dev = 0;
+    sal_status st = sal::check_hip(hipGetDevice(&dev), "hipGetDevice");
+    if (st) return st;
+    return sal::init_device(dev);
+}
 
 const char* sal_last_error(void) { return sal::g_error.c_str(); }
 

@@ -41,8 +41,8 @@ sal_status check_spec(const sal_spec* spec, int64_t T, int64_t IL, int64_t XL);
 
 // ---------------------------------------------------------------- constant tables
 
-// Per (device, n, window) device tables, built once on the host in double and
-// uploaded (the first call for a configuration copies synchronously).
+// Per (device, n, window) device tables, built once on the host in double and uploaded into
+// static device memory by sal_init() (or by the first call on a device outside a capture).
 struct Tables {
     int n = 0;
     int window = 0;
@@ -61,13 +61,18 @@ struct Tables {
     const uint16_t* cpx_h16 = nullptr;
 };
 
-sal_status get_tables(int n, int window, const Tables** out);
+// The tables of the current device.  If they are not uploaded yet and `stream` is not being
+// captured, uploads them (blocking); inside a capture fails with SAL_ERR_STATE.
+sal_status get_tables(hipStream_t stream, int n, int window, const Tables** out);
+
+// Uploads every table of device `dev` (current).
+sal_status init_device(int dev);
 
 // Per (device, n, s, window) B operands of the reduced-precision pass A, [KH][3][16 cols][32 K]:
 // planes bf16 hi, bf16 lo, fp16; column c < 8 is (c >> 2: h cos | -h sin, c & 3: window column
 // xc), K = sample x of a staged row, holding the taper*twiddle of tap x - xc*s (zero outside
 // the window and for columns 8..15).
-sal_status get_pass_a_ops(int n, int s, int window, const uint16_t** out);
+sal_status get_pass_a_ops(hipStream_t stream, int n, int s, int window, const uint16_t** out);
 
 // Packed row r of an n-point transform: its frequency q and whether it is a sine row.
 // Rows: 0 -> cos 0, 1 -> cos n/2, 2q -> cos q, 2q+1 -> sin q (1 <= q < n/2), r >= n -> zero.

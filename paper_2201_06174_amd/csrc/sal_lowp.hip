@@ -786,7 +786,7 @@ sal_status project_lowp_params(int n, int s, int precision, int CT, const float*
     p.wts = (const float4*)tb->wts_nat_h;
     p.pa_ops = nullptr;
     if (lowp_fixed(n, s, CT)) {
-        sal_status st = get_pass_a_ops(n, s, tb->window, &p.pa_ops);
+        sal_status st = get_pass_a_ops(nullptr, n, s, tb->window, &p.pa_ops);  // the tables are uploaded by now
         if (st) return st;
     }
     p.E = E;

@@ -58,7 +58,8 @@ struct sal_plan_s {
     uint32_t flags = 0;
     int device = 0;
     void* dev = nullptr;
-    size_t dcs_items_off = 0, dcs_first_off = 0, fuse_items_off = 0, comb_first_off = 0, adapt_off = 0, parts_off = 0;
+    size_t dcs_items_off = 0, dcs_first_off = 0, fuse_items_off = 0, comb_first_off = 0, adapt_off = 0, parts_off = 0,
+           status_off = 0;
     int64_t dcs_blocks = 0, comb_rows = 0;
     int nadapt = 0;
     hipStream_t cap = nullptr;
@@ -77,7 +78,7 @@ sal_status build_class_params(sal_plan* plan, Class& c, int CT) {
     int64_t total = 0;
     size_t lds = 0;
     const Tables* tb = nullptr;
-    sal_status st = get_tables(c.spec.n, c.spec.window, &tb);
+    sal_status st = get_tables(nullptr, c.spec.n, c.spec.window, &tb);
     if (st) return st;
     for (size_t k = 0; k < c.members.size(); k++) {
         const sal_batch_item& it = plan->items[c.members[k]];
@@ -146,8 +147,11 @@ sal_status enqueue_all(sal_plan* plan, hipStream_t stream) {
     if ((st = launch_dcs_batch((const DcsItem*)(base + plan->dcs_items_off), (const int64_t*)(base + plan->dcs_first_off),
                                n, plan->dcs_blocks, stream)))
         return st;
-    return launch_fuse_batch((const FuseItem*)(base + plan->fuse_items_off), n, (const int*)(base + plan->adapt_off),
-                             plan->nadapt, (const int64_t*)(base + plan->comb_first_off), plan->comb_rows, stream);
+    if ((st = launch_fuse_batch((const FuseItem*)(base + plan->fuse_items_off), n, (const int*)(base + plan->adapt_off),
+                                plan->nadapt, (const int64_t*)(base + plan->comb_first_off), plan->comb_rows, stream)))
+        return st;
+    return launch_plan_status((const FuseItem*)(base + plan->fuse_items_off), n, (int64_t*)(base + plan->status_off),
+                              stream);
 }
 
 // Time every candidate tile depth of a class on its own members; keep the fastest.
@@ -246,6 +250,9 @@ sal_status sal_plan_create(const sal_batch_item* items, int64_t count, uint32_t 
             return fail(st, "member " + std::to_string(i) + ": " + sal_last_error());
         if ((st = check_fusion_args(&it.fusion, it.D)))
             return fail(st, "member " + std::to_string(i) + ": " + sal_last_error());
+        if (it.fusion.sections != 0)
+            return fail(SAL_ERR_UNSUPPORTED, "member " + std::to_string(i) +
+                                                 ": sectioned re-adaptation is not batched (use sal_fuse)");
     }
     sal_plan* plan = new sal_plan();
     plan->items.assign(items, items + count);
@@ -326,6 +333,7 @@ sal_status sal_plan_create(const sal_batch_item* items, int64_t count, uint32_t 
     plan->comb_first_off = off; off = align256(off + cfirst.size() * sizeof(int64_t));
     plan->adapt_off = off; off = align256(off + std::max<size_t>(1, adapt.size()) * sizeof(int));
     plan->parts_off = off; off = align256(off + adapt.size() * kBatchParts * kStats * sizeof(double));
+    plan->status_off = off; off = align256(off + 2 * sizeof(int64_t));
     if ((st = check_hip(hipMalloc(&plan->dev, off), "hipMalloc(plan)"))) { destroy(plan); return st; }
     char* base = (char*)plan->dev;
     for (size_t k = 0; k < adapt.size(); k++)
@@ -384,6 +392,20 @@ sal_status sal_plan_launch(sal_plan* plan, sal_stream stream) {
     if (!plan) return fail(SAL_ERR_ARG, "plan is NULL");
     if (plan->flags & SAL_PLAN_NO_GRAPH) return enqueue_all(plan, (hipStream_t)stream);
     return check_hip(hipGraphLaunch(plan->exec, (hipStream_t)stream), "hipGraphLaunch");
+}
+
+sal_status sal_plan_status(const sal_plan* plan, sal_stream stream, int64_t* fallback_count, int64_t* first_fallback) {
+    if (!plan) return fail(SAL_ERR_ARG, "plan is NULL");
+    if (!fallback_count || !first_fallback) return fail(SAL_ERR_ARG, "NULL output");
+    int64_t h[2] = {0, -1};
+    sal_status st = check_hip(hipMemcpyAsync(h, (const char*)plan->dev + plan->status_off, sizeof(h),
+                                             hipMemcpyDeviceToHost, (hipStream_t)stream),
+                              "hipMemcpyAsync(plan status)");
+    if (!st) st = check_hip(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
+    if (st) return st;
+    *fallback_count = h[0];
+    *first_fallback = h[1];
+    return SAL_OK;
 }
 
 const char* sal_plan_describe(const sal_plan* plan) { return plan ? plan->desc.c_str() : ""; }

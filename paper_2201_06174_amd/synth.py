@@ -92,7 +92,7 @@ def make_volume(spec: VolumeSpec, seed: int, with_mask: bool = False):
     margin = RICKER_TAPS // 2 + 16
     Tm = T + 2 * margin
     r1 = _layered_reflectivity(rng, Tm)
-    refl = np.broadcast_to(r1[:, None, None], (Tm, IL, XL)).astype(np.float32).copy()
+    refl = np.broadcast_to(r1[:, None, None], (Tm, IL, XL)).astype(np.float32)
     mask = np.zeros((Tm, IL, XL), np.uint8) if with_mask else None
     for _ in range(spec.channels):
         t_ch = int(rng.integers(margin + T // 8, margin + (7 * T) // 8))
@@ -109,17 +109,23 @@ def make_volume(spec: VolumeSpec, seed: int, with_mask: bool = False):
             mask[t_ch:t_ch + 2][:, inside] = 1
     if spec.salt is not None:
         (ct, ci, cx), (at, ai, ax) = spec.salt
-        tt = np.arange(-margin, T + margin, dtype=np.float64)[:, None, None]
-        ii = np.arange(IL, dtype=np.float64)[None, :, None]
-        xx = np.arange(XL, dtype=np.float64)[None, None, :]
-        rho = np.sqrt(((tt - ct) / at) ** 2 + ((ii - ci) / ai) ** 2 + ((xx - cx) / ax) ** 2)
-        shell = np.abs(rho - 1.0) < 1.0 / at
-        interior = (rho < 1.0) & ~shell
-        refl[interior] = rng.normal(0.0, 0.05, size=int(interior.sum())).astype(np.float32)
-        refl[shell] = np.float32(0.5)
-        if with_mask:
-            mask[shell] = 1
-        del rho, shell, interior
+        ii = np.arange(IL, dtype=np.float64)[:, None]
+        xx = np.arange(XL, dtype=np.float64)[None, :]
+        ri, rx = ((ii - ci) / ai) ** 2, ((xx - cx) / ax) ** 2
+        # one t plane at a time (the same arithmetic and the same draw order as the whole
+        # volume at once: the interior's normal draws follow C order, plane after plane)
+        for k in range(Tm):
+            rt = ((k - margin - ct) / at) ** 2
+            if rt > (1.0 + 1.0 / at) ** 2:
+                continue  # the plane misses the body and its shell
+            rho = np.sqrt(rt + ri + rx)
+            shell = np.abs(rho - 1.0) < 1.0 / at
+            interior = (rho < 1.0) & ~shell
+            plane = refl[k]
+            plane[interior] = rng.normal(0.0, 0.05, size=int(interior.sum())).astype(np.float32)
+            plane[shell] = np.float32(0.5)
+            if with_mask:
+                mask[k][shell] = 1
     for f in spec.faults:
         tt, plane_t = _fault_geometry(f, spec.shape, margin)
         hanging = tt < plane_t          # above the plane (shallower)

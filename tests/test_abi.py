@@ -135,3 +135,62 @@ def test_peak_microbenchmark_arguments():
                                    (0, ctypes.c_void_p(264), None, 1024), (1, fake, None, 1024),
                                    (1, fake, ctypes.c_void_p(256 + 512), 1024)]:
         assert _err(lib.sal_peak_stream(kind, src, dst, nbytes, fake, 16, None)) == "SAL_ERR_ARG"
+
+
+def test_per_plane_stencil_validation():
+    lib = _lib.load()
+    E, S = ctypes.c_void_p(16), ctypes.c_void_p(32)
+    ok = ([[1, 0, 0], [-1, 0, 0]], None)
+    # an empty grid launches nothing, so a valid per-plane stencil returns OK without a device
+    st, keep = _lib.make_stencil(None, planes=[ok, ([[0, 0, 2]], [0.5]), ([[2, 2, 0]], None)])
+    assert _err(lib.sal_center_surround(E, 0, 4, 4, 1, st, S, None)) == "SAL_OK"
+    # one plane off the stride-2 grid
+    st, keep = _lib.make_stencil(None, planes=[ok, ([[0, 0, 2]], None), ([[2, 2, 0]], None)])
+    assert _err(lib.sal_center_surround(E, 0, 4, 4, 2, st, S, None)) == "SAL_ERR_ARG"
+    # the union of the three planes holds more than SAL_MAX_STENCIL distinct offsets
+    many = [np.array([[a + 1, b, c] for a in range(4) for b in range(4) for c in range(2)]) + 10 * m
+            for m in range(3)]
+    st, keep = _lib.make_stencil(None, planes=[(o, None) for o in many])
+    assert _err(lib.sal_center_surround(E, 0, 4, 4, 1, st, S, None)) == "SAL_ERR_ARG"
+    # a per-plane stencil may not nest further stencils
+    st, keep = _lib.make_stencil(None, planes=[ok, ok, ok])
+    inner = ctypes.cast(st.per_plane, ctypes.POINTER(_lib.SalStencil))
+    inner[1].per_plane = st.per_plane
+    assert _err(lib.sal_center_surround(E, 0, 4, 4, 1, st, S, None)) == "SAL_ERR_ARG"
+
+
+def test_sections_and_groups():
+    lib = _lib.load()
+    f = _lib.make_fusion("adapt_ls", sections=3)
+    assert lib.sal_fuse_groups(f, 7) == 3 and lib.sal_fuse_groups(f, 6) == 2 and lib.sal_fuse_groups(f, 0) == 0
+    assert lib.sal_fuse_groups(_lib.make_fusion("equal"), 200) == 1 and lib.sal_fuse_groups(None, 5) == 0
+    # the workspace grows with the number of groups
+    one = lib.sal_fuse_workspace_size(4, 9, 4, _lib.make_fusion("adapt_ls"))
+    assert lib.sal_fuse_workspace_size(4, 9, 4, f) == 3 * one
+    sp = _lib.SalSpec(8, 1, 0, 0)
+    assert lib.sal_backward_workspace_size(16, 18, 16, sp, f) > lib.sal_backward_workspace_size(16, 18, 16, sp, None)
+    p = ctypes.c_void_p(64)
+    bad = _lib.make_fusion("equal", sections=-1)
+    assert _err(lib.sal_fuse(p, 4, 4, 4, bad, None, None, 8, 8, 8, 2, p, p, None, 0, None)) == "SAL_ERR_ARG"
+    # workspace sized for one group is too small for three
+    assert _err(lib.sal_fuse(p, 4, 9, 4, f, p, None, 8, 18, 8, 2, p, p, p, one, None)) == "SAL_ERR_NOMEM"
+
+
+def test_line_template_matches_the_oracle():
+    """sal_line_template (host code of the library) and the oracle's own template give the
+    same offsets and weights (the two are written independently)."""
+    from oracle import oracle as orc
+    for d, L, sig in (([2, 0, 0], 3, 1.5), ([0, 0, 1], 1, 0.5), ([1, 0, 1], 4, 2.0), ([0, -3, 3], 2, 1.0)):
+        off, w = _lib.line_template(d, L, sig)
+        ro, rw = orc.line_template(d, L, sig)
+        assert np.array_equal(off, ro)
+        assert np.allclose(w, rw, rtol=1e-7, atol=0)
+    for d, L, sig in (([0, 0, 0], 2, 1.0), ([1, 0, 0], 0, 1.0), ([1, 0, 0], 33, 1.0), ([1, 0, 0], 2, 0.0)):
+        with pytest.raises(_lib.SalError):
+            _lib.line_template(d, L, sig)
+
+
+def test_plan_status_arguments():
+    lib = _lib.load()
+    c, f = ctypes.c_int64(), ctypes.c_int64()
+    assert _err(lib.sal_plan_status(None, None, ctypes.byref(c), ctypes.byref(f))) == "SAL_ERR_ARG"

@@ -72,3 +72,44 @@ def test_stats_summary_lists_every_kernel(tmp_path):
     rows = [l for l in md.splitlines() if l.startswith("| `")]
     assert len(rows) == 40 + 5
     assert rows[0].startswith("| `k0`") and rows[40].startswith("| `k0`")
+
+
+def test_oracle_section_errors_of_the_oracle_itself():
+    """The bench's per-output error plumbing: a 'pipeline' holding the full-grid oracle's
+    own outputs has zero error against the one-section oracle."""
+    import numpy as np
+    import torch
+    from oracle import oracle as orc
+    from paper_2201_06174_amd import synth
+
+    shape, n, s = (20, 24, 18), 8, 2
+    V, M = synth.make_volume(synth.VolumeSpec(shape, faults=[synth.centre_fault(shape)]), 5, with_mask=True)
+    D, mask = synth.desired_map(M, s)
+
+    class W:
+        pass
+    w = W()
+    w.n, w.s, w.offsets = n, s, synth.cube_stencil(2 * s)
+    o = orc.forward(V, orc.Params(n=n, s=s, offsets=w.offsets, fusion="adapt_ls", delta=1e-6, D=D, mask=mask))
+    sec = bench.OracleSection(V, w, D, mask, 1e-6)
+
+    class Pipe:
+        pass
+    p = Pipe()
+    p.torch = torch
+    p.E = torch.from_numpy(o["E"])
+    p.Sm = torch.from_numpy(o["Sm"])
+    p.W = torch.from_numpy(np.append(o["W"], 0.0))
+    p.S = torch.from_numpy(o["S"])
+    e = sec.errors(p)
+    assert e["E"] == 0.0 and e["Sm"] == 0.0 and e["W"] < 1e-15 and e["S"] < 1e-15 and e["fallback"] == 0
+    # a planted error in one output shows up in that output only
+    p.Sm = p.Sm.clone()
+    p.Sm[1, :, sec.mid, 3] *= 1.01
+    e = sec.errors(p)
+    assert e["Sm"] > 1e-3 and e["E"] == 0.0
+
+
+def test_cpu_model_reads_proc():
+    name, count = bench.cpu_model()
+    assert isinstance(name, str) and count >= 0

@@ -123,3 +123,26 @@ def test_full_batch_and_oracle_samples(torch_sal):
         assert np.max(np.abs(S - Sr)) / np.max(np.abs(Sr)) < 1e-5
     _same_as_single(torch, sal, plan, members[:6])
     plan.close()
+
+
+def test_plan_status_word(torch_sal):
+    """sal_plan_status: the number of members whose adapted fit fell back to equal weights
+    and the lowest of them, from the device status word the plan's graph writes."""
+    torch, sal = torch_sal
+    members = []
+    for i, fallback in enumerate((False, True, False, True)):
+        shape = (20 + i, 18, 22)
+        V = synth.make_volume(synth.VolumeSpec(shape, faults=[synth.centre_fault(shape)]), seed=900 + i)
+        gs = sal.grid_shape(shape, 1)
+        D = np.ones(gs, np.float32)
+        # a member whose fit mask is empty has no Gram matrix to solve: equal weights, flagged
+        mask = np.zeros(gs, np.uint8) if fallback else np.ones(gs, np.uint8)
+        cfg = sal.Config(n=8, s=1, offsets=synth.axis_stencil(4), fusion="adapt_ls", delta=0.0)
+        members.append({"V": torch.from_numpy(V).cuda(), "cfg": cfg, "D": torch.from_numpy(D).cuda(),
+                        "mask": torch.from_numpy(mask).cuda()})
+    plan = sal.Plan(members)
+    plan.launch()
+    assert plan.status() == (2, 1)
+    for i in range(4):
+        assert plan.output(i)["W"][3].item() == (1.0 if i in (1, 3) else 0.0)
+    plan.close()

@@ -171,6 +171,7 @@ def test_small_workload_end_to_end(torch_sal):
         assert _rel(r["S"].cpu().numpy(), o["S"]) < TOL_FP32
 
 
+@pytest.mark.timeout(300)
 def test_survey_workload_sampled(torch_sal):
     """256 x 400 x 600, window 16^3 Hann, stride 2, 26 neighbours at offset 8:
     E and S_m at sampled grid points (interior, faces, corners) against the
@@ -193,14 +194,19 @@ def test_survey_workload_sampled(torch_sal):
     Sg = Sm[:, g[:, 0], g[:, 1], g[:, 2]].T
     assert _rel(Eg, Er) < TOL_FP32
     assert _rel(Sg, Sr) < TOL_FP32
-    # W: residual of the normal equations of the masked fit, in FP64 on the host
-    U = Sm.reshape(3, -1).T.astype(np.float64)[mask.reshape(-1) == 1]
-    d = D.reshape(-1)[mask.reshape(-1) == 1].astype(np.float64)
+    # W: the oracle's fit on the GPU's own S_m (stagewise); then the oracle's combine of
+    # the GPU's S_m and W against the GPU's S, every voxel
     assert W[3] == 0
-    Wr = np.linalg.solve(U.T @ U + 1e-6 * np.eye(3), U.T @ d)
-    assert np.max(np.abs(W[:3] - Wr)) < 1e-8 * np.abs(Wr).max()
-    # S from its definition at sampled voxels
-    v = np.stack([rng.integers(0, N, 4096) for N in V.shape], 1)
+    Wr, fb, _ = orc.fusion_weights(Sm, D, mask, "adapt_ls", delta=1e-6)
+    assert fb == 0 and np.max(np.abs(W[:3] - Wr)) < 1e-9 * np.abs(Wr).max()
+    assert _rel(S, orc.combine(Sm, W[:3], V.shape, w.s)) < 1e-6
+    # and the oracle's own S_m, W and S on the middle inline section, where the fit is made
+    mid = gs[1] // 2
+    assert mask.sum() == mask[:, mid, :].sum()
+    E_o, S_o = orc.saliency_inline_plane(V, w.n, w.s, "hann", w.offsets, None, False, mid)
+    W_o, fb_o, _ = orc.fusion_weights(S_o, D[:, mid, :], mask[:, mid, :], "adapt_ls", delta=1e-6)
+    assert _rel(E[:, :, mid, :], E_o) < TOL_FP32 and _rel(Sm[:, :, mid, :], S_o) < TOL_FP32
+    assert _rel(W[:3], W_o) < TOL_FP32
+    v = np.stack([rng.integers(0, V.shape[0], 4096), np.full(4096, mid * w.s), rng.integers(0, V.shape[2], 4096)], 1)
     gv = np.minimum(v // w.s, np.array(gs) - 1)
-    ref = (W[:3, None] * Sm[:, gv[:, 0], gv[:, 1], gv[:, 2]].astype(np.float64)).sum(0)
-    assert _rel(S[v[:, 0], v[:, 1], v[:, 2]], ref) < TOL_FP32
+    assert _rel(S[v[:, 0], v[:, 1], v[:, 2]], (W_o[:, None] * S_o[:, gv[:, 0], gv[:, 2]]).sum(0)) < TOL_FP32

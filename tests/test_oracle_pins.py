@@ -243,6 +243,58 @@ def test_dcs_single_neighbour_and_literal():
     assert abs(S2l[0, 1, 1, 1] - abs(E[0, 1, 1, 1] - 0.5 * E[0, 1, 2, 0])) < 1e-15
 
 
+def test_line_template_ramp_closed_form():
+    """Graded line templates (Sec. 2 step 4, Fig. 4) on E = a * t: a template along t
+    sees |dE| = a |j| d at offset j, so an interior point gives S = a d sum_j w_j |j| / 2L
+    and a point at t = 0 keeps only the j > 0 half (S = a d sum_{j>0} w_j j / L); along the
+    crossline the ramp is flat (S = 0), along the t-x diagonal it is the same as along t.
+    The weights are positive, symmetric in j, largest at |j| = 1 and of mean 1."""
+    L, sigma, d, a = 3, 1.5, 2, 0.75
+    off_t, w = orc.line_template([d, 0, 0], L, sigma)
+    assert off_t.shape == (2 * L, 3) and np.all(off_t[:, 1:] == 0)
+    assert list(off_t[:, 0]) == [-3 * d, -2 * d, -d, d, 2 * d, 3 * d]
+    assert abs(w.mean() - 1.0) < 1e-15 and np.all(w > 0)
+    assert np.allclose(w, w[::-1], rtol=0, atol=1e-15) and w[L] > w[L + 1] > w[L + 2]
+    j = off_t[:, 0] // d
+    shape = (14, 5, 14)
+    E1 = a * np.broadcast_to(np.arange(shape[0], dtype=float)[:, None, None], shape)
+    E = np.stack([E1, E1, E1]).copy()
+    S = orc.dcs(E, 1, off_t, w)
+    assert abs(S[0, 7, 2, 4] - a * d * np.sum(w * np.abs(j)) / (2 * L)) < 1e-14
+    assert abs(S[0, 0, 2, 4] - a * d * np.sum((w * j)[j > 0]) / L) < 1e-14
+    off_x, wx = orc.line_template([0, 0, d], L, sigma)
+    assert np.all(orc.dcs(E, 1, off_x, wx) == 0.0)
+    off_tx, wtx = orc.line_template([d, 0, d], L, sigma)
+    assert np.array_equal(wtx, w)
+    Stx = orc.dcs(E, 1, off_tx, wtx)
+    assert abs(Stx[1, 7, 2, 7] - a * d * np.sum(w * np.abs(j)) / (2 * L)) < 1e-14
+
+
+def test_dcs_planes_closed_form():
+    """A stencil per plane (Sec. 2 step 4): plane t with a line along t, plane x with a line
+    along the crossline, plane y with a line along the inline, on planes that each ramp
+    along their own axis (E_t = a t, E_x = b xl, E_y = c il): every plane sees its own
+    ramp, S_m = slope * d * sum_j w_j |j| / 2L at interior points.  Swapping the stencils
+    of planes t and x makes both flat (S = 0) where their ramps are perpendicular."""
+    L, sigma, d = 2, 1.0, 1
+    st = [orc.line_template(v, L, sigma) for v in ([d, 0, 0], [0, 0, d], [0, d, 0])]
+    w = st[0][1]
+    j = st[0][0][:, 0] // d
+    shape = (9, 10, 11)
+    t, il, xl = np.meshgrid(*[np.arange(N, dtype=float) for N in shape], indexing="ij")
+    a, b, c = 0.5, 1.25, 2.0
+    E = np.stack([a * t, b * xl, c * il])
+    S = orc.dcs_planes(E, 1, st)
+    base = d * np.sum(w * np.abs(j)) / (2 * L)
+    for m, slope in enumerate((a, b, c)):
+        assert abs(S[m, 4, 5, 5] - slope * base) < 1e-14, m
+    S2 = orc.dcs_planes(E, 1, [st[1], st[0], st[2]])
+    assert np.all(S2[0] == 0.0) and np.all(S2[1] == 0.0)
+    # three copies of one stencil: the shared-stencil map
+    one = (synth.cube_stencil(2), None)
+    assert np.array_equal(orc.dcs_planes(E, 1, [one] * 3), orc.dcs(E, 1, one[0]))
+
+
 def test_dcs_rejects_offsets_off_the_grid():
     with pytest.raises(ValueError):
         orc.dcs(np.zeros((3, 4, 4, 4)), 2, np.array([[1, 0, 0]]))
@@ -315,6 +367,61 @@ def test_fusion_fallback_when_not_definite():
     assert fb == 1 and np.allclose(W, 1 / 3)
 
 
+def test_sections_cover_the_volume_once():
+    """Re-adaptation every N sections (Sec. 2, last paragraph): N at or above the number
+    of grid inline planes gives the single fit of the whole volume exactly."""
+    rng = _rng(31)
+    Sm = rng.uniform(size=(3, 4, 7, 5))
+    D = rng.uniform(size=(4, 7, 5)).astype(np.float32)
+    mask = (rng.uniform(size=(4, 7, 5)) < 0.7).astype(np.uint8)
+    W, fb, st = orc.fusion_weights(Sm, D, mask, "adapt_ls", delta=1e-3)
+    for N in (7, 9):
+        Wk, fbk, stk = orc.fusion_weights_sections(Sm, N, D, mask, "adapt_ls", delta=1e-3)
+        assert Wk.shape == (1, 3) and np.array_equal(Wk[0], W) and fbk[0] == fb and np.array_equal(stk[0], st)
+
+
+def test_sections_recover_their_own_weights():
+    """D built as sum_m W_km S_m with weights of its own on each group of N = 3 inline
+    sections: every group's least-squares fit returns its own weights (to the rounding of
+    D in float32); a group with no masked point falls back to equal weights on its own."""
+    rng = _rng(32)
+    Tg, ILg, XLg, N = 5, 8, 6, 3
+    Sm = rng.uniform(0.5, 2.0, size=(3, Tg, ILg, XLg))
+    Wtrue = rng.uniform(-1.0, 1.0, size=(3, 3))
+    grp = np.arange(ILg) // N
+    D = np.einsum("mtix,im->tix", Sm, Wtrue[grp]).astype(np.float32)
+    W, fb, _ = orc.fusion_weights_sections(Sm, N, D, None, "adapt_ls")
+    assert W.shape == (3, 3) and not fb.any()
+    assert np.max(np.abs(W - Wtrue)) < 1e-5
+    mask = np.ones((Tg, ILg, XLg), np.uint8)
+    mask[:, 3:6, :] = 0  # group 1 has no point to fit
+    W2, fb2, _ = orc.fusion_weights_sections(Sm, N, D, mask, "adapt_ls")
+    assert list(fb2) == [0, 1, 0]
+    assert np.max(np.abs(W2[[0, 2]] - Wtrue[[0, 2]])) < 1e-5 and np.allclose(W2[1], 1 / 3)
+    # equal and fixed weights do not depend on the group
+    We, _, _ = orc.fusion_weights_sections(Sm, N, mode="equal")
+    assert np.all(We == 1 / 3)
+
+
+@pytest.mark.parametrize("s,N", [(1, 2), (2, 1), (3, 2)])
+def test_combine_sections_by_search(s, N):
+    """Each voxel takes the weights of its nearest centre's group of N inline sections."""
+    shape = (7, 11, 8)
+    gs = orc.grid_shape(shape, s)
+    rng = _rng(33)
+    Sm = rng.uniform(size=(3,) + gs)
+    K = -(-gs[1] // N)
+    W = rng.uniform(size=(K, 3))
+    S = orc.combine_sections(Sm, W, N, shape, s)
+    for t in range(shape[0]):
+        for i in range(shape[1]):
+            for x in range(shape[2]):
+                g = []
+                for v, Ng in zip((t, i, x), gs):
+                    g.append(int(np.argmin([abs(v - c * s) for c in range(Ng)])))
+                assert abs(S[t, i, x] - W[g[1] // N] @ Sm[(slice(None),) + tuple(g)]) < 1e-15
+
+
 @pytest.mark.parametrize("s", [1, 2, 3])
 def test_combine_nearest_centre(s):
     shape = (7, 5, 8)
@@ -338,37 +445,134 @@ def _loss(V, p, gS):
     return float(np.sum(orc.forward(V, p)["S"] * gS.astype(np.float64)))
 
 
-@pytest.mark.parametrize("fusion", ["equal", "adapt_ls"])
-def test_gradient_finite_differences(fusion):
-    """Central differences with an exactly representable step h = 2^-14 on
-    dyadic inputs; samples whose one-sided slopes disagree (a kink of |.|
-    inside the step) are skipped and counted."""
-    rng = _rng(21)
-    shape = (10, 9, 8)
+def _one_sided_stencil():
+    """Four offsets that are not closed under negation (the adjoint's general gather path)."""
+    return np.array([[2, 0, 0], [0, 2, 0], [0, 0, -2], [2, 2, 0]], np.int32)
+
+
+# shape, n, s, window, offsets, explicit weights (None = Gaussian default), literal, fusion, masked fit
+FD_CASES = [
+    ((10, 9, 8), 4, 1, "hann", synth.axis_stencil(2), None, False, "equal", False),
+    ((10, 9, 8), 4, 1, "hann", synth.axis_stencil(2), None, False, "adapt_ls", False),
+    # Gaussian weights (cube stencil: three distinct weights), stride 2
+    ((13, 12, 11), 6, 2, "hann", synth.cube_stencil(2), None, False, "equal", False),
+    # literal Eq. 3 form (weight inside the modulus) with the adapted weights and a fit mask
+    ((13, 12, 11), 6, 2, "hann", synth.cube_stencil(2), None, True, "adapt_ls", True),
+    # stride 3, fixed weights, flat window
+    ((14, 13, 15), 8, 3, "rect", synth.axis_stencil(3), None, False, "fixed", False),
+    # a one-sided stencil with explicit non-unit weights
+    ((11, 10, 9), 4, 1, "hann", _one_sided_stencil(), np.array([0.5, 1.25, 2.0, 0.75]), False, "equal", False),
+    ((13, 12, 11), 6, 2, "hann", _one_sided_stencil(), np.array([0.5, 1.25, 2.0, 0.75]), True, "fixed", False),
+]
+
+# per-plane stencils (graded line templates along t, x and t-x) and re-adaptation every N
+# inline sections: shape, n, s, planes, literal, fusion, masked, sections
+FD_CASES_EXT = [
+    ((12, 11, 10), 4, 1, [([1, 0, 0], 2, 1.0), ([0, 0, 1], 2, 1.0), ([1, 0, 1], 1, 1.0)], False, "adapt_ls", True, 0),
+    ((12, 11, 10), 4, 1, [([1, 0, 0], 2, 1.0), ([0, 1, 0], 1, 1.0), ([0, 0, 1], 2, 0.7)], True, "equal", False, 0),
+    ((12, 13, 10), 4, 1, None, False, "adapt_ls", True, 4),
+    ((13, 14, 11), 6, 2, [([2, 0, 0], 2, 1.0), ([0, 0, 2], 1, 1.0), ([2, 2, 0], 1, 1.0)], False, "adapt_ls", False, 2),
+]
+
+
+@pytest.mark.parametrize("case", range(len(FD_CASES)))
+def test_gradient_finite_differences(case):
+    """Central differences of the oracle's forward against orc_backward (Eq. 1-4 and
+    their exact adjoint).  The steps h = 2^-14 and 2^-15 are exactly representable and
+    the inputs dyadic, so V +- h is exact in float32; the two central differences are
+    Richardson-extrapolated (error O(h^4)); samples whose one-sided slopes disagree
+    (a kink of |.| inside the step) are skipped and counted.  The cases cover every
+    branch of the adjoint the GPU gradient tests lean on: Gaussian weights (s > 1),
+    the literal Eq. 3 form, fixed and least-squares weights (with and without a fit
+    mask), a flat window and a stencil that is not symmetric."""
+    shape, n, s, window, off, weights, literal, fusion, masked = FD_CASES[case]
+    rng = _rng(21 + case)
     V = (np.round(rng.standard_normal(shape) * 256) / 1024).astype(np.float32)
     gS = (np.round(rng.uniform(size=shape) * 256) / 256).astype(np.float32)
-    p = orc.Params(n=4, s=1, offsets=synth.axis_stencil(2), fusion=fusion)
+    p = orc.Params(n=n, s=s, window=window, offsets=off, weights=weights, literal=literal, fusion=fusion)
+    gs = orc.grid_shape(shape, s)
     if fusion == "adapt_ls":
-        D = (rng.uniform(size=shape) < 0.3).astype(np.float32)
-        p.D, p.delta = D, 1e-4
+        p.D = (rng.uniform(size=gs) < 0.3).astype(np.float32)
+        p.delta = 1e-4
+        if masked:
+            p.mask = (rng.uniform(size=gs) < 0.6).astype(np.uint8)
+    if fusion == "fixed":
+        p.wfix = np.array([0.2, 0.5, 0.3])
     gV, W, fb = orc.backward(V, p, gS)
     assert fb == 0
     h = 2.0 ** -14
     L0 = _loss(V, p, gS)
     checked = skipped = 0
-    for idx in rng.integers(0, [10, 9, 8], size=(24, 3)):
+    for idx in rng.integers(0, shape, size=(24, 3)):
         idx = tuple(int(v) for v in idx)
-        Vp = V.copy(); Vp[idx] += np.float32(h)
-        Vm = V.copy(); Vm[idx] -= np.float32(h)
-        Lp, Lm = _loss(Vp, p, gS), _loss(Vm, p, gS)
-        fwd, bwd = (Lp - L0) / h, (L0 - Lm) / h
+
+        def central(step):
+            Vp = V.copy(); Vp[idx] += np.float32(step)
+            Vm = V.copy(); Vm[idx] -= np.float32(step)
+            Lp, Lm = _loss(Vp, p, gS), _loss(Vm, p, gS)
+            return (Lp - Lm) / (2 * step), (Lp - L0) / step, (L0 - Lm) / step
+
+        d1, fwd, bwd = central(h)
         if abs(fwd - bwd) > 1e-3 * (abs(fwd) + abs(bwd) + 1e-3):
             skipped += 1
             continue
-        fd = (Lp - Lm) / (2 * h)
-        assert abs(fd - gV[idx]) < 1e-6 * (abs(fd) + 1e-2), (idx, fd, gV[idx])
+        d2, _, _ = central(h / 2)
+        # Richardson extrapolation: the h^2 term of the central difference cancels; what
+        # remains of the two estimates' spread bounds the rounding noise of the losses
+        fd = (4.0 * d2 - d1) / 3.0
+        spread = abs(d1 - d2)
+        assert spread < 1e-5 * (abs(fd) + 1e-2), (idx, d1, d2)
+        assert abs(fd - gV[idx]) < 1e-7 * (abs(fd) + 1e-2) + 2.0 * spread, (idx, fd, gV[idx], d1, d2)
         checked += 1
     assert checked >= 16, (checked, skipped)
+
+
+def _fd_check(V, p, gS, gV, rng, shape):
+    h = 2.0 ** -14
+    L0 = _loss(V, p, gS)
+    checked = skipped = 0
+    for idx in rng.integers(0, shape, size=(24, 3)):
+        idx = tuple(int(v) for v in idx)
+
+        def central(step):
+            Vp = V.copy(); Vp[idx] += np.float32(step)
+            Vm = V.copy(); Vm[idx] -= np.float32(step)
+            Lp, Lm = _loss(Vp, p, gS), _loss(Vm, p, gS)
+            return (Lp - Lm) / (2 * step), (Lp - L0) / step, (L0 - Lm) / step
+
+        d1, fwd, bwd = central(h)
+        if abs(fwd - bwd) > 1e-3 * (abs(fwd) + abs(bwd) + 1e-3):
+            skipped += 1
+            continue
+        d2, _, _ = central(h / 2)
+        fd = (4.0 * d2 - d1) / 3.0
+        spread = abs(d1 - d2)
+        assert spread < 1e-5 * (abs(fd) + 1e-2), (idx, d1, d2)
+        assert abs(fd - gV[idx]) < 1e-7 * (abs(fd) + 1e-2) + 2.0 * spread, (idx, fd, gV[idx], d1, d2)
+        checked += 1
+    assert checked >= 16, (checked, skipped)
+
+
+@pytest.mark.parametrize("case", range(len(FD_CASES_EXT)))
+def test_gradient_finite_differences_planes_sections(case):
+    """As test_gradient_finite_differences, for per-plane line templates (Sec. 2 step 4,
+    Fig. 4) and the weights re-adapted every N inline sections (Sec. 2, last paragraph)."""
+    shape, n, s, planes, literal, fusion, masked, sections = FD_CASES_EXT[case]
+    rng = _rng(41 + case)
+    V = (np.round(rng.standard_normal(shape) * 256) / 1024).astype(np.float32)
+    gS = (np.round(rng.uniform(size=shape) * 256) / 256).astype(np.float32)
+    p = orc.Params(n=n, s=s, literal=literal, fusion=fusion, sections=sections, offsets=synth.axis_stencil(s))
+    if planes is not None:
+        p.planes = [orc.line_template(d, L, sig) for d, L, sig in planes]
+    gs = orc.grid_shape(shape, s)
+    if fusion == "adapt_ls":
+        p.D = (rng.uniform(size=gs) < 0.3).astype(np.float32)
+        p.delta = 1e-4
+        if masked:
+            p.mask = (rng.uniform(size=gs) < 0.6).astype(np.uint8)
+    gV, W, fb = orc.backward(V, p, gS)
+    assert not np.any(fb)
+    _fd_check(V, p, gS, gV, rng, shape)
 
 
 def test_backward_at_matches_full_backward():
@@ -394,6 +598,18 @@ def test_saliency_at_matches_full_grid():
     Sa, Ea = orc.saliency_at(V, 6, 2, "hann", off, None, False, g)
     assert np.allclose(Sa, S[:, g[:, 0], g[:, 1], g[:, 2]].T, atol=1e-14)
     assert np.allclose(Ea, E[:, g[:, 0], g[:, 1], g[:, 2]].T, atol=1e-14)
+
+
+def test_saliency_inline_plane_matches_full_grid():
+    """The one-plane oracle used at survey sizes equals the full-grid oracle exactly, at the
+    border planes and inside, for a stencil reaching two planes along the inline."""
+    V = _rng(24).standard_normal((20, 22, 18)).astype(np.float32)
+    off = synth.cube_stencil(4)
+    E = orc.features(V, 8, 2, "hann")
+    S = orc.dcs(E, 2, off)
+    for il in (0, 1, 5, 10):
+        Ep, Sp = orc.saliency_inline_plane(V, 8, 2, "hann", off, None, False, il)
+        assert np.array_equal(Ep, E[:, :, il, :]) and np.array_equal(Sp, S[:, :, il, :])
 
 
 def test_structures_are_salient():
