@@ -8,7 +8,8 @@ argument marshalling only, all arithmetic lives in the C file.  It follows
 Shafiq, Long, Di, AlRegib (ACI 2021), Section 2:
 
 * local 3D DFT of each window (Sec. 2 step 1, Eq. 2) -- ``local_spectra``;
-* spectral projection and features E_m (Eq. 1, third step) -- ``features``;
+* spectral projection and features E_m (Eq. 1, third step), as the mean of
+  |F_m| or of the energy |F_m|^2 -- ``features``;
 * directional center-surround S_m (Eq. 3) -- ``dcs``, ``saliency_at``;
 * fusion weights and the combined map S (Eq. 4) -- ``fusion_weights``,
   ``combine``, and with re-adaptation every N inline sections
@@ -33,6 +34,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 WINDOWS = {"hann": 0, "rect": 1}
+FEATURES = {"magnitude": 0, "energy": 1}
 FUSION_MODES = {"equal": 0, "fixed": 1, "adapt_ls": 2}
 
 
@@ -105,25 +107,28 @@ def grid_shape(shape, s):
     return tuple(-(-int(N) // int(s)) for N in shape)
 
 
-def features(V, n: int, s: int, kind="hann", nthreads=None) -> np.ndarray:
-    """E[3][Tg][ILg][XLg] in FP64 (planes t, x=XL, y=IL)."""
+def features(V, n: int, s: int, kind="hann", nthreads=None, feature="magnitude") -> np.ndarray:
+    """E[3][Tg][ILg][XLg] in FP64 (planes t, x=XL, y=IL); feature "magnitude" (mean |F_m|) or
+    "energy" (mean |F_m|^2)."""
     V = _vol(V)
     gs = grid_shape(V.shape, s)
     E = np.zeros((3,) + gs, np.float64)
-    rc = _load().orc_features(_p(V), _i64(V.shape[0]), _i64(V.shape[1]), _i64(V.shape[2]), ctypes.c_int(n),
-                              ctypes.c_int(s), ctypes.c_int(WINDOWS.get(kind, kind)), _p(E), _nthreads(nthreads))
+    rc = _load().orc_features_ex(_p(V), _i64(V.shape[0]), _i64(V.shape[1]), _i64(V.shape[2]), ctypes.c_int(n),
+                                 ctypes.c_int(s), ctypes.c_int(WINDOWS.get(kind, kind)),
+                                 ctypes.c_int(FEATURES[feature]), _p(E), _nthreads(nthreads))
     _check(rc, "features")
     return E
 
 
-def features_at(V, n: int, s: int, kind, g, nthreads=None) -> np.ndarray:
+def features_at(V, n: int, s: int, kind, g, nthreads=None, feature="magnitude") -> np.ndarray:
     """E at grid points g[cnt][3]; returns [cnt][3]."""
     V = _vol(V)
     g = np.ascontiguousarray(g, dtype=np.int64).reshape(-1, 3)
     E = np.zeros((g.shape[0], 3), np.float64)
-    rc = _load().orc_features_at(_p(V), _i64(V.shape[0]), _i64(V.shape[1]), _i64(V.shape[2]), ctypes.c_int(n),
-                                 ctypes.c_int(s), ctypes.c_int(WINDOWS.get(kind, kind)), _p(g), _i64(g.shape[0]),
-                                 _p(E), _nthreads(nthreads))
+    rc = _load().orc_features_at_ex(_p(V), _i64(V.shape[0]), _i64(V.shape[1]), _i64(V.shape[2]), ctypes.c_int(n),
+                                    ctypes.c_int(s), ctypes.c_int(WINDOWS.get(kind, kind)),
+                                    ctypes.c_int(FEATURES[feature]), _p(g), _i64(g.shape[0]), _p(E),
+                                    _nthreads(nthreads))
     _check(rc, "features_at")
     return E
 
@@ -300,6 +305,8 @@ class Params:
     planes: Optional[list] = None
     # re-adaptation every `sections` grid inline sections (0: one fit)
     sections: int = 0
+    # "magnitude" (mean |F_m|, Sec. 2 third step) or "energy" (mean |F_m|^2)
+    feature: str = "magnitude"
 
 
 def _plane_stencils(p: Params):
@@ -314,7 +321,7 @@ def forward(V, p: Params, nthreads=None) -> dict:
     """E, S_m, W, fallback flag and S for the whole volume (W [3] and an int flag without
     sections, W [K][3] and flags [K] with them)."""
     V = _vol(V)
-    E = features(V, p.n, p.s, p.window, nthreads)
+    E = features(V, p.n, p.s, p.window, nthreads, p.feature)
     if p.planes is not None:
         Sm = dcs_planes(E, p.s, p.planes, p.literal)
     else:
@@ -344,7 +351,8 @@ def backward(V, p: Params, gS, nthreads=None):
     W = np.zeros((K, 3), np.float64)
     fb = np.zeros(K, np.int32)
     rc = _load().orc_backward_ex(_p(V), _i64(V.shape[0]), _i64(V.shape[1]), _i64(V.shape[2]), ctypes.c_int(p.n),
-                                 ctypes.c_int(p.s), ctypes.c_int(WINDOWS.get(p.window, p.window)), _p(q3), _p(off),
+                                 ctypes.c_int(p.s), ctypes.c_int(WINDOWS.get(p.window, p.window)),
+                                 ctypes.c_int(FEATURES[p.feature]), _p(q3), _p(off),
                                  _p(w), ctypes.c_int(int(bool(p.literal))),
                                  ctypes.c_int(FUSION_MODES.get(p.fusion, p.fusion)), _p(wf), ctypes.c_double(p.delta),
                                  _p(Dp), _p(Mp), _i64(p.sections), _p(gS), _p(gV), _p(W), _p(fb),

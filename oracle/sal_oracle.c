@@ -238,16 +238,26 @@ static void window_spectrum(const float* V, int64_t T, int64_t IL, int64_t XL, c
     memcpy(w->xi, w->yi, sizeof(double) * n3);
 }
 
-/* Features of one window (Sec. 2 steps 2-3, Eq. 1): E_m = n^-3 sum_k alpha_m(k) |F(k)|. */
-static void window_features(const orc_tables* tb, const orc_work* w, double* E3) {
+/* Features of one window (Sec. 2 steps 2-3, Eq. 1), the mean over the n^3 cube of the
+ * projected spectrum F_m = alpha_m F:
+ *   feature 0 (magnitude): E_m = n^-3 sum_k |F_m(k)| = n^-3 sum_k alpha_m(k) |F(k)|;
+ *   feature 1 (energy):    E_m = n^-3 sum_k |F_m(k)|^2 = n^-3 sum_k alpha_m(k)^2 |F(k)|^2. */
+static void window_features(const orc_tables* tb, const orc_work* w, int feature, double* E3) {
     int n = tb->n;
     int64_t n3 = (int64_t)n * n * n;
     double et = 0.0, ex = 0.0, ey = 0.0;
     for (int64_t k = 0; k < n3; k++) {
-        double mag = sqrt(w->xr[k] * w->xr[k] + w->xi[k] * w->xi[k]);
-        et += tb->at[k] * mag;
-        ex += tb->ax[k] * mag;
-        ey += tb->ay[k] * mag;
+        double p = w->xr[k] * w->xr[k] + w->xi[k] * w->xi[k];
+        if (feature == 1) {
+            et += tb->at[k] * tb->at[k] * p;
+            ex += tb->ax[k] * tb->ax[k] * p;
+            ey += tb->ay[k] * tb->ay[k] * p;
+        } else {
+            double mag = sqrt(p);
+            et += tb->at[k] * mag;
+            ex += tb->ax[k] * mag;
+            ey += tb->ay[k] * mag;
+        }
     }
     E3[0] = et / (double)n3;
     E3[1] = ex / (double)n3;
@@ -279,10 +289,11 @@ int orc_local_spectra(const float* V, int64_t T, int64_t IL, int64_t XL, int n, 
 }
 
 /* E at a list of grid points g[cnt][3]; output E[cnt][3]. */
-int orc_features_at(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s, int window,
-                    const int64_t* g, int64_t cnt, double* E, int nthreads) {
+int orc_features_at_ex(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s, int window, int feature,
+                       const int64_t* g, int64_t cnt, double* E, int nthreads) {
     int rc = check_spec(T, IL, XL, n, s, window);
     if (rc) return rc;
+    if (feature != 0 && feature != 1) return ORC_EARG;
     int64_t Tg = ceil_div(T, s), ILg = ceil_div(IL, s), XLg = ceil_div(XL, s);
     for (int64_t j = 0; j < cnt; j++)
         if (g[3 * j] < 0 || g[3 * j] >= Tg || g[3 * j + 1] < 0 || g[3 * j + 1] >= ILg || g[3 * j + 2] < 0 ||
@@ -304,7 +315,7 @@ int orc_features_at(const float* V, int64_t T, int64_t IL, int64_t XL, int n, in
         for (int64_t j = 0; j < cnt; j++) {
             if (!ok) continue;
             window_spectrum(V, T, IL, XL, &tb, g[3 * j] * s, g[3 * j + 1] * s, g[3 * j + 2] * s, &w);
-            window_features(&tb, &w, E + 3 * j);
+            window_features(&tb, &w, feature, E + 3 * j);
         }
         work_free(&w);
     }
@@ -312,11 +323,17 @@ int orc_features_at(const float* V, int64_t T, int64_t IL, int64_t XL, int n, in
     return fail ? ORC_ENOMEM : ORC_OK;
 }
 
+int orc_features_at(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s, int window,
+                    const int64_t* g, int64_t cnt, double* E, int nthreads) {
+    return orc_features_at_ex(V, T, IL, XL, n, s, window, 0, g, cnt, E, nthreads);
+}
+
 /* E on the whole grid, planar layout E[3][Tg][ILg][XLg]. */
-int orc_features(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s, int window, double* E,
-                 int nthreads) {
+int orc_features_ex(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s, int window, int feature,
+                    double* E, int nthreads) {
     int rc = check_spec(T, IL, XL, n, s, window);
     if (rc) return rc;
+    if (feature != 0 && feature != 1) return ORC_EARG;
     int64_t Tg = ceil_div(T, s), ILg = ceil_div(IL, s), XLg = ceil_div(XL, s);
     int64_t G = Tg * ILg * XLg;
     orc_tables tb;
@@ -337,7 +354,7 @@ int orc_features(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s
             int64_t gt = j / (ILg * XLg), gi = (j / XLg) % ILg, gx = j % XLg;
             double e3[3];
             window_spectrum(V, T, IL, XL, &tb, gt * s, gi * s, gx * s, &w);
-            window_features(&tb, &w, e3);
+            window_features(&tb, &w, feature, e3);
             E[j] = e3[0];
             E[G + j] = e3[1];
             E[2 * G + j] = e3[2];
@@ -346,6 +363,11 @@ int orc_features(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s
     }
     tables_free(&tb);
     return fail ? ORC_ENOMEM : ORC_OK;
+}
+
+int orc_features(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s, int window, double* E,
+                 int nthreads) {
+    return orc_features_ex(V, T, IL, XL, n, s, window, 0, E, nthreads);
 }
 
 /* Default DCS weights: Gaussian exp(-|o|^2 / (2 d^2)) with d the stencil's
@@ -479,12 +501,12 @@ int orc_saliency_at(const float* V, int64_t T, int64_t IL, int64_t XL, int n, in
             double e0[3], e1[3], acc[3] = {0, 0, 0};
             int Q = 0;
             window_spectrum(V, T, IL, XL, &tb, gt * s, gi * s, gx * s, &w_);
-            window_features(&tb, &w_, e0);
+            window_features(&tb, &w_, 0, e0);
             for (int k = 0; k < q; k++) {
                 int64_t nt = gt + off[3 * k] / s, ni = gi + off[3 * k + 1] / s, nx = gx + off[3 * k + 2] / s;
                 if (nt < 0 || nt >= Tg || ni < 0 || ni >= ILg || nx < 0 || nx >= XLg) continue;
                 window_spectrum(V, T, IL, XL, &tb, nt * s, ni * s, nx * s, &w_);
-                window_features(&tb, &w_, e1);
+                window_features(&tb, &w_, 0, e1);
                 for (int m = 0; m < 3; m++) acc[m] += literal ? fabs(e0[m] - w[k] * e1[m]) : w[k] * fabs(e0[m] - e1[m]);
                 Q++;
             }
@@ -642,12 +664,21 @@ static double sgn(double v) { return v > 0.0 ? 1.0 : (v < 0.0 ? -1.0 : 0.0); }
 
 /* Spectral adjoint of one window: given gE (3 values) and the window's
  * spectrum F in (w->xr, w->xi), form Y(k) = c(k) F(k)/|F(k)| with
- * c(k) = sum_m gE_m alpha_m(k) / n^3 (zero at DC and where |F| = 0), and the
- * tapered real field H(a) Re sum_k Y(k) e^{+2 pi i k.a/n} into w->yr. */
-static void window_adjoint(const orc_tables* tb, const double gE[3], orc_work* w) {
+ * c(k) = sum_m gE_m alpha_m(k) / n^3 (zero at DC and where |F| = 0) for the
+ * magnitude feature, or Y(k) = 2 c(k) F(k) with c(k) = sum_m gE_m
+ * alpha_m(k)^2 / n^3 for the energy feature, and the tapered real field
+ * H(a) Re sum_k Y(k) e^{+2 pi i k.a/n} into w->yr. */
+static void window_adjoint(const orc_tables* tb, const double gE[3], int feature, orc_work* w) {
     int n = tb->n;
     int64_t n3 = (int64_t)n * n * n;
     for (int64_t k = 0; k < n3; k++) {
+        if (feature == 1) {
+            double c = (gE[0] * tb->at[k] * tb->at[k] + gE[1] * tb->ax[k] * tb->ax[k] +
+                        gE[2] * tb->ay[k] * tb->ay[k]) / (double)n3;
+            w->xr[k] = 2.0 * c * w->xr[k];
+            w->xi[k] = 2.0 * c * w->xi[k];
+            continue;
+        }
         double mag = sqrt(w->xr[k] * w->xr[k] + w->xi[k] * w->xi[k]);
         double c = (gE[0] * tb->at[k] + gE[1] * tb->ax[k] + gE[2] * tb->ay[k]) / (double)n3;
         if (mag > 0.0) {
@@ -716,13 +747,14 @@ static void dcs_adjoint(const double* E, const double* gSm, int64_t Tg, int64_t 
  * weights re-adapted every N inline sections (as in
  * orc_fusion_weights_sections; N = 0: one fit).  Also returns the forward's
  * W [K][3] and fallback flags [K]. */
-int orc_backward_ex(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s, int window, const int* q3,
+int orc_backward_ex(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s, int window, int feature,
+                    const int* q3,
                     const int32_t* off_all, const double* w_all, int literal, int mode, const double* wfix,
                     double delta, const float* D, const uint8_t* mask, int64_t N, const float* gS, double* gV,
                     double* W_out, int* fallback_out, int nthreads) {
     int rc = check_spec(T, IL, XL, n, s, window);
     if (rc) return rc;
-    if (N < 0) return ORC_EARG;
+    if (N < 0 || (feature != 0 && feature != 1)) return ORC_EARG;
     {
         int base = 0;
         for (int m = 0; m < 3; m++) {
@@ -742,7 +774,7 @@ int orc_backward_ex(const float* V, int64_t T, int64_t IL, int64_t XL, int n, in
     double* gW = (double*)calloc((size_t)(3 * K), sizeof(double));
     int* fb = (int*)malloc(sizeof(int) * K);
     if (!E || !Sm || !gSm || !gE || !cell || !W || !st || !gW || !fb) { rc = ORC_ENOMEM; goto done; }
-    rc = orc_features(V, T, IL, XL, n, s, window, E, nthreads);
+    rc = orc_features_ex(V, T, IL, XL, n, s, window, feature, E, nthreads);
     if (rc) goto done;
     orc_dcs_planes(E, Tg, ILg, XLg, s, q3, off_all, w_all, literal, Sm);
     rc = orc_fusion_weights_sections(Sm, Tg, ILg, XLg, D, mask, mode, wfix, delta, N, W, fb, st);
@@ -814,7 +846,7 @@ int orc_backward_ex(const float* V, int64_t T, int64_t IL, int64_t XL, int n, in
                 double ge[3] = {gE[j], gE[G + j], gE[2 * G + j]};
                 if (ge[0] == 0.0 && ge[1] == 0.0 && ge[2] == 0.0) continue;
                 window_spectrum(V, T, IL, XL, &tb, gt * s, gi * s, gx * s, &wk);
-                window_adjoint(&tb, ge, &wk);
+                window_adjoint(&tb, ge, feature, &wk);
                 int half = n / 2;
                 for (int at = 0; at < n; at++) {
                     int64_t pt = reflect_index(gt * s - half + at, T);
@@ -857,7 +889,7 @@ int orc_backward(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s
         memcpy(off3 + 3 * q * m, off, sizeof(int32_t) * 3 * q);
         memcpy(w3 + q * m, w, sizeof(double) * q);
     }
-    int rc = orc_backward_ex(V, T, IL, XL, n, s, window, q3, off3, w3, literal, mode, wfix, delta, D, mask, 0, gS,
+    int rc = orc_backward_ex(V, T, IL, XL, n, s, window, 0, q3, off3, w3, literal, mode, wfix, delta, D, mask, 0, gS,
                              gV, W_out, fallback_out, nthreads);
     free(off3);
     free(w3);
@@ -944,7 +976,7 @@ int orc_backward_at(const float* V, int64_t T, int64_t IL, int64_t XL, int n, in
             for (int64_t b = 0; b < nb; b++) {
                 int64_t bt = b / (bx[1] * bx[2]), bi = (b / bx[2]) % bx[1], bxx = b % bx[2];
                 window_spectrum(V, T, IL, XL, &tb, (lo[0] + bt) * s, (lo[1] + bi) * s, (lo[2] + bxx) * s, &wk);
-                window_features(&tb, &wk, Eb + 3 * b);
+                window_features(&tb, &wk, 0, Eb + 3 * b);
             }
 #define EB(gt_, gi_, gx_, m_) Eb[3 * ((((gt_) - lo[0]) * bx[1] + ((gi_) - lo[1])) * bx[2] + ((gx_) - lo[2])) + (m_)]
             double total = 0.0;
@@ -1020,7 +1052,7 @@ int orc_backward_at(const float* V, int64_t T, int64_t IL, int64_t XL, int n, in
 #undef CELLSUM
                         if (ge[0] == 0.0 && ge[1] == 0.0 && ge[2] == 0.0) continue;
                         window_spectrum(V, T, IL, XL, &tb, gt * s, gi * s, gx * s, &wk);
-                        window_adjoint(&tb, ge, &wk);
+                        window_adjoint(&tb, ge, 0, &wk);
                         for (int jt = 0; jt < cntl[0]; jt++) {
                             if (gl[0][jt] != gt) continue;
                             for (int ji = 0; ji < cntl[1]; ji++) {

@@ -42,17 +42,19 @@ def near_tie_voxels(E, shape, n, s, stencils, literal, tau):
 
 
 def check_gradient(gV, ref, amb, tol, max_exempt=0.01):
-    """Every voxel off by more than tol must be explained by a near tie, and the near-tie
-    voxels must be few (at most max_exempt of the volume)."""
+    """Every voxel off by more than tol must be explained by a near tie, and the voxels so
+    exempted must be few (at most max_exempt of the volume).  `amb`, the footprint of every
+    near-tie term, is wide (a window's n^3 voxels per term); the exempted voxels are those
+    of it that actually miss the tolerance."""
     rel = np.abs(gV - ref) / np.max(np.abs(ref))
     bad = rel > tol
     unexplained = bad & ~amb
-    frac = float(amb.mean())
-    print("  max rel err %.3e over all voxels, %.3e off near-tie voxels; %d voxels above %.0e, %d near-tie "
-          "voxels (%.3f %% of the volume)" % (rel.max(), rel[~amb].max() if (~amb).any() else 0.0, int(bad.sum()),
-                                               tol, int(amb.sum()), 100 * frac), flush=True)
+    print("  max rel err %.3e over all voxels, %.3e off near-tie footprints; %d voxels above %.0e (%.3f %% of the "
+          "volume), near-tie footprints cover %.1f %%" % (rel.max(), rel[~amb].max() if (~amb).any() else 0.0,
+                                                          int(bad.sum()), tol, 100 * float(bad.mean()),
+                                                          100 * float(amb.mean())), flush=True)
     assert not unexplained.any(), np.argwhere(unexplained)[:8]
-    assert frac <= max_exempt, frac
+    assert float(bad.mean()) <= max_exempt, float(bad.mean())
 
 
 def voxel_explained_by_tie(V, n, s, window, offsets, weights, literal, voxel, tau):

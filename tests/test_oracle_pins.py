@@ -472,6 +472,10 @@ FD_CASES_EXT = [
     ((12, 11, 10), 4, 1, [([1, 0, 0], 2, 1.0), ([0, 1, 0], 1, 1.0), ([0, 0, 1], 2, 0.7)], True, "equal", False, 0),
     ((12, 13, 10), 4, 1, None, False, "adapt_ls", True, 4),
     ((13, 14, 11), 6, 2, [([2, 0, 0], 2, 1.0), ([0, 0, 2], 1, 1.0), ([2, 2, 0], 1, 1.0)], False, "adapt_ls", False, 2),
+    # the energy feature (mean of |F_m|^2)
+    ((12, 11, 10), 4, 1, None, False, "adapt_ls", True, 0, "energy"),
+    ((13, 12, 11), 6, 2, [([2, 0, 0], 1, 1.0), ([0, 0, 2], 1, 1.0), ([2, 0, 2], 1, 1.0)], True, "equal", False, 3,
+     "energy"),
 ]
 
 
@@ -556,12 +560,15 @@ def _fd_check(V, p, gS, gV, rng, shape):
 @pytest.mark.parametrize("case", range(len(FD_CASES_EXT)))
 def test_gradient_finite_differences_planes_sections(case):
     """As test_gradient_finite_differences, for per-plane line templates (Sec. 2 step 4,
-    Fig. 4) and the weights re-adapted every N inline sections (Sec. 2, last paragraph)."""
-    shape, n, s, planes, literal, fusion, masked, sections = FD_CASES_EXT[case]
+    Fig. 4), the weights re-adapted every N inline sections (Sec. 2, last paragraph) and
+    the energy feature (mean of |F_m|^2)."""
+    shape, n, s, planes, literal, fusion, masked, sections = FD_CASES_EXT[case][:8]
+    feature = FD_CASES_EXT[case][8] if len(FD_CASES_EXT[case]) > 8 else "magnitude"
     rng = _rng(41 + case)
     V = (np.round(rng.standard_normal(shape) * 256) / 1024).astype(np.float32)
     gS = (np.round(rng.uniform(size=shape) * 256) / 256).astype(np.float32)
-    p = orc.Params(n=n, s=s, literal=literal, fusion=fusion, sections=sections, offsets=synth.axis_stencil(s))
+    p = orc.Params(n=n, s=s, literal=literal, fusion=fusion, sections=sections, offsets=synth.axis_stencil(s),
+                   feature=feature)
     if planes is not None:
         p.planes = [orc.line_template(d, L, sig) for d, L, sig in planes]
     gs = orc.grid_shape(shape, s)
@@ -598,6 +605,35 @@ def test_saliency_at_matches_full_grid():
     Sa, Ea = orc.saliency_at(V, 6, 2, "hann", off, None, False, g)
     assert np.allclose(Sa, S[:, g[:, 0], g[:, 1], g[:, 2]].T, atol=1e-14)
     assert np.allclose(Ea, E[:, g[:, 0], g[:, 1], g[:, 2]].T, atol=1e-14)
+
+
+def test_energy_feature_parseval():
+    """Energy feature E_m = n^-3 sum_k |F_m(k)|^2 with F_m = alpha_m F: since
+    alpha_t^2 + alpha_x^2 + alpha_y^2 = 2 away from DC, Parseval's identity gives
+    sum_m E_m = 2 (sum_a (h V)^2 - (sum_a h V)^2 / n^3) for every window, a sum over the
+    tapered cube alone (no transform), at interior and border windows."""
+    rng = _rng(51)
+    V = rng.standard_normal((13, 12, 11)).astype(np.float32)
+    for n, s, kind in ((8, 1, "hann"), (6, 2, "rect"), (4, 1, "hann")):
+        E = orc.features(V, n, s, kind, feature="energy")
+        for g in ((0, 0, 0), (3, 5, 4), (6 // s, 11 // s, 10 // s)):
+            cube = _cube(V, n, np.array(g) * s, kind)
+            ref = 2.0 * (np.sum(cube ** 2) - np.sum(cube) ** 2 / n ** 3)
+            assert abs(E[:, g[0], g[1], g[2]].sum() - ref) < 1e-10 * ref, (n, g)
+
+
+def test_energy_feature_plane_wave():
+    """Flat window, V = cos(2 pi a t / n): the spectrum is n^3/2 at kt = +-a and zero
+    elsewhere, where alpha_t = 0 and alpha_x = alpha_y = 1, so E = (0, n^3/2, n^3/2); the
+    magnitude feature of the same wave is (0, 1, 1)."""
+    n, a = 8, 2
+    t = np.arange(24)
+    V = np.broadcast_to(np.cos(2 * np.pi * a * t / n)[:, None, None], (24, 16, 16)).astype(np.float32)
+    E = orc.features(V, n, 1, "rect", feature="energy")
+    g = (10, 8, 8)
+    assert np.allclose(E[:, g[0], g[1], g[2]], [0.0, n ** 3 / 2, n ** 3 / 2], rtol=0, atol=1e-9)
+    Em = orc.features(V, n, 1, "rect")
+    assert np.allclose(Em[:, g[0], g[1], g[2]], [0.0, 1.0, 1.0], rtol=0, atol=1e-12)
 
 
 def test_saliency_inline_plane_matches_full_grid():
