@@ -201,6 +201,25 @@ sal_status sal_fuse(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const
                     void* ws, size_t ws_bytes, sal_stream stream);
 
 /*
+ * sal_fuse_noalloc -- for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * sal_fuse with its workspace in a static device array of
+ * sal_fuse_noalloc_max_bytes() bytes, which the library holds on each device
+ * it runs on until the process ends.  Arguments and results are those of
+ * sal_fuse (bit for bit) without ws / ws_bytes.  ADAPT_LS takes at most 64
+ * weight groups (sal_fuse_groups()); more returns SAL_ERR_NOMEM (use sal_fuse
+ * with a workspace).  Every call on a device shares that device's array, so
+ * calls that overlap on one device (two streams or threads) race: serialise
+ * them.  Call sal_init() on the device before capturing a call in a graph
+ * (otherwise the first call resolves the array and, inside a capture, returns
+ * SAL_ERR_STATE).  Never allocates or frees device memory.
+ */
+size_t sal_fuse_noalloc_max_bytes(void);
+sal_status sal_fuse_noalloc(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion* fusion,
+                            const float* D, const uint8_t* mask, int64_t T, int64_t IL, int64_t XL, int32_t s,
+                            double* W_out, float* S_out, sal_stream stream);
+
+/*
  * sal_backward -- adjoint of the whole path (sal_project, sal_center_surround,
  * sal_fuse) for the scalar loss L = sum_v gS(v) S(v): gV = dL/dV.  Local
  * spectra are recomputed from V, never stored.  With ADAPT_LS the weights'

@@ -70,6 +70,9 @@ SIGNATURES = {
     "sal_fuse_workspace_size": (c_size_t, [c_int64, c_int64, c_int64, POINTER(SalFusion)]),
     "sal_fuse": (c_int32, [c_void_p, c_int64, c_int64, c_int64, POINTER(SalFusion), c_void_p, c_void_p, c_int64,
                            c_int64, c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "sal_fuse_noalloc_max_bytes": (c_size_t, []),
+    "sal_fuse_noalloc": (c_int32, [c_void_p, c_int64, c_int64, c_int64, POINTER(SalFusion), c_void_p, c_void_p,
+                                   c_int64, c_int64, c_int64, c_int32, c_void_p, c_void_p, c_void_p]),
     "sal_backward_workspace_size": (c_size_t, [c_int64, c_int64, c_int64, POINTER(SalSpec), POINTER(SalFusion)]),
     "sal_backward": (c_int32, [c_void_p, c_int64, c_int64, c_int64, POINTER(SalSpec), POINTER(SalStencil),
                                POINTER(SalFusion), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,

@@ -328,7 +328,11 @@ static sal_status init_device_tables(int dev) {
     return SAL_OK;
 }
 
-sal_status init_device(int dev) { return init_device_tables(dev); }
+sal_status init_device(int dev) {
+    sal_status st = init_device_tables(dev);
+    if (st) return st;
+    return init_noalloc_scratch(dev);
+}
 
 // The tables of the current device, uploading them first if `stream` is not capturing.
 static sal_status device_tables(hipStream_t stream, DeviceTables** out) {

@@ -65,8 +65,12 @@ struct Tables {
 // captured, uploads them (blocking); inside a capture fails with SAL_ERR_STATE.
 sal_status get_tables(hipStream_t stream, int n, int window, const Tables** out);
 
-// Uploads every table of device `dev` (current).
+// Uploads every table of device `dev` (current) and resolves its no-allocation scratch.
 sal_status init_device(int dev);
+// Resolves the device address of sal_fuse_noalloc's static scratch on `dev` (current).
+sal_status init_noalloc_scratch(int dev);
+// Fusion argument checks shared by sal_fuse, sal_fuse_noalloc and the plans.
+sal_status check_fusion_args(const sal_fusion* f, const float* D);
 
 // Per (device, n, s, window) B operands of the reduced-precision pass A, [KH][3][16 cols][32 K]:
 // planes bf16 hi, bf16 lo, fp16; column c < 8 is (c >> 2: h cos | -h sin, c & 3: window column

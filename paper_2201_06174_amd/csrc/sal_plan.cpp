@@ -15,9 +15,6 @@
 
 namespace sal {
 
-// Fusion checks shared with sal_fuse (defined in sal_api.cpp).
-sal_status check_fusion_args(const sal_fusion* f, const float* D);
-
 namespace {
 
 struct Class {
