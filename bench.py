@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-errors", action="store_true", help="skip the per-output errors against the oracle")
     ap.add_argument("--fwd-bwd-workload", default="grad", help="workload of --part fwd_bwd (grad or salt)")
+    ap.add_argument("--cache", default=None,
+                    help="directory for generated volumes (.npy): reused by later runs with the same workload")
     ap.add_argument("--part", choices=["fwd_bwd", "batch", "peaks"], default=None,
                     help="time only the forward + adjoint on the gradient workload, only the batch, or only "
                          "the device-peak microbenchmarks, and print that object")
@@ -115,6 +117,25 @@ class Pipeline:
                                           T, IL, XL, self.s, ctypes.c_void_p(self.W.data_ptr()),
                                           ctypes.c_void_p(self.S.data_ptr()), ctypes.c_void_p(self.ws.data_ptr()),
                                           self.ws.numel(), st))
+
+
+CACHE_DIR = None
+
+
+def make_volume(w, with_mask=False):
+    """The workload's synthetic volume (and structure mask), from --cache when present there."""
+    from paper_2201_06174_amd import synth
+    if CACHE_DIR:
+        base = os.path.join(CACHE_DIR, "%s_%d" % (w.name, w.seed))
+        if os.path.exists(base + "_V.npy") and os.path.exists(base + "_M.npy"):
+            V, M = np.load(base + "_V.npy"), np.load(base + "_M.npy")
+            return (V, M) if with_mask else V
+        V, M = synth.make_volume(w.spec, w.seed, with_mask=True)
+        os.makedirs(CACHE_DIR, exist_ok=True)
+        np.save(base + "_V.npy", V)
+        np.save(base + "_M.npy", M)
+        return (V, M) if with_mask else V
+    return synth.make_volume(w.spec, w.seed, with_mask=with_mask)
 
 
 def time_forward(torch, pipe, steps, warmup):
@@ -236,7 +257,7 @@ def time_fwd_bwd(torch, w_name, steps, warmup, peaks=None, V=None):
     from paper_2201_06174_amd import synth
     w = synth.workload(w_name)
     if V is None:
-        V = synth.make_volume(w.spec, w.seed)
+        V = make_volume(w)
     Vd = torch.from_numpy(V).cuda()
     gS = torch.from_numpy(synth.loss_weights(V.shape, 5001)).cuda()
     cfg = sal.Config(n=w.n, s=w.s, offsets=w.offsets, fusion="equal")
@@ -527,7 +548,9 @@ def oracle_rate(V, w, seconds, nth):
 
 
 def main():
+    global CACHE_DIR
     args = parse()
+    CACHE_DIR = args.cache
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (requested --gpus %d)" % args.gpus)
         sys.exit(2)
@@ -545,7 +568,7 @@ def main():
         print(json.dumps(measure_peaks(torch, lib)), flush=True)
         return
     w = synth.workload(args.workload)
-    V, M = synth.make_volume(w.spec, w.seed, with_mask=True)
+    V, M = make_volume(w, with_mask=True)
     D, mask = synth.desired_map(M, w.s)
     dev = torch.device("cuda:0")
     Vd = torch.from_numpy(V).to(dev)
@@ -611,7 +634,7 @@ def main():
         other = "survey" if args.workload != "survey" else "salt"
         progress("generating the %s volume" % other)
         wo = synth.workload(other)
-        Vo, Mo = synth.make_volume(wo.spec, wo.seed, with_mask=True)
+        Vo, Mo = make_volume(wo, with_mask=True)
         Do, masko = synth.desired_map(Mo, wo.s)
         Vod, Dod, Mod = (torch.from_numpy(a).to(dev) for a in (Vo, Do, masko))
         orc_o = OracleSection(Vo, wo, Do, masko, 1e-6) if errs else None
