@@ -66,6 +66,12 @@ typedef enum { SAL_WINDOW_HANN = 0, SAL_WINDOW_RECT = 1 } sal_window;
  * fusion statistics). */
 typedef enum { SAL_PREC_FP32 = 0, SAL_PREC_SPLIT_BF16 = 1, SAL_PREC_FP16 = 2 } sal_precision;
 
+/* Feature of the third step of Sec. 2, the mean over the n^3 cube of the
+ * projected spectrum F_m = alpha_m F (Eq. 1): of its magnitude |F_m|
+ * (MAGNITUDE, the default), or of its energy |F_m|^2 = alpha_m^2 |F|^2
+ * (ENERGY; FP32 only, not batched). */
+typedef enum { SAL_FEATURE_MAGNITUDE = 0, SAL_FEATURE_ENERGY = 1 } sal_feature;
+
 /* Window and sampling (Sec. 2 step 1: local cube of side n, sliding window
  * with more than 50 % overlap).  n in {4, 8, 12, 16}; 1 <= s < n/2. */
 typedef struct {
@@ -73,6 +79,7 @@ typedef struct {
     int32_t s;         /* stride between window centres, voxels */
     int32_t window;    /* sal_window */
     int32_t precision; /* sal_precision */
+    int32_t feature;   /* sal_feature */
 } sal_spec;
 
 /* Directional center-surround stencil (Sec. 2 step 4, Eq. 3 and Fig. 4).
@@ -110,7 +117,14 @@ typedef struct sal_stencil {
 sal_status sal_line_template(const int32_t* dir, int32_t length, double sigma, int32_t* offsets_out,
                              float* weights_out);
 
-typedef enum { SAL_FUSE_EQUAL = 0, SAL_FUSE_FIXED = 1, SAL_FUSE_ADAPT_LS = 2 } sal_fusion_mode;
+typedef enum {
+    SAL_FUSE_EQUAL = 0,
+    SAL_FUSE_FIXED = 1,
+    SAL_FUSE_ADAPT_LS = 2,
+    SAL_FUSE_LMS = 3,
+    SAL_FUSE_NLMS = 4,
+    SAL_FUSE_RLS = 5
+} sal_fusion_mode;
 
 /* Fusion of the three directional maps (Sec. 2 step 5, Eq. 4).  EQUAL: 1/3
  * each; FIXED: w_fixed (the "empirical" template); ADAPT_LS: the
@@ -119,6 +133,17 @@ typedef enum { SAL_FUSE_EQUAL = 0, SAL_FUSE_FIXED = 1, SAL_FUSE_ADAPT_LS = 2 } s
  * paper's LMS/NLMS/RLS adaptation converges to.  A Gram matrix that is not
  * numerically positive definite falls back to EQUAL and raises the status
  * word (see sal_fuse).
+ * LMS, NLMS, RLS: the sequential recursions themselves (Sec. 2: the weights
+ * are adapted with LMS, NLMS or RLS; Fig. 6), starting from W0 = w_fixed and
+ * sweeping the masked grid points in memory order `passes` times; at each
+ * sample u = (S_t, S_x, S_y) with a priori error e = D - W.u:
+ *   LMS  W += mu e u;   NLMS W += mu e u / (eps + u.u);
+ *   RLS  P0 = I / delta, k = P u / (lambda + u.P u), W += k e,
+ *        P = (P - k (P u)^T) / lambda.
+ * RLS with lambda = 1 and W0 = 0 ends at the ADAPT_LS weights with the same
+ * delta.  Their status word is 0.  sal_adapt_weights also returns the
+ * learning curve.  The adjoint (sal_backward), the batched plans and
+ * sal_fuse_noalloc do not take these modes (SAL_ERR_UNSUPPORTED).
  * sections: 0 fits one W for the whole volume; N > 0 re-adapts every N
  * inline sections (Sec. 2, last paragraph): the grid's inline planes are cut
  * into K = ceil(ILg / N) groups [kN, kN + N), each with its own W fitted on
@@ -126,9 +151,13 @@ typedef enum { SAL_FUSE_EQUAL = 0, SAL_FUSE_FIXED = 1, SAL_FUSE_ADAPT_LS = 2 } s
  * group.  sal_fuse_groups() gives K. */
 typedef struct {
     int32_t mode;
-    double w_fixed[3];
-    double delta;     /* >= 0 */
-    int64_t sections; /* >= 0 */
+    double w_fixed[3];  /* FIXED: the weights; LMS / NLMS / RLS: the starting weights */
+    double delta;       /* >= 0; ADAPT_LS: the ridge term; RLS: P0 = I / delta (> 0) */
+    int64_t sections;   /* >= 0 */
+    double mu;          /* LMS / NLMS step (> 0) */
+    double eps;         /* NLMS regulariser (>= 0) */
+    double lambda;      /* RLS forgetting factor, in (0, 1] */
+    int32_t passes;     /* LMS / NLMS / RLS sweeps over the masked points (>= 1) */
 } sal_fusion;
 
 /* Number of weight groups K of a fusion over a grid with ILg inline planes
@@ -163,7 +192,8 @@ sal_status sal_local_spectra(const float* V, int64_t T, int64_t IL, int64_t XL, 
 
 /*
  * sal_project -- Sec. 2 steps 1-3, Eq. 1-2.
- * Features E_m(g) = n^-3 sum_{k != 0} alpha_m(k) |F_g(k)| with
+ * Features E_m(g) = n^-3 sum_{k != 0} alpha_m(k) |F_g(k)| (or, with the
+ * energy feature, n^-3 sum_{k != 0} alpha_m(k)^2 |F_g(k)|^2) with
  * alpha_t = sqrt(ki^2 + kx^2)/|k|, alpha_x = sqrt(kt^2 + ki^2)/|k|,
  * alpha_y = sqrt(kt^2 + kx^2)/|k| (signed bin frequencies; the DC bin, the
  * centre of the spectral cube, is not computed).
@@ -193,12 +223,30 @@ sal_status sal_center_surround(const float* E, int64_t Tg, int64_t ILg, int64_t 
  *   W_out   device double [K][4], K = sal_fuse_groups(): per group W_t, W_x, W_y,
  *           then the status word (0, or 1 if ADAPT_LS fell back to equal weights)
  *   S_out   device float [T][IL][XL]
- *   ws      device workspace of at least sal_fuse_workspace_size() bytes (ADAPT_LS)
+ *   ws      device workspace of at least sal_fuse_workspace_size() bytes (ADAPT_LS,
+ *           LMS, NLMS, RLS)
  */
 size_t sal_fuse_workspace_size(int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion* fusion);
 sal_status sal_fuse(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion* fusion, const float* D,
                     const uint8_t* mask, int64_t T, int64_t IL, int64_t XL, int32_t s, double* W_out, float* S_out,
                     void* ws, size_t ws_bytes, sal_stream stream);
+
+/*
+ * sal_adapt_weights -- the sequential LMS / NLMS / RLS weights of Eq. 4 and
+ * their learning curve (Sec. 2, fusion paragraph; Fig. 6), without the combine.
+ *   fusion     mode SAL_FUSE_LMS, SAL_FUSE_NLMS or SAL_FUSE_RLS (see sal_fusion)
+ *   Sm, D, mask as in sal_fuse
+ *   W_out      device double [K][4] (the status words are 0)
+ *   err2_out   device float [K][cap]: the squared a priori errors e^2 of the first
+ *              cap updates of each group, in update order (NULL: not written)
+ *   count_out  device int64 [K]: the samples of one pass of each group (NULL: not written)
+ *   ws         device workspace of at least sal_fuse_workspace_size() bytes
+ * Needs fewer than 2^31 grid points.  sal_fuse with the same fusion gives the
+ * same W bit for bit.
+ */
+sal_status sal_adapt_weights(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion* fusion,
+                             const float* D, const uint8_t* mask, double* W_out, float* err2_out, int64_t cap,
+                             int64_t* count_out, void* ws, size_t ws_bytes, sal_stream stream);
 
 /*
  * sal_fuse_noalloc -- for callers that cannot allocate device memory (code under

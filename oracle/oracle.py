@@ -12,7 +12,8 @@ Shafiq, Long, Di, AlRegib (ACI 2021), Section 2:
   |F_m| or of the energy |F_m|^2 -- ``features``;
 * directional center-surround S_m (Eq. 3) -- ``dcs``, ``saliency_at``;
 * fusion weights and the combined map S (Eq. 4) -- ``fusion_weights``,
-  ``combine``, and with re-adaptation every N inline sections
+  ``combine``; the sequential LMS / NLMS / RLS weights and their learning
+  curve -- ``adapt_sequential``; with re-adaptation every N inline sections
   ``fusion_weights_sections``, ``combine_sections``;
 * per-plane stencils and graded line templates (Sec. 2 step 4, Fig. 4) --
   ``dcs_planes``, ``line_template``;
@@ -215,6 +216,30 @@ def fusion_weights_sections(Sm, sections: int, D=None, mask=None, mode="equal", 
                                              ctypes.c_double(delta), _i64(sections), _p(W), _p(fb), _p(st))
     _check(rc, "fusion_weights_sections")
     return W, fb, st
+
+
+ADAPT_RULES = {"lms": 0, "nlms": 1, "rls": 2}
+
+
+def adapt_sequential(Sm, D, mask=None, rule="nlms", mu=0.5, eps=1e-6, lam=1.0, delta=1.0, w0=(1 / 3, 1 / 3, 1 / 3),
+                     passes=1, sections=0, cap=0):
+    """(W[K][3], count[K], err2[K][cap]): the sequential LMS / NLMS / RLS weights over the masked
+    grid points in memory order, and the squared a priori errors in update order."""
+    Sm = np.ascontiguousarray(Sm, dtype=np.float64)
+    _, Tg, ILg, XLg = Sm.shape
+    K = fuse_groups(ILg, sections)
+    Dp = np.ascontiguousarray(D, dtype=np.float32).reshape(-1)
+    Mp = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
+    w = np.ascontiguousarray(w0, dtype=np.float64)
+    W = np.zeros((K, 3), np.float64)
+    cnt = np.zeros(K, np.int64)
+    err = np.zeros((K, max(cap, 1)), np.float64)
+    rc = _load().orc_adapt_sequential(_p(Sm), _i64(Tg), _i64(ILg), _i64(XLg), _p(Dp), _p(Mp),
+                                      ctypes.c_int(ADAPT_RULES[rule]), ctypes.c_double(mu), ctypes.c_double(eps),
+                                      ctypes.c_double(lam), ctypes.c_double(delta), _p(w), ctypes.c_int(passes),
+                                      _i64(sections), _p(W), _p(cnt), _p(err) if cap else None, _i64(cap))
+    _check(rc, "adapt_sequential")
+    return W, cnt, err[:, :cap]
 
 
 def combine_sections(Sm, W, sections: int, shape, s: int) -> np.ndarray:

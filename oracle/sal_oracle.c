@@ -20,8 +20,10 @@
  *          templates along a direction (Fig. 4);
  *   step 5 (Sec. 2, Eq. 4): S = W_t S_t + W_x S_x + W_y S_y with equal, fixed
  *          or least-squares-adapted weights (the fixed point of the LMS/NLMS
- *          and the exact result of RLS with unit forgetting factor), fitted
- *          once or again every N inline sections (last paragraph of Sec. 2).
+ *          and the exact result of RLS with unit forgetting factor), or the
+ *          weights of the sequential LMS, NLMS and RLS recursions themselves,
+ *          fitted once or again every N inline sections (last paragraph of
+ *          Sec. 2).
  *
  * Readings taken where the paper is silent (each is listed in the design doc):
  *   - volume V is float32 [T][IL][XL] (XL fastest); feature/saliency planes
@@ -638,6 +640,61 @@ int orc_fusion_weights_sections(const double* Sm, int64_t Tg, int64_t ILg, int64
     }
     free(mk);
     return rc;
+}
+
+/* Sequential weight adaptation (Sec. 2, fusion paragraph, and Fig. 6: the
+ * weights are adapted with LMS, NLMS or RLS towards the desired map).  The
+ * samples are the masked grid points of each weight group in memory order,
+ * u = (S_t, S_x, S_y), swept `passes` times; starting weights w0.  At every
+ * sample, with the a priori error e = D - w.u:
+ *   rule 0 (LMS):  w += mu e u;
+ *   rule 1 (NLMS): w += mu e u / (eps + u.u);
+ *   rule 2 (RLS):  P0 = I / delta (per group), k = P u / (lambda + u.P u),
+ *                  w += k e, P = (P - k (P u)^T) / lambda.
+ * W: [K][3]; count: [K] samples per pass; err2: [K][cap] squared a priori
+ * errors in update order (the learning curve; the first cap kept), or NULL. */
+int orc_adapt_sequential(const double* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const float* D,
+                         const uint8_t* mask, int rule, double mu, double eps, double lambda, double delta,
+                         const double* w0, int passes, int64_t N, double* W, int64_t* count, double* err2,
+                         int64_t cap) {
+    if (rule < 0 || rule > 2 || passes < 1 || N < 0 || !D) return ORC_EARG;
+    if (rule == 2 && (!(lambda > 0.0) || lambda > 1.0 || !(delta > 0.0))) return ORC_EARG;
+    int64_t G = Tg * ILg * XLg, K = orc_fuse_groups(ILg, N);
+    for (int64_t k = 0; k < K; k++) {
+        double w[3] = {w0[0], w0[1], w0[2]};
+        double P[9] = {1.0 / delta, 0, 0, 0, 1.0 / delta, 0, 0, 0, 1.0 / delta};
+        int64_t it = 0, cnt = 0;
+        for (int pass = 0; pass < passes; pass++) {
+            cnt = 0;
+            for (int64_t j = 0; j < G; j++) {
+                int64_t gi = (j / XLg) % ILg;
+                if (N > 0 && (gi < k * N || gi >= (k + 1) * N)) continue;
+                if (mask && !mask[j]) continue;
+                double u[3] = {Sm[j], Sm[G + j], Sm[2 * G + j]};
+                double e = (double)D[j] - (w[0] * u[0] + w[1] * u[1] + w[2] * u[2]);
+                if (err2 && it < cap) err2[k * cap + it] = e * e;
+                if (rule == 0) {
+                    for (int m = 0; m < 3; m++) w[m] += mu * e * u[m];
+                } else if (rule == 1) {
+                    double g = mu * e / (eps + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+                    for (int m = 0; m < 3; m++) w[m] += g * u[m];
+                } else {
+                    double Pu[3];
+                    for (int a = 0; a < 3; a++) Pu[a] = P[3 * a] * u[0] + P[3 * a + 1] * u[1] + P[3 * a + 2] * u[2];
+                    double den = lambda + u[0] * Pu[0] + u[1] * Pu[1] + u[2] * Pu[2];
+                    double kg[3] = {Pu[0] / den, Pu[1] / den, Pu[2] / den};
+                    for (int m = 0; m < 3; m++) w[m] += kg[m] * e;
+                    for (int a = 0; a < 3; a++)
+                        for (int b = 0; b < 3; b++) P[3 * a + b] = (P[3 * a + b] - kg[a] * Pu[b]) / lambda;
+                }
+                it++;
+                cnt++;
+            }
+        }
+        W[3 * k] = w[0]; W[3 * k + 1] = w[1]; W[3 * k + 2] = w[2];
+        count[k] = cnt;
+    }
+    return ORC_OK;
 }
 
 /* S(v) = sum_m W_m S_m(g(v)) with the weights of g(v)'s group. */

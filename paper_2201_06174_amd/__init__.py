@@ -15,7 +15,7 @@ import numpy as np
 from . import _lib
 
 __all__ = ["Config", "init", "local_spectra", "project", "center_surround", "fuse", "saliency", "backward",
-           "SaliencyFn", "grid_shape", "fuse_groups", "fuse_workspace_size", "backward_workspace_size",
+           "SaliencyFn", "grid_shape", "fuse_groups", "fuse_workspace_size", "backward_workspace_size", "adapt_weights",
            "line_template", "Plan"]
 
 
@@ -80,6 +80,8 @@ class Config:
     s: int = 1
     window: str = "hann"
     precision: str = "fp32"
+    # "magnitude" (mean |F_m|) or "energy" (mean |F_m|^2; fp32 only)
+    feature: str = "magnitude"
     offsets: np.ndarray = field(default_factory=lambda: np.zeros((0, 3), np.int32))
     weights: Optional[np.ndarray] = None
     literal: bool = False
@@ -90,6 +92,11 @@ class Config:
     planes: Optional[list] = None
     # re-adapt the fusion weights every `sections` grid inline sections (0: one fit)
     sections: int = 0
+    # sequential rules (fusion "lms", "nlms", "rls"; wfix = starting weights, delta = RLS P0^-1)
+    mu: float = 0.5
+    eps: float = 1e-6
+    lam: float = 1.0
+    passes: int = 1
 
 
 def line_template(direction, length, sigma):
@@ -120,7 +127,7 @@ def local_spectra(V, centers, n, window="hann"):
     return torch.view_as_complex(F)
 
 
-def project(V, n, s, window="hann", precision="fp32"):
+def project(V, n, s, window="hann", precision="fp32", feature="magnitude"):
     """Features E[3][Tg][ILg][XLg] (planes t, x = XL, y = IL)."""
     torch = _torch()
     _need(V, torch.float32, "V")
@@ -128,7 +135,7 @@ def project(V, n, s, window="hann", precision="fp32"):
         raise ValueError("V must be [T][IL][XL]")
     T, IL, XL = V.shape
     E = torch.empty((3,) + grid_shape(V.shape, s), dtype=torch.float32, device=V.device)
-    spec = _lib.make_spec(n, s, window, precision)
+    spec = _lib.make_spec(n, s, window, precision, feature)
     _lib.check(_lib.load().sal_project(_ptr(V), T, IL, XL, spec, _ptr(E), _stream()))
     return E
 
@@ -146,14 +153,20 @@ def center_surround(E, s, offsets, weights=None, literal=False, planes=None):
     return Sm
 
 
-def fuse_workspace_size(grid, sections=0):
-    f = _lib.make_fusion("equal", None, 0.0, sections)
+def fuse_workspace_size(grid, sections=0, mode="equal"):
+    f = _lib.make_fusion(mode, None, 0.0, sections)
     return int(_lib.load().sal_fuse_workspace_size(grid[0], grid[1], grid[2], f))
 
 
-def fuse(Sm, shape, s, mode="equal", wfix=None, delta=0.0, D=None, mask=None, ws=None, sections=0):
+def _fusion(cfg):
+    return _lib.make_fusion(cfg.fusion, cfg.wfix, cfg.delta, cfg.sections, cfg.mu, cfg.eps, cfg.lam, cfg.passes)
+
+
+def fuse(Sm, shape, s, mode="equal", wfix=None, delta=0.0, D=None, mask=None, ws=None, sections=0, mu=0.5,
+         eps=1e-6, lam=1.0, passes=1):
     """(S[T][IL][XL], W float64: W_t, W_x, W_y, fallback flag -- shape [4] without sections,
-    [K][4] with re-adaptation every `sections` inline sections)."""
+    [K][4] with re-adaptation every `sections` inline sections).  Modes equal, fixed,
+    adapt_ls, and the sequential lms, nlms, rls (wfix: their starting weights)."""
     torch = _torch()
     _need(Sm, torch.float32, "Sm")
     if Sm.dim() != 4 or Sm.shape[0] != 3:
@@ -167,10 +180,10 @@ def fuse(Sm, shape, s, mode="equal", wfix=None, delta=0.0, D=None, mask=None, ws
         _need(mask, torch.uint8, "mask", grid)
     T, IL, XL = shape
     S = torch.empty((T, IL, XL), dtype=torch.float32, device=Sm.device)
-    f = _lib.make_fusion(mode, wfix, delta, sections)
+    f = _lib.make_fusion(mode, wfix, delta, sections, mu, eps, lam, passes)
     K = int(_lib.load().sal_fuse_groups(f, grid[1]))
     W = torch.empty((K, 4) if sections else (4,), dtype=torch.float64, device=Sm.device)
-    nbytes = fuse_workspace_size(grid, sections)
+    nbytes = fuse_workspace_size(grid, sections, mode)
     if ws is None:
         ws = torch.empty(nbytes, dtype=torch.uint8, device=Sm.device)
     _lib.check(_lib.load().sal_fuse(_ptr(Sm), grid[0], grid[1], grid[2], f, _ptr(D), _ptr(mask), T, IL, XL, s,
@@ -180,10 +193,36 @@ def fuse(Sm, shape, s, mode="equal", wfix=None, delta=0.0, D=None, mask=None, ws
 
 def saliency(V, cfg: Config, D=None, mask=None):
     """Whole forward path: returns dict(E, Sm, S, W)."""
-    E = project(V, cfg.n, cfg.s, cfg.window, cfg.precision)
+    E = project(V, cfg.n, cfg.s, cfg.window, cfg.precision, cfg.feature)
     Sm = center_surround(E, cfg.s, cfg.offsets, cfg.weights, cfg.literal, cfg.planes)
-    S, W = fuse(Sm, tuple(V.shape), cfg.s, cfg.fusion, cfg.wfix, cfg.delta, D, mask, sections=cfg.sections)
+    S, W = fuse(Sm, tuple(V.shape), cfg.s, cfg.fusion, cfg.wfix, cfg.delta, D, mask, sections=cfg.sections,
+                mu=cfg.mu, eps=cfg.eps, lam=cfg.lam, passes=cfg.passes)
     return {"E": E, "Sm": Sm, "S": S, "W": W}
+
+
+def adapt_weights(Sm, cfg: Config, D, mask=None, cap=0):
+    """The sequential LMS / NLMS / RLS weights (cfg.fusion "lms", "nlms" or "rls") and their
+    learning curve: (W [K][4] float64, err2 [K][cap] float32 squared a priori errors in update
+    order, count [K] int64 samples per pass)."""
+    torch = _torch()
+    _need(Sm, torch.float32, "Sm")
+    if Sm.dim() != 4 or Sm.shape[0] != 3:
+        raise ValueError("Sm must be [3][Tg][ILg][XLg], got %s" % (tuple(Sm.shape),))
+    grid = tuple(Sm.shape[1:])
+    _need(D, torch.float32, "D", grid)
+    if mask is not None:
+        _need(mask, torch.uint8, "mask", grid)
+    f = _fusion(cfg)
+    K = int(_lib.load().sal_fuse_groups(f, grid[1]))
+    W = torch.empty((K, 4), dtype=torch.float64, device=Sm.device)
+    err = torch.empty((K, max(int(cap), 1)), dtype=torch.float32, device=Sm.device)
+    cnt = torch.empty(K, dtype=torch.int64, device=Sm.device)
+    nbytes = int(_lib.load().sal_fuse_workspace_size(grid[0], grid[1], grid[2], f))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=Sm.device)
+    _lib.check(_lib.load().sal_adapt_weights(_ptr(Sm), grid[0], grid[1], grid[2], f, _ptr(D), _ptr(mask), _ptr(W),
+                                             _ptr(err) if cap else None, int(cap), _ptr(cnt), _ptr(ws), ws.numel(),
+                                             _stream()))
+    return W, err[:, :cap], cnt
 
 
 def backward_workspace_size(shape, n, s, window="hann", precision="fp32", sections=0):
@@ -210,9 +249,9 @@ def backward(V, cfg: Config, E, Sm, W, gS, D=None, mask=None):
         _need(mask, torch.uint8, "mask", grid)
     T, IL, XL = V.shape
     gV = torch.empty_like(V)
-    spec = _lib.make_spec(cfg.n, cfg.s, cfg.window, cfg.precision)
+    spec = _lib.make_spec(cfg.n, cfg.s, cfg.window, cfg.precision, cfg.feature)
     st, keep = _lib.make_stencil(cfg.offsets, cfg.weights, cfg.literal, cfg.planes)
-    f = _lib.make_fusion(cfg.fusion, cfg.wfix, cfg.delta, cfg.sections)
+    f = _fusion(cfg)
     nbytes = backward_workspace_size(V.shape, cfg.n, cfg.s, cfg.window, cfg.precision, cfg.sections)
     ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=V.device)
     _lib.check(_lib.load().sal_backward(_ptr(V), T, IL, XL, spec, st, f, _ptr(E), _ptr(Sm), _ptr(W), _ptr(D),
@@ -284,9 +323,9 @@ class Plan:
             it = arr[i]
             it.V = V.data_ptr()
             it.T, it.IL, it.XL = V.shape
-            it.spec = _lib.make_spec(cfg.n, cfg.s, cfg.window, cfg.precision)
+            it.spec = _lib.make_spec(cfg.n, cfg.s, cfg.window, cfg.precision, cfg.feature)
             it.stencil = st
-            it.fusion = _lib.make_fusion(cfg.fusion, cfg.wfix, cfg.delta, cfg.sections)
+            it.fusion = _fusion(cfg)
             it.D = None if D is None else _need(D, torch.float32, "D", grid).data_ptr()
             it.mask = None if mask is None else _need(mask, torch.uint8, "mask", grid).data_ptr()
             it.E_out = out["E"].data_ptr()

@@ -17,12 +17,13 @@ STATUS_NAMES = {0: "SAL_OK", 1: "SAL_ERR_ARG", 2: "SAL_ERR_SHAPE", 3: "SAL_ERR_U
                 5: "SAL_ERR_DEVICE", 6: "SAL_ERR_STATE"}
 WINDOW = {"hann": 0, "rect": 1}
 PRECISION = {"fp32": 0, "split_bf16": 1, "fp16": 2}
-FUSION = {"equal": 0, "fixed": 1, "adapt_ls": 2}
+FEATURE = {"magnitude": 0, "energy": 1}
+FUSION = {"equal": 0, "fixed": 1, "adapt_ls": 2, "lms": 3, "nlms": 4, "rls": 5}
 MAX_STENCIL = 64
 
 
 class SalSpec(ctypes.Structure):
-    _fields_ = [("n", c_int32), ("s", c_int32), ("window", c_int32), ("precision", c_int32)]
+    _fields_ = [("n", c_int32), ("s", c_int32), ("window", c_int32), ("precision", c_int32), ("feature", c_int32)]
 
 
 class SalStencil(ctypes.Structure):
@@ -34,7 +35,8 @@ SalStencil._fields_ = [("q", c_int32), ("offsets", POINTER(c_int32)), ("weights"
 
 
 class SalFusion(ctypes.Structure):
-    _fields_ = [("mode", c_int32), ("w_fixed", c_double * 3), ("delta", c_double), ("sections", c_int64)]
+    _fields_ = [("mode", c_int32), ("w_fixed", c_double * 3), ("delta", c_double), ("sections", c_int64),
+                ("mu", c_double), ("eps", c_double), ("lambda_", c_double), ("passes", c_int32)]
 
 
 class SalBatchItem(ctypes.Structure):
@@ -70,6 +72,8 @@ SIGNATURES = {
     "sal_fuse_workspace_size": (c_size_t, [c_int64, c_int64, c_int64, POINTER(SalFusion)]),
     "sal_fuse": (c_int32, [c_void_p, c_int64, c_int64, c_int64, POINTER(SalFusion), c_void_p, c_void_p, c_int64,
                            c_int64, c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "sal_adapt_weights": (c_int32, [c_void_p, c_int64, c_int64, c_int64, POINTER(SalFusion), c_void_p, c_void_p,
+                                    c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_size_t, c_void_p]),
     "sal_fuse_noalloc_max_bytes": (c_size_t, []),
     "sal_fuse_noalloc": (c_int32, [c_void_p, c_int64, c_int64, c_int64, POINTER(SalFusion), c_void_p, c_void_p,
                                    c_int64, c_int64, c_int64, c_int32, c_void_p, c_void_p, c_void_p]),
@@ -152,13 +156,18 @@ def make_stencil(offsets, weights=None, literal=False, planes=None):
     return st, keep
 
 
-def make_fusion(mode="equal", wfix=None, delta=0.0, sections=0):
+def make_fusion(mode="equal", wfix=None, delta=0.0, sections=0, mu=0.0, eps=0.0, lam=1.0, passes=1):
+    """SalFusion; wfix: FIXED weights, or the starting weights of LMS / NLMS / RLS."""
     f = SalFusion()
     f.mode = FUSION[mode] if isinstance(mode, str) else int(mode)
     w = [0.0, 0.0, 0.0] if wfix is None else [float(v) for v in wfix]
     f.w_fixed = (c_double * 3)(*w)
     f.delta = float(delta)
     f.sections = int(sections)
+    f.mu = float(mu)
+    f.eps = float(eps)
+    f.lambda_ = float(lam)
+    f.passes = int(passes)
     return f
 
 
@@ -173,9 +182,10 @@ def line_template(direction, length, sigma):
     return off, w
 
 
-def make_spec(n, s, window="hann", precision="fp32"):
+def make_spec(n, s, window="hann", precision="fp32", feature="magnitude"):
     sp = SalSpec()
     sp.n, sp.s = int(n), int(s)
     sp.window = WINDOW[window] if isinstance(window, str) else int(window)
     sp.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    sp.feature = FEATURE[feature] if isinstance(feature, str) else int(feature)
     return sp

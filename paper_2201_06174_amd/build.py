@@ -17,7 +17,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["sal_host.cpp", "sal_api.cpp", "sal_project.hip", "sal_aux.hip", "sal_backward.hip", "sal_lowp.hip",
-           "sal_batch.hip", "sal_plan.cpp", "sal_peak.hip", "sal_noalloc.hip"]
+           "sal_batch.hip", "sal_plan.cpp", "sal_peak.hip", "sal_noalloc.hip",
+           "sal_adapt.hip"]
 
 FLAGS = [
     "-x", "hip", "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",

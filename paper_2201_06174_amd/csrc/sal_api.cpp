@@ -125,8 +125,23 @@ sal_status make_stencil(const sal_stencil* st, int s, DcsStencil* out) {
 
 static sal_status check_fusion(const sal_fusion* f, const float* D) {
     if (!f) return fail(SAL_ERR_ARG, "fusion is NULL");
-    if (f->mode != SAL_FUSE_EQUAL && f->mode != SAL_FUSE_FIXED && f->mode != SAL_FUSE_ADAPT_LS)
+    if (f->mode != SAL_FUSE_EQUAL && f->mode != SAL_FUSE_FIXED && f->mode != SAL_FUSE_ADAPT_LS &&
+        !fuse_sequential(f->mode))
         return fail(SAL_ERR_ARG, "unknown fusion mode");
+    if (fuse_sequential(f->mode)) {
+        if (!D) return fail(SAL_ERR_ARG, "LMS / NLMS / RLS need a desired map D");
+        for (int m = 0; m < 3; m++)
+            if (!std::isfinite(f->w_fixed[m])) return fail(SAL_ERR_ARG, "starting weights must be finite");
+        if (f->passes < 1) return fail(SAL_ERR_ARG, "passes must be >= 1");
+        if (f->mode != SAL_FUSE_RLS && (!(f->mu > 0.0) || !std::isfinite(f->mu)))
+            return fail(SAL_ERR_ARG, "mu must be finite and > 0");
+        if (f->mode == SAL_FUSE_NLMS && (!(f->eps >= 0.0) || !std::isfinite(f->eps)))
+            return fail(SAL_ERR_ARG, "eps must be finite and >= 0");
+        if (f->mode == SAL_FUSE_RLS && (!(f->lambda > 0.0) || f->lambda > 1.0))
+            return fail(SAL_ERR_ARG, "lambda must lie in (0, 1]");
+        if (f->mode == SAL_FUSE_RLS && (!(f->delta > 0.0) || !std::isfinite(f->delta)))
+            return fail(SAL_ERR_ARG, "RLS needs a finite delta > 0 (P0 = I / delta)");
+    }
     if (f->mode == SAL_FUSE_ADAPT_LS) {
         if (!D) return fail(SAL_ERR_ARG, "ADAPT_LS needs a desired map D");
         if (!(f->delta >= 0.0) || !std::isfinite(f->delta)) return fail(SAL_ERR_ARG, "delta must be finite and >= 0");
@@ -152,6 +167,7 @@ sal_status sal_local_spectra(const float* V, int64_t T, int64_t IL, int64_t XL, 
     sal_spec sp = *spec;
     sp.s = 1;
     sp.precision = SAL_PREC_FP32;
+    sp.feature = SAL_FEATURE_MAGNITUDE;
     sal_status st = check_spec(&sp, T, IL, XL);
     if (st) return st;
     if (cnt < 0) return fail(SAL_ERR_ARG, "negative centre count");
@@ -168,7 +184,7 @@ sal_status sal_project(const float* V, int64_t T, int64_t IL, int64_t XL, const 
     if ((st = get_tables((hipStream_t)stream, spec->n, spec->window, &tb))) return st;
     switch (spec->precision) {
         case SAL_PREC_FP32:
-            return launch_project_fp32(V, T, IL, XL, spec->n, spec->s, tb, E_out, (hipStream_t)stream);
+            return launch_project_fp32(V, T, IL, XL, spec->n, spec->s, spec->feature, tb, E_out, (hipStream_t)stream);
         default:
             return launch_project_lowp(V, T, IL, XL, spec->n, spec->s, spec->precision, tb, E_out,
                                        (hipStream_t)stream);
@@ -191,10 +207,15 @@ int64_t sal_fuse_groups(const sal_fusion* fusion, int64_t ILg) {
     return fuse_groups(fusion->sections, ILg);
 }
 
+static size_t fuse_ws_bytes(const sal_fusion* f, int64_t Tg, int64_t ILg, int64_t XLg) {
+    const int64_t K = f && f->sections > 0 ? fuse_groups(f->sections, ILg) : 1;
+    if (f && fuse_sequential(f->mode)) return seq_workspace_bytes(Tg * ILg * XLg, K);
+    return fuse_workspace_bytes(K);
+}
+
 size_t sal_fuse_workspace_size(int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion* fusion) {
     if (Tg < 0 || ILg < 0 || XLg < 0) return 0;
-    const int64_t K = fusion ? sal_fuse_groups(fusion, ILg) : 1;
-    return fuse_workspace_bytes(K > 0 ? K : 1);
+    return fuse_ws_bytes(fusion, Tg, ILg, XLg);
 }
 
 sal_status sal_line_template(const int32_t* dir, int32_t length, double sigma, int32_t* offsets_out,
@@ -227,10 +248,34 @@ sal_status sal_fuse(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const
     if (!Sm || !W_out || !S_out) return fail(SAL_ERR_ARG, "NULL buffer");
     if (T < 1 || IL < 1 || XL < 1) return fail(SAL_ERR_SHAPE, "empty volume");
     if ((st = check_grid(T, IL, XL, s, Tg, ILg, XLg))) return st;
-    if (fusion->mode == SAL_FUSE_ADAPT_LS && (!ws || ws_bytes < fuse_workspace_bytes(fuse_groups(fusion->sections, ILg))))
+    const bool needs_ws = fusion->mode == SAL_FUSE_ADAPT_LS || fuse_sequential(fusion->mode);
+    if (needs_ws && (!ws || ws_bytes < fuse_ws_bytes(fusion, Tg, ILg, XLg)))
         return fail(SAL_ERR_NOMEM, "workspace smaller than sal_fuse_workspace_size()");
+    if (fuse_sequential(fusion->mode)) {
+        const int64_t K = fuse_groups(fusion->sections, ILg);
+        if ((st = launch_seq_adapt(Sm, Tg, ILg, XLg, *fusion, D, mask, W_out, nullptr, 0, nullptr, ws,
+                                   (hipStream_t)stream)))
+            return st;
+        return launch_combine(Sm, Tg, ILg, XLg, K > 1 ? fusion->sections : 0, T, IL, XL, s, W_out, S_out,
+                              (hipStream_t)stream);
+    }
     return launch_fuse(Sm, Tg, ILg, XLg, *fusion, D, mask, T, IL, XL, s, W_out, S_out, (double*)ws,
                        (hipStream_t)stream);
+}
+
+sal_status sal_adapt_weights(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion* fusion,
+                             const float* D, const uint8_t* mask, double* W_out, float* err2_out, int64_t cap,
+                             int64_t* count_out, void* ws, size_t ws_bytes, sal_stream stream) {
+    sal_status st = check_fusion(fusion, D);
+    if (st) return st;
+    if (!fuse_sequential(fusion->mode)) return fail(SAL_ERR_ARG, "sal_adapt_weights takes the LMS, NLMS and RLS modes");
+    if (!Sm || !W_out) return fail(SAL_ERR_ARG, "NULL buffer");
+    if (Tg < 0 || ILg < 0 || XLg < 0) return fail(SAL_ERR_SHAPE, "negative grid extent");
+    if (cap < 0 || (cap > 0 && !err2_out)) return fail(SAL_ERR_ARG, "err2_out must hold cap >= 0 values");
+    if (!ws || ws_bytes < fuse_ws_bytes(fusion, Tg, ILg, XLg))
+        return fail(SAL_ERR_NOMEM, "workspace smaller than sal_fuse_workspace_size()");
+    return launch_seq_adapt(Sm, Tg, ILg, XLg, *fusion, D, mask, W_out, cap > 0 ? err2_out : nullptr, cap, count_out,
+                            ws, (hipStream_t)stream);
 }
 
 }  // extern "C"

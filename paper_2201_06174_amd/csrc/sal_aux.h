@@ -50,6 +50,19 @@ sal_status launch_fuse(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, co
                        const uint8_t* mask, int64_t T, int64_t IL, int64_t XL, int s, double* W, float* S, double* ws,
                        hipStream_t stream);
 size_t fuse_adjoint_workspace_bytes(int64_t K);
+// The sequential rules (LMS, NLMS, RLS).
+inline bool fuse_sequential(int mode) {
+    return mode == SAL_FUSE_LMS || mode == SAL_FUSE_NLMS || mode == SAL_FUSE_RLS;
+}
+// Workspace of the sequential rules: the index list of the masked points and the block counts.
+size_t seq_workspace_bytes(int64_t G, int64_t K);
+// W: K x 4 doubles; err2: K x cap floats or nullptr; count: K int64 or nullptr.
+sal_status launch_seq_adapt(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion& f,
+                            const float* D, const uint8_t* mask, double* W, float* err2, int64_t cap, int64_t* count,
+                            void* ws, hipStream_t stream);
+// S(v) = sum_m W_m S_m(g(v)) with the weights of each row's group (W: K x 4).
+sal_status launch_combine(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, int64_t sections, int64_t T,
+                          int64_t IL, int64_t XL, int s, const double* W, float* S, hipStream_t stream);
 // Writes R_m(g) = gS_m(g) / Q(g), the fusion adjoint divided by the number Q(g) of stencil
 // neighbours of g inside the grid (0 where Q(g) = 0): the per-point factor of every term of
 // the center-surround adjoint.
@@ -59,8 +72,8 @@ sal_status launch_fuse_adjoint(const float* Sm, int64_t Tg, int64_t ILg, int64_t
                                hipStream_t stream);
 sal_status launch_project_lowp(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s, int precision,
                                const Tables* tb, float* E, hipStream_t stream);
-sal_status launch_project_fp32(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s, const Tables* tb,
-                               float* E, hipStream_t stream);
+sal_status launch_project_fp32(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s, int feature,
+                               const Tables* tb, float* E, hipStream_t stream);
 
 // Batched (persistent) feature launches over many volumes of one window class.  The
 // per-volume kernel parameters are opaque blocks of *_param_bytes() bytes.

@@ -347,6 +347,11 @@ sal_status launch_fuse(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, co
                        f.mode == SAL_FUSE_ADAPT_LS ? ws + K * kFuseParts * kStats : nullptr);
     sal_status st = check_hip(hipGetLastError(), "launch k_fuse_solve");
     if (st) return st;
+    return launch_combine(Sm, Tg, ILg, XLg, sections, T, IL, XL, s, W, S, stream);
+}
+
+sal_status launch_combine(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, int64_t sections, int64_t T,
+                          int64_t IL, int64_t XL, int s, const double* W, float* S, hipStream_t stream) {
     if (T * IL * XL == 0) return SAL_OK;
     if (!wide_grid_fits(T * IL, 256)) return fail(SAL_ERR_SHAPE, "volume too large for one launch");
     if (XL % 4 == 0 && reinterpret_cast<uintptr_t>(S) % 16 == 0) {

@@ -103,7 +103,9 @@ constexpr int adj_waves_per_simd() {
     return Gm::SEP && Gm::ROWS * Gm::RX <= 40 ? (N <= 8 && S <= 2 ? 6 : 4) : 2;
 }
 
-template <int N, int S>
+// EN: the adjoint of the energy feature, Y = 2 c(k) F(k) with c(k) from the squared projection
+// weights (p.wts), instead of c(k) F(k) / |F(k)|.
+template <int N, int S, bool EN = false>
 __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_adjoint(AdjParams p) {
     using Gm = AdjGeom<N, S>;
     constexpr int CT = Gm::CT, KH = Gm::KH, NK = Gm::NK, RT = Gm::RT, RI = Gm::RI, RX = Gm::RX, RXp = Gm::RXp,
@@ -276,8 +278,8 @@ __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_
                     const float c1 = fmaf(ge[0], wa.x, fmaf(ge[1], wa.y, ge[2] * wa.z));
                     const float c2 = fmaf(ge[0], wb.x, fmaf(ge[1], wb.y, ge[2] * wb.z));
                     const float q1 = fmaf(re1, re1, im1 * im1), q2 = fmaf(re2, re2, im2 * im2);
-                    const float s1 = q1 > 0.f ? c1 * __builtin_amdgcn_rsqf(q1) : 0.f;
-                    const float s2 = q2 > 0.f ? c2 * __builtin_amdgcn_rsqf(q2) : 0.f;
+                    const float s1 = EN ? 2.f * c1 : (q1 > 0.f ? c1 * __builtin_amdgcn_rsqf(q1) : 0.f);
+                    const float s2 = EN ? 2.f * c2 : (q2 > 0.f ? c2 * __builtin_amdgcn_rsqf(q2) : 0.f);
                     const float y1r = s1 * re1, y1i = s1 * im1, y2r = s2 * re2, y2i = s2 * im2;
                     // packed inverse-DFT inputs: cos row gets Y(+q) + Y(-q), sin row i (Y(+q) - Y(-q))
                     y[4 * pr + 0] = sp ? y1r : y1r + y2r;   // real chain, cos row
@@ -343,8 +345,8 @@ __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_
                         const float c1 = fmaf(ge[0], wa.x, fmaf(ge[1], wa.y, ge[2] * wa.z));
                         const float c2 = fmaf(ge[0], wb.x, fmaf(ge[1], wb.y, ge[2] * wb.z));
                         const float q1 = fmaf(re1, re1, im1 * im1), q2 = fmaf(re2, re2, im2 * im2);
-                        const float s1 = q1 > 0.f ? c1 * __builtin_amdgcn_rsqf(q1) : 0.f;
-                        const float s2 = q2 > 0.f ? c2 * __builtin_amdgcn_rsqf(q2) : 0.f;
+                        const float s1 = EN ? 2.f * c1 : (q1 > 0.f ? c1 * __builtin_amdgcn_rsqf(q1) : 0.f);
+                        const float s2 = EN ? 2.f * c2 : (q2 > 0.f ? c2 * __builtin_amdgcn_rsqf(q2) : 0.f);
                         const float y1r = s1 * re1, y1i = s1 * im1, y2r = s2 * re2, y2i = s2 * im2;
                         y[4 * pr + 0] = sp ? y1r : y1r + y2r;
                         y[4 * pr + 1] = sp ? y2r : y2i - y1i;
@@ -662,21 +664,27 @@ static sal_status adj_layout_dispatch(int n, int s, int64_t T, int64_t IL, int64
     return fail(SAL_ERR_UNSUPPORTED, "adjoint built for n in {4, 8, 12, 16} and 1 <= s < n/2");
 }
 
-template <int N, int S>
+template <int N, int S, bool EN>
 static sal_status launch_adj(const AdjParams& p, const AdjLayout& L, hipStream_t stream) {
     static std::atomic<uint64_t> attr{0};
-    sal_status st = lds_limit_once((const void*)k_spectral_adjoint<N, S>, 160 * 1024, attr,
+    sal_status st = lds_limit_once((const void*)k_spectral_adjoint<N, S, EN>, 160 * 1024, attr,
                                    "hipFuncSetAttribute(adjoint)");
     if (st) return st;
     const int64_t grid = xcd_grid(L.ntiles);
     if (!wide_grid_fits(grid, 512)) return fail(SAL_ERR_SHAPE, "volume too large for one launch");
-    hipLaunchKernelGGL((k_spectral_adjoint<N, S>), wide_grid(grid, 512), dim3(512), L.lds, stream, p);
+    hipLaunchKernelGGL((k_spectral_adjoint<N, S, EN>), wide_grid(grid, 512), dim3(512), L.lds, stream, p);
     return check_hip(hipGetLastError(), "launch k_spectral_adjoint");
 }
 
-static sal_status launch_adj_dispatch(int n, int s, const AdjParams& p, const AdjLayout& L, hipStream_t stream) {
+template <int N, int S>
+static sal_status launch_adj_feature(bool energy, const AdjParams& p, const AdjLayout& L, hipStream_t stream) {
+    return energy ? launch_adj<N, S, true>(p, L, stream) : launch_adj<N, S, false>(p, L, stream);
+}
+
+static sal_status launch_adj_dispatch(int n, int s, bool energy, const AdjParams& p, const AdjLayout& L,
+                                      hipStream_t stream) {
 #define SAL_ADJ_CASE(NN, SS) \
-    if (n == NN && s == SS) return launch_adj<NN, SS>(p, L, stream);
+    if (n == NN && s == SS) return launch_adj_feature<NN, SS>(energy, p, L, stream);
     SAL_ADJ_CASE(4, 1)
     SAL_ADJ_CASE(8, 1) SAL_ADJ_CASE(8, 2) SAL_ADJ_CASE(8, 3)
     SAL_ADJ_CASE(12, 1) SAL_ADJ_CASE(12, 2) SAL_ADJ_CASE(12, 3) SAL_ADJ_CASE(12, 4) SAL_ADJ_CASE(12, 5)
@@ -732,6 +740,9 @@ sal_status sal_backward(const float* V, int64_t T, int64_t IL, int64_t XL, const
     if (spec->precision != SAL_PREC_FP32) return fail(SAL_ERR_UNSUPPORTED, "the adjoint runs in fp32 only");
     if (!V || !E || !Sm || !W || !gS || !gV_out) return fail(SAL_ERR_ARG, "NULL buffer");
     if (!fusion) return fail(SAL_ERR_ARG, "fusion is NULL");
+    if (fuse_sequential(fusion->mode))
+        return fail(SAL_ERR_UNSUPPORTED, "the adjoint of the LMS / NLMS / RLS recursions is not built (fix their "
+                                         "weights with SAL_FUSE_FIXED to differentiate the rest of the path)");
     if (fusion->mode != SAL_FUSE_EQUAL && fusion->mode != SAL_FUSE_FIXED && fusion->mode != SAL_FUSE_ADAPT_LS)
         return fail(SAL_ERR_ARG, "unknown fusion mode");
     if (fusion->mode == SAL_FUSE_ADAPT_LS && (!D || !(fusion->delta >= 0.0)))
@@ -768,9 +779,10 @@ sal_status sal_backward(const float* V, int64_t T, int64_t IL, int64_t XL, const
     p.passA = tb->passA;
     p.mat = tb->mat;
     p.inv = tb->inv;
-    p.wts = (const float4*)tb->wts;
+    const bool energy = spec->feature == SAL_FEATURE_ENERGY;
+    p.wts = (const float4*)(energy ? tb->wts_e : tb->wts);
     p.part = part;
-    if ((st = launch_adj_dispatch(spec->n, s, p, L, stream))) return st;
+    if ((st = launch_adj_dispatch(spec->n, s, energy, p, L, stream))) return st;
 
     GatherParams gp;
     gp.part = part;

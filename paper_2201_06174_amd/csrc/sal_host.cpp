@@ -38,6 +38,10 @@ sal_status check_spec(const sal_spec* spec, int64_t T, int64_t IL, int64_t XL) {
     if (spec->window != SAL_WINDOW_HANN && spec->window != SAL_WINDOW_RECT) return fail(SAL_ERR_ARG, "unknown window");
     if (spec->precision != SAL_PREC_FP32 && spec->precision != SAL_PREC_SPLIT_BF16 && spec->precision != SAL_PREC_FP16)
         return fail(SAL_ERR_ARG, "unknown precision");
+    if (spec->feature != SAL_FEATURE_MAGNITUDE && spec->feature != SAL_FEATURE_ENERGY)
+        return fail(SAL_ERR_ARG, "unknown feature");
+    if (spec->feature == SAL_FEATURE_ENERGY && spec->precision != SAL_PREC_FP32)
+        return fail(SAL_ERR_UNSUPPORTED, "the energy feature is built for the fp32 path only");
     if (T < n / 2 || IL < n / 2 || XL < n / 2)
         return fail(SAL_ERR_SHAPE, "every volume axis must hold at least n/2 voxels (single reflection at borders)");
     if (T > (int64_t(1) << 31) || IL > (int64_t(1) << 31) || XL > (int64_t(1) << 31))
@@ -99,7 +103,7 @@ static uint16_t to_f16(float f) {
 // not be inside a stream capture).
 constexpr int kSides[4] = {4, 8, 12, 16};
 constexpr int kTableSlots = 4 * 2;                  // (n, window)
-constexpr size_t kTableSlotBytes = 128 * 1024;      // 122,880 B at n = 16
+constexpr size_t kTableSlotBytes = 160 * 1024;      // 159,744 B at n = 16
 constexpr int kStridesPerWindow = 1 + 3 + 5 + 7;    // 1 <= s < n/2 for n = 4, 8, 12, 16
 constexpr int kPassASlots = kStridesPerWindow * 2;  // (n, s, window)
 constexpr size_t kPassASlotBytes = 27648;           // (n/2 + 1) x 3 x 16 x 32 x 2 B at n = 16
@@ -123,7 +127,7 @@ static int pass_a_slot(int n, int s, int window) {
 static std::vector<unsigned char> build_table_slot(int n, int window, Tables* t) {
     const int KH = n / 2 + 1;
     std::vector<float> passA(size_t(KH) * n * 2), mat(16 * size_t(n)), wts(size_t(KH) * n * 16 * 4, 0.f),
-        inv(16 * 16, 0.f);
+        wts_e(size_t(KH) * n * 16 * 4, 0.f), inv(16 * 16, 0.f);
     for (int k = 0; k < KH; k++)
         for (int a = 0; a < n; a++) {
             double h = taper(a, n, window);
@@ -159,6 +163,11 @@ static std::vector<unsigned char> build_table_slot(int n, int window, Tables* t)
                 w[0] = float(mult * std::sqrt(ki * ki + double(kx) * kx) / kn / n3);
                 w[1] = float(mult * std::sqrt(kt * kt + ki * ki) / kn / n3);
                 w[2] = float(mult * std::sqrt(kt * kt + double(kx) * kx) / kn / n3);
+                // energy: the squared projection weights alpha_m^2 = P_m^2 / |k|^2
+                float* we = &wts_e[((size_t(kx) * n + u) * 16 + r) * 4];
+                we[0] = float(mult * (ki * ki + double(kx) * kx) / k2 / n3);
+                we[1] = float(mult * (kt * kt + ki * ki) / k2 / n3);
+                we[2] = float(mult * (kt * kt + double(kx) * kx) / k2 / n3);
             }
         }
     }
@@ -219,7 +228,8 @@ static std::vector<unsigned char> build_table_slot(int n, int window, Tables* t)
         off += (nb + 255) / 256 * 256;  // keep every table 256-byte aligned
         return at;
     };
-    size_t o[9];
+    size_t o[10];
+    o[9] = 0;
     o[0] = put(passA.data(), passA.size() * 4);
     o[1] = put(mat.data(), mat.size() * 4);
     o[2] = put(wts.data(), wts.size() * 4);
@@ -229,6 +239,7 @@ static std::vector<unsigned char> build_table_slot(int n, int window, Tables* t)
     o[6] = put(chi.data(), chi.size() * 2);
     o[7] = put(clo.data(), clo.size() * 2);
     o[8] = put(ch16.data(), ch16.size() * 2);
+    o[9] = put(wts_e.data(), wts_e.size() * 4);
     for (size_t v : o)
         if (v == SIZE_MAX) return {};  // cannot happen for n <= 16 (the slot is sized for n = 16)
     t->n = n;
@@ -243,6 +254,7 @@ static std::vector<unsigned char> build_table_slot(int n, int window, Tables* t)
     t->cpx_hi = (const uint16_t*)o[6];
     t->cpx_lo = (const uint16_t*)o[7];
     t->cpx_h16 = (const uint16_t*)o[8];
+    t->wts_e = (const float*)o[9];
     return img;
 }
 
@@ -309,6 +321,7 @@ static sal_status init_device_tables(int dev) {
             t.cpx_hi = (const uint16_t*)(b + (size_t)t.cpx_hi);
             t.cpx_lo = (const uint16_t*)(b + (size_t)t.cpx_lo);
             t.cpx_h16 = (const uint16_t*)(b + (size_t)t.cpx_h16);
+            t.wts_e = (const float*)(b + (size_t)t.wts_e);
             d.t[slot] = t;
         }
     std::vector<uint16_t> pimg(size_t(kPassASlots) * kPassASlotBytes / 2);

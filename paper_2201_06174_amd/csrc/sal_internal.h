@@ -49,6 +49,7 @@ struct Tables {
     const float* passA = nullptr;   // [KH][n][2]: h(a) cos(2 pi k a/n), -h(a) sin(2 pi k a/n)
     const float* mat = nullptr;     // [16][n]: packed taper*DFT rows c0, c_{n/2}, c1, s1, c2, s2, ...
     const float* wts = nullptr;     // [KH][n][16][4]: bin weights mult(kx) alpha_m / n^3 per packed row
+    const float* wts_e = nullptr;   // the same with alpha_m^2 (energy feature)
     const float* inv = nullptr;     // [16 a][16 r]: h(a) * trig row r at sample a (transpose of `mat`), zero padded
     const float* wts_nat = nullptr; // [KH][n][16][4]: bin weights for natural-order rows (row r = bin r)
     const float* wts_nat_h = nullptr; // the same, with ki slots (n/2, n) of the planes kx = 0, n/2 folded into

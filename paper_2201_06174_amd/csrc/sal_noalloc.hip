@@ -58,6 +58,9 @@ sal_status sal_fuse_noalloc(const float* Sm, int64_t Tg, int64_t ILg, int64_t XL
     if (s < 1) return fail(SAL_ERR_ARG, "stride must be >= 1");
     if (ceil_div(T, s) != Tg || ceil_div(IL, s) != ILg || ceil_div(XL, s) != XLg)
         return fail(SAL_ERR_SHAPE, "grid extents must equal ceil(N / s) of the volume extents");
+    if (fuse_sequential(fusion->mode))
+        return fail(SAL_ERR_UNSUPPORTED, "sal_fuse_noalloc: the LMS / NLMS / RLS rules need a workspace of the grid's "
+                                         "size (use sal_fuse)");
     const int64_t K = fuse_groups(fusion->sections, ILg);
     if (fusion->mode == SAL_FUSE_ADAPT_LS && fuse_workspace_bytes(K) > sal_fuse_noalloc_max_bytes())
         return fail(SAL_ERR_NOMEM, "sal_fuse_noalloc: " + std::to_string(K) + " weight groups need " +

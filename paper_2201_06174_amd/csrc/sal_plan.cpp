@@ -247,6 +247,11 @@ sal_status sal_plan_create(const sal_batch_item* items, int64_t count, uint32_t 
             return fail(st, "member " + std::to_string(i) + ": " + sal_last_error());
         if ((st = check_fusion_args(&it.fusion, it.D)))
             return fail(st, "member " + std::to_string(i) + ": " + sal_last_error());
+        if (it.spec.feature != SAL_FEATURE_MAGNITUDE)
+            return fail(SAL_ERR_UNSUPPORTED, "member " + std::to_string(i) + ": the energy feature is not batched");
+        if (fuse_sequential(it.fusion.mode))
+            return fail(SAL_ERR_UNSUPPORTED, "member " + std::to_string(i) +
+                                                 ": the LMS / NLMS / RLS rules are not batched (use sal_fuse)");
         if (it.fusion.sections != 0)
             return fail(SAL_ERR_UNSUPPORTED, "member " + std::to_string(i) +
                                                  ": sectioned re-adaptation is not batched (use sal_fuse)");

@@ -69,7 +69,9 @@ constexpr bool fp32_prefetch() {
 // region is already in LDS; with `has_next` the region of tile `next` (of the volume pn, of
 // the same window class and tile depth) is fetched into LDS during the last kx step
 // (fp32_prefetch instances).
-template <int N, int S, int CTW>
+// EN: the energy feature, |F|^2 against the squared projection weights (p.wts then holds
+// mult(kx) alpha_m^2 / n^3), instead of |F|.
+template <int N, int S, int CTW, bool EN = false>
 __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int64_t tile, float* lds,
                                                   bool staged = false, bool has_next = false, int64_t next = 0,
                                                   const ProjParams* pn = nullptr) {
@@ -263,8 +265,9 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
                     const float Ca = dr[2 * pr], Sb = dr[2 * pr + 1], Cai = di[2 * pr], Sbi = di[2 * pr + 1];
                     const float re1 = sp ? Ca : Ca + Sbi, im1 = sp ? Cai : Cai - Sb;
                     const float re2 = sp ? Sb : Ca - Sbi, im2 = sp ? Sbi : Cai + Sb;
-                    const float m1 = __builtin_amdgcn_sqrtf(fmaf(re1, re1, im1 * im1));
-                    const float m2 = __builtin_amdgcn_sqrtf(fmaf(re2, re2, im2 * im2));
+                    const float q1 = fmaf(re1, re1, im1 * im1), q2 = fmaf(re2, re2, im2 * im2);
+                    const float m1 = EN ? q1 : __builtin_amdgcn_sqrtf(q1);
+                    const float m2 = EN ? q2 : __builtin_amdgcn_sqrtf(q2);
                     const float4 wa = pr ? w2 : w0, wb = pr ? w3 : w1;
                     acc[0][0] = fmaf(wa.x, m1, fmaf(wb.x, m2, acc[0][0]));
                     acc[0][1] = fmaf(wa.y, m1, fmaf(wb.y, m2, acc[0][1]));
@@ -329,8 +332,9 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
                         const float Ca = dr[2 * pr], Sb = dr[2 * pr + 1], Cai = di[2 * pr], Sbi = di[2 * pr + 1];
                         const float re1 = sp ? Ca : Ca + Sbi, im1 = sp ? Cai : Cai - Sb;
                         const float re2 = sp ? Sb : Ca - Sbi, im2 = sp ? Sbi : Cai + Sb;
-                        const float m1 = __builtin_amdgcn_sqrtf(fmaf(re1, re1, im1 * im1));
-                        const float m2 = __builtin_amdgcn_sqrtf(fmaf(re2, re2, im2 * im2));
+                        const float q1 = fmaf(re1, re1, im1 * im1), q2 = fmaf(re2, re2, im2 * im2);
+                        const float m1 = EN ? q1 : __builtin_amdgcn_sqrtf(q1);
+                        const float m2 = EN ? q2 : __builtin_amdgcn_sqrtf(q2);
                         const float4 wa = pr ? w2 : w0, wb = pr ? w3 : w1;
                         acc[c][0] = fmaf(wa.x, m1, fmaf(wb.x, m2, acc[c][0]));
                         acc[c][1] = fmaf(wa.y, m1, fmaf(wb.y, m2, acc[c][1]));
@@ -441,7 +445,7 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
 template <int N>
 constexpr int fp32_waves_per_simd() { return N == 8 ? 8 : 4; }
 
-template <int N, int S, int CTW>
+template <int N, int S, int CTW, bool EN = false>
 __global__ __launch_bounds__(kNT, (fp32_waves_per_simd<N>())) void k_project_fp32(ProjParams p) {
     extern __shared__ float lds[];
     if constexpr (fp32_prefetch<N, S, CTW>()) {
@@ -450,12 +454,12 @@ __global__ __launch_bounds__(kNT, (fp32_waves_per_simd<N>())) void k_project_fp3
         const int64_t per = (p.ntiles + 7) / 8, stride = gridDim.x / 8;
         const int64_t lo = (int64_t)(blockIdx.x % 8) * per, hi = lo + per < p.ntiles ? lo + per : p.ntiles;
         for (int64_t g = lo + blockIdx.x / 8; g < hi; g += stride)
-            project_tile_fp32<N, S, CTW>(p, g, lds, g != lo + blockIdx.x / 8, g + stride < hi, g + stride);
+            project_tile_fp32<N, S, CTW, EN>(p, g, lds, g != lo + blockIdx.x / 8, g + stride < hi, g + stride);
         return;
     }
     const int64_t tile = xcd_block(p.ntiles);
     if (tile >= p.ntiles) return;
-    project_tile_fp32<N, S, CTW>(p, tile, lds);
+    project_tile_fp32<N, S, CTW, EN>(p, tile, lds);
 }
 
 // Persistent form over the concatenated tiles of many volumes of one window
@@ -606,10 +610,10 @@ static sal_status set_lds_attr(K kernel, const char* what) {
         default: return fail(SAL_ERR_UNSUPPORTED, "window side not built"); \
     }
 
-template <int N, int S, int CTW>
+template <int N, int S, int CTW, bool EN>
 static sal_status launch_project(const ProjParams& p, size_t lds, hipStream_t stream) {
     static std::atomic<uint64_t> attr{0};
-    sal_status st = lds_limit_once((const void*)k_project_fp32<N, S, CTW>, (int)kLdsMax, attr,
+    sal_status st = lds_limit_once((const void*)k_project_fp32<N, S, CTW, EN>, (int)kLdsMax, attr,
                                    "hipFuncSetAttribute(project)");
     if (st) return st;
     int64_t grid = xcd_grid(p.ntiles);
@@ -620,25 +624,32 @@ static sal_status launch_project(const ProjParams& p, size_t lds, hipStream_t st
         if ((st = check_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev),
                             "hipDeviceGetAttribute")))
             return st;
-        if ((st = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_project_fp32<N, S, CTW>, kNT, lds),
+        if ((st = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_project_fp32<N, S, CTW, EN>, kNT,
+                                                                         lds),
                             "hipOccupancyMaxActiveBlocksPerMultiprocessor")))
             return st;
         grid = std::min<int64_t>(grid, std::max<int64_t>(8, (int64_t)cus * std::max(per_cu, 1) / 8 * 8));
     }
     if (!wide_grid_fits(grid, kNT)) return fail(SAL_ERR_SHAPE, "volume too large for one launch");
-    hipLaunchKernelGGL((k_project_fp32<N, S, CTW>), wide_grid(grid, kNT), dim3(kNT), lds, stream, p);
+    hipLaunchKernelGGL((k_project_fp32<N, S, CTW, EN>), wide_grid(grid, kNT), dim3(kNT), lds, stream, p);
     return check_hip(hipGetLastError(), "launch k_project_fp32");
 }
 
-sal_status launch_project_fp32(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s, const Tables* tb,
-                               float* E, hipStream_t stream) {
+sal_status launch_project_fp32(const float* V, int64_t T, int64_t IL, int64_t XL, int n, int s, int feature,
+                               const Tables* tb, float* E, hipStream_t stream) {
     ProjParams p;
     int64_t nt = 0;
     size_t lds = 0;
     sal_status st = project_fp32_params(n, s, 0, V, T, IL, XL, tb, E, &p, &nt, &lds);
     if (st) return st;
     if (nt == 0) return SAL_OK;
-#define CALL(NN, SS, CC) launch_project<NN, SS, CC>(p, lds, stream)
+    if (feature == SAL_FEATURE_ENERGY) {
+        p.wts = (const float4*)tb->wts_e;
+#define CALL(NN, SS, CC) launch_project<NN, SS, CC, true>(p, lds, stream)
+        SAL_FP32_DISPATCH(CALL)
+#undef CALL
+    }
+#define CALL(NN, SS, CC) launch_project<NN, SS, CC, false>(p, lds, stream)
     SAL_FP32_DISPATCH(CALL)
 #undef CALL
 }

@@ -194,3 +194,40 @@ def test_plan_status_arguments():
     lib = _lib.load()
     c, f = ctypes.c_int64(), ctypes.c_int64()
     assert _err(lib.sal_plan_status(None, None, ctypes.byref(c), ctypes.byref(f))) == "SAL_ERR_ARG"
+
+
+def test_sequential_fusion_validation():
+    lib = _lib.load()
+    p = ctypes.c_void_p(64)
+    ws = 1 << 24
+
+    def fuse(f, D=p):
+        return _err(lib.sal_fuse(p, 4, 4, 4, f, D, None, 8, 8, 8, 2, p, p, p, ws, None))
+    assert fuse(_lib.make_fusion("nlms", mu=0.5), None) == "SAL_ERR_ARG"     # no desired map
+    assert fuse(_lib.make_fusion("lms", mu=0.0)) == "SAL_ERR_ARG"            # no step
+    assert fuse(_lib.make_fusion("nlms", mu=0.5, eps=-1.0)) == "SAL_ERR_ARG"
+    assert fuse(_lib.make_fusion("rls", delta=1.0, lam=1.5)) == "SAL_ERR_ARG"  # forgetting factor above 1
+    assert fuse(_lib.make_fusion("rls", delta=0.0)) == "SAL_ERR_ARG"          # P0 undefined
+    assert fuse(_lib.make_fusion("nlms", mu=0.5, passes=0)) == "SAL_ERR_ARG"
+    f = _lib.make_fusion("nlms", mu=0.5)
+    # the workspace holds the index list of the grid's points
+    assert lib.sal_fuse_workspace_size(4, 4, 4, f) >= 4 * 64
+    assert _err(lib.sal_fuse(p, 4, 4, 4, f, p, None, 8, 8, 8, 2, p, p, p, 16, None)) == "SAL_ERR_NOMEM"
+    assert _err(lib.sal_adapt_weights(p, 4, 4, 4, _lib.make_fusion("adapt_ls"), p, None, p, None, 0, None, p, ws,
+                                      None)) == "SAL_ERR_ARG"
+    assert _err(lib.sal_adapt_weights(p, 4, 4, 4, f, p, None, p, None, 5, None, p, ws, None)) == "SAL_ERR_ARG"
+    # not taken by the adjoint, the no-allocation fusion and the plans
+    sp = _lib.SalSpec(8, 1, 0, 0)
+    st, keep = _lib.make_stencil([[1, 0, 0], [-1, 0, 0]])
+    assert _err(lib.sal_backward(p, 8, 8, 8, sp, st, f, p, p, p, p, None, p, p, p, ws, None)) == "SAL_ERR_UNSUPPORTED"
+    assert _err(lib.sal_fuse_noalloc(p, 4, 4, 4, f, p, None, 8, 8, 8, 2, p, p, None)) == "SAL_ERR_UNSUPPORTED"
+
+
+def test_energy_feature_validation():
+    lib = _lib.load()
+    for prec, code in ((1, "SAL_ERR_UNSUPPORTED"), (2, "SAL_ERR_UNSUPPORTED")):
+        sp = _lib.SalSpec(8, 1, 0, prec, 1)
+        rc = lib.sal_project(ctypes.c_void_p(16), 32, 32, 32, sp, ctypes.c_void_p(16), None)
+        assert _err(rc) == code
+    sp = _lib.SalSpec(8, 1, 0, 0, 7)
+    assert _err(lib.sal_project(ctypes.c_void_p(16), 32, 32, 32, sp, ctypes.c_void_p(16), None)) == "SAL_ERR_ARG"

@@ -403,6 +403,85 @@ def test_sections_recover_their_own_weights():
     assert np.all(We == 1 / 3)
 
 
+def _stationary(seed, shape=(6, 9, 7), noise=0.0):
+    rng = _rng(seed)
+    Sm = rng.uniform(0.2, 1.5, size=(3,) + shape)
+    Wt = np.array([0.7, -0.4, 1.1])
+    D = (np.einsum("m...,m->...", Sm, Wt) + noise * rng.standard_normal(shape)).astype(np.float32)
+    return Sm, D, Wt
+
+
+def test_rls_unit_forgetting_is_the_regularised_least_squares():
+    """RLS with lambda = 1 and P0 = I / delta solves sum (D - w.u)^2 + delta |w - w0|^2 after
+    one pass: with w0 = 0 that is the ADAPT_LS weights (G + delta I)^-1 p, and in general
+    (G + delta I)^-1 (p + delta w0) (a library solve)."""
+    Sm, D, _ = _stationary(61, noise=0.1)
+    mask = (_rng(62).uniform(size=D.shape) < 0.7).astype(np.uint8)
+    for delta in (1e-3, 0.5):
+        W, cnt, _ = orc.adapt_sequential(Sm, D, mask, "rls", lam=1.0, delta=delta, w0=(0.0, 0.0, 0.0))
+        Wls, fb, st = orc.fusion_weights(Sm, D, mask, "adapt_ls", delta=delta)
+        assert cnt[0] == mask.sum() and fb == 0
+        assert np.max(np.abs(W[0] - Wls)) < 1e-9 * np.abs(Wls).max()
+        w0 = np.array([0.3, 0.2, -0.1])
+        W2, _, _ = orc.adapt_sequential(Sm, D, mask, "rls", lam=1.0, delta=delta, w0=w0)
+        U = Sm.reshape(3, -1).T[mask.reshape(-1) == 1]
+        d = D.reshape(-1)[mask.reshape(-1) == 1].astype(np.float64)
+        ref = np.linalg.solve(U.T @ U + delta * np.eye(3), U.T @ d + delta * w0)
+        assert np.max(np.abs(W2[0] - ref)) < 1e-9 * np.abs(ref).max()
+
+
+def test_lms_and_nlms_converge_to_the_weights_of_a_noise_free_map():
+    """On D = W* . u exactly, LMS (step below 2 / largest eigenvalue of the input
+    correlation) and NLMS converge to W*; with noise, NLMS with a small step settles near
+    the least-squares weights (its fixed point in the mean)."""
+    Sm, D, Wt = _stationary(63)
+    W, _, err = orc.adapt_sequential(Sm, D, None, "lms", mu=0.2, passes=400, cap=D.size * 400)
+    assert np.max(np.abs(W[0] - Wt)) < 1e-6
+    Wn, _, errn = orc.adapt_sequential(Sm, D, None, "nlms", mu=0.5, passes=200, cap=D.size * 200)
+    assert np.max(np.abs(Wn[0] - Wt)) < 1e-6
+    # the learning curve falls: squared a priori errors of the last sweep far below the first
+    for e in (err[0], errn[0]):
+        assert e[-D.size:].mean() < 1e-6 * e[:D.size].mean()
+    Sm2, D2, _ = _stationary(64, shape=(8, 10, 9), noise=0.05)
+    Wls, _, _ = orc.fusion_weights(Sm2, D2, None, "adapt_ls")
+    Wn2, _, _ = orc.adapt_sequential(Sm2, D2, None, "nlms", mu=0.01, passes=300)
+    assert np.max(np.abs(Wn2[0] - Wls)) < 2e-2 * np.abs(Wls).max()
+
+
+def test_sequential_first_updates_by_hand():
+    """One masked sample, worked by hand: e = D - w0.u; LMS w = w0 + mu e u; NLMS
+    w = w0 + mu e u / (eps + u.u); RLS k = P0 u / (lambda + u.P0 u), w = w0 + k e."""
+    Sm = np.zeros((3, 2, 3, 2))
+    Sm[:, 1, 2, 0] = [0.5, 2.0, -1.0]
+    D = np.zeros((2, 3, 2), np.float32)
+    D[1, 2, 0] = 1.5
+    mask = np.zeros((2, 3, 2), np.uint8)
+    mask[1, 2, 0] = 1
+    u, w0 = np.array([0.5, 2.0, -1.0]), np.array([0.1, 0.2, 0.3])
+    e = 1.5 - w0 @ u
+    W, cnt, err = orc.adapt_sequential(Sm, D, mask, "lms", mu=0.1, w0=w0, cap=4)
+    assert cnt[0] == 1 and abs(err[0, 0] - e * e) < 1e-15
+    assert np.allclose(W[0], w0 + 0.1 * e * u, rtol=0, atol=1e-15)
+    W, _, _ = orc.adapt_sequential(Sm, D, mask, "nlms", mu=0.5, eps=0.25, w0=w0)
+    assert np.allclose(W[0], w0 + 0.5 * e * u / (0.25 + u @ u), rtol=0, atol=1e-15)
+    W, _, _ = orc.adapt_sequential(Sm, D, mask, "rls", lam=0.9, delta=2.0, w0=w0)
+    k = (u / 2.0) / (0.9 + u @ u / 2.0)
+    assert np.allclose(W[0], w0 + k * e, rtol=0, atol=1e-15)
+
+
+def test_sequential_sections_adapt_each_group_on_its_own():
+    """With re-adaptation every N sections each group runs its own recursion from w0: a
+    group's weights equal those of the same recursion on a mask holding that group only."""
+    Sm, D, _ = _stationary(65, shape=(4, 9, 5), noise=0.2)
+    W, cnt, _ = orc.adapt_sequential(Sm, D, None, "nlms", mu=0.3, passes=3, sections=4)
+    assert W.shape == (3, 3) and list(cnt) == [80, 80, 20]
+    for k, (lo, hi) in enumerate(((0, 4), (4, 8), (8, 9))):
+        m = np.zeros(D.shape, np.uint8)
+        m[:, lo:hi, :] = 1
+        Wk, _, _ = orc.adapt_sequential(Sm, D, m, "nlms", mu=0.3, passes=3)
+        assert np.array_equal(W[k], Wk[0])
+
+
 @pytest.mark.parametrize("s,N", [(1, 2), (2, 1), (3, 2)])
 def test_combine_sections_by_search(s, N):
     """Each voxel takes the weights of its nearest centre's group of N inline sections."""
