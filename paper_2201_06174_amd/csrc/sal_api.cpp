@@ -161,7 +161,7 @@ using namespace sal;
 
 extern "C" {
 
-sal_status sal_local_spectra(const float* V, int64_t T, int64_t IL, int64_t XL, const sal_spec* spec,
+static sal_status sal_local_spectra_body(const float* V, int64_t T, int64_t IL, int64_t XL, const sal_spec* spec,
                              const int32_t* centers, int64_t cnt, float* F_out, sal_stream stream) {
     if (!spec) return fail(SAL_ERR_ARG, "spec is NULL");
     sal_spec sp = *spec;
@@ -175,7 +175,13 @@ sal_status sal_local_spectra(const float* V, int64_t T, int64_t IL, int64_t XL, 
     return launch_local_spectra(V, T, IL, XL, sp.n, sp.window, centers, cnt, F_out, (hipStream_t)stream);
 }
 
-sal_status sal_project(const float* V, int64_t T, int64_t IL, int64_t XL, const sal_spec* spec, float* E_out,
+sal_status sal_local_spectra(const float* V, int64_t T, int64_t IL, int64_t XL, const sal_spec* spec,
+                             const int32_t* centers, int64_t cnt, float* F_out, sal_stream stream) {
+    CallScope cs("sal_local_spectra");
+    return cs.done(sal_local_spectra_body(V, T, IL, XL, spec, centers, cnt, F_out, stream));
+}
+
+static sal_status sal_project_body(const float* V, int64_t T, int64_t IL, int64_t XL, const sal_spec* spec, float* E_out,
                        sal_stream stream) {
     sal_status st = check_spec(spec, T, IL, XL);
     if (st) return st;
@@ -191,7 +197,13 @@ sal_status sal_project(const float* V, int64_t T, int64_t IL, int64_t XL, const 
     }
 }
 
-sal_status sal_center_surround(const float* E, int64_t Tg, int64_t ILg, int64_t XLg, int32_t s,
+sal_status sal_project(const float* V, int64_t T, int64_t IL, int64_t XL, const sal_spec* spec, float* E_out,
+                       sal_stream stream) {
+    CallScope cs("sal_project");
+    return cs.done(sal_project_body(V, T, IL, XL, spec, E_out, stream));
+}
+
+static sal_status sal_center_surround_body(const float* E, int64_t Tg, int64_t ILg, int64_t XLg, int32_t s,
                                const sal_stencil* stencil, float* Sm_out, sal_stream stream) {
     if (!E || !Sm_out) return fail(SAL_ERR_ARG, "NULL buffer");
     if (E == Sm_out) return fail(SAL_ERR_ARG, "Sm_out must not alias E");
@@ -200,6 +212,12 @@ sal_status sal_center_surround(const float* E, int64_t Tg, int64_t ILg, int64_t 
     sal_status st = make_stencil(stencil, s, &ds);
     if (st) return st;
     return launch_dcs(E, Sm_out, Tg, ILg, XLg, ds, (hipStream_t)stream);
+}
+
+sal_status sal_center_surround(const float* E, int64_t Tg, int64_t ILg, int64_t XLg, int32_t s,
+                               const sal_stencil* stencil, float* Sm_out, sal_stream stream) {
+    CallScope cs("sal_center_surround");
+    return cs.done(sal_center_surround_body(E, Tg, ILg, XLg, s, stencil, Sm_out, stream));
 }
 
 int64_t sal_fuse_groups(const sal_fusion* fusion, int64_t ILg) {
@@ -240,7 +258,7 @@ sal_status sal_line_template(const int32_t* dir, int32_t length, double sigma, i
     return SAL_OK;
 }
 
-sal_status sal_fuse(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion* fusion, const float* D,
+static sal_status sal_fuse_body(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion* fusion, const float* D,
                     const uint8_t* mask, int64_t T, int64_t IL, int64_t XL, int32_t s, double* W_out, float* S_out,
                     void* ws, size_t ws_bytes, sal_stream stream) {
     sal_status st = check_fusion(fusion, D);
@@ -263,7 +281,14 @@ sal_status sal_fuse(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const
                        (hipStream_t)stream);
 }
 
-sal_status sal_adapt_weights(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion* fusion,
+sal_status sal_fuse(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion* fusion, const float* D,
+                    const uint8_t* mask, int64_t T, int64_t IL, int64_t XL, int32_t s, double* W_out, float* S_out,
+                    void* ws, size_t ws_bytes, sal_stream stream) {
+    CallScope cs("sal_fuse");
+    return cs.done(sal_fuse_body(Sm, Tg, ILg, XLg, fusion, D, mask, T, IL, XL, s, W_out, S_out, ws, ws_bytes, stream));
+}
+
+static sal_status sal_adapt_weights_body(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion* fusion,
                              const float* D, const uint8_t* mask, double* W_out, float* err2_out, int64_t cap,
                              int64_t* count_out, void* ws, size_t ws_bytes, sal_stream stream) {
     sal_status st = check_fusion(fusion, D);
@@ -276,6 +301,13 @@ sal_status sal_adapt_weights(const float* Sm, int64_t Tg, int64_t ILg, int64_t X
         return fail(SAL_ERR_NOMEM, "workspace smaller than sal_fuse_workspace_size()");
     return launch_seq_adapt(Sm, Tg, ILg, XLg, *fusion, D, mask, W_out, cap > 0 ? err2_out : nullptr, cap, count_out,
                             ws, (hipStream_t)stream);
+}
+
+sal_status sal_adapt_weights(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion* fusion,
+                             const float* D, const uint8_t* mask, double* W_out, float* err2_out, int64_t cap,
+                             int64_t* count_out, void* ws, size_t ws_bytes, sal_stream stream) {
+    CallScope cs("sal_adapt_weights");
+    return cs.done(sal_adapt_weights_body(Sm, Tg, ILg, XLg, fusion, D, mask, W_out, err2_out, cap, count_out, ws, ws_bytes, stream));
 }
 
 }  // extern "C"

@@ -730,7 +730,7 @@ size_t sal_backward_workspace_size(int64_t T, int64_t IL, int64_t XL, const sal_
     return bwd_ws(G, L, K).total;
 }
 
-sal_status sal_backward(const float* V, int64_t T, int64_t IL, int64_t XL, const sal_spec* spec,
+static sal_status sal_backward_body(const float* V, int64_t T, int64_t IL, int64_t XL, const sal_spec* spec,
                         const sal_stencil* stencil, const sal_fusion* fusion, const float* E, const float* Sm,
                         const double* W, const float* D, const uint8_t* mask, const float* gS, float* gV_out,
                         void* ws, size_t ws_bytes, sal_stream stream_) {
@@ -805,6 +805,14 @@ sal_status sal_backward(const float* V, int64_t T, int64_t IL, int64_t XL, const
     else
         hipLaunchKernelGGL(k_gather<int64_t>, grid, block, 0, stream, gp);
     return check_hip(hipGetLastError(), "launch k_gather");
+}
+
+sal_status sal_backward(const float* V, int64_t T, int64_t IL, int64_t XL, const sal_spec* spec,
+                        const sal_stencil* stencil, const sal_fusion* fusion, const float* E, const float* Sm,
+                        const double* W, const float* D, const uint8_t* mask, const float* gS, float* gV_out,
+                        void* ws, size_t ws_bytes, sal_stream stream_) {
+    CallScope cs("sal_backward");
+    return cs.done(sal_backward_body(V, T, IL, XL, spec, stencil, fusion, E, Sm, W, D, mask, gS, gV_out, ws, ws_bytes, stream_));
 }
 
 }  // extern "C"

@@ -1,7 +1,10 @@
 // sal_host.cpp -- error state, argument checks and the constant tables of libsal.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <atomic>
+#include <cstdio>
+#include <cstdlib>
 #include <climits>
 #include <cmath>
 #include <cstdint>
@@ -26,6 +29,29 @@ sal_status fail(sal_status code, const std::string& msg) {
 sal_status check_hip(hipError_t e, const char* what) {
     if (e == hipSuccess) return SAL_OK;
     return fail(SAL_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static bool log_enabled() {
+    static const bool on = [] {
+        const char* v = std::getenv("SAL_LOG");
+        return v && *v && std::strcmp(v, "0") != 0;
+    }();
+    return on;
+}
+
+CallScope::CallScope(const char* name) : name_(name) { roctxRangePushA(name); }
+
+CallScope::~CallScope() { roctxRangePop(); }
+
+sal_status CallScope::done(sal_status st) {
+    if (log_enabled()) {
+        static const char* names[] = {"SAL_OK", "SAL_ERR_ARG", "SAL_ERR_SHAPE", "SAL_ERR_UNSUPPORTED",
+                                      "SAL_ERR_NOMEM", "SAL_ERR_DEVICE", "SAL_ERR_STATE"};
+        const char* sn = (int)st >= 0 && (int)st < 7 ? names[(int)st] : "?";
+        if (st == SAL_OK) std::fprintf(stderr, "[libsal] %s -> %s\n", name_, sn);
+        else std::fprintf(stderr, "[libsal] %s -> %s: %s\n", name_, sn, g_error.c_str());
+    }
+    return st;
 }
 
 sal_status check_spec(const sal_spec* spec, int64_t T, int64_t IL, int64_t XL) {

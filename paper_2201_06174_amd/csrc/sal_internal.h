@@ -31,6 +31,21 @@ inline sal_status lds_limit_once(const void* kernel, int bytes, std::atomic<uint
     return st;
 }
 
+// ---------------------------------------------------------------- observability
+
+// Opened by every C-ABI entry point that enqueues device work: a roctx range named after the
+// call (recorded by rocprofv3 --marker-trace), and with SAL_LOG=1 in the environment one line
+// per call on stderr with its status and, on failure, the message of sal_last_error().
+class CallScope {
+  public:
+    explicit CallScope(const char* name);
+    ~CallScope();
+    sal_status done(sal_status st);
+
+  private:
+    const char* name_;
+};
+
 // ---------------------------------------------------------------- shapes
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

@@ -48,7 +48,7 @@ extern "C" {
 
 size_t sal_fuse_noalloc_max_bytes(void) { return sizeof(double) * kScratchDoubles; }
 
-sal_status sal_fuse_noalloc(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion* fusion,
+static sal_status sal_fuse_noalloc_body(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion* fusion,
                             const float* D, const uint8_t* mask, int64_t T, int64_t IL, int64_t XL, int32_t s,
                             double* W_out, float* S_out, sal_stream stream) {
     sal_status st = check_fusion_args(fusion, D);
@@ -81,6 +81,13 @@ sal_status sal_fuse_noalloc(const float* Sm, int64_t Tg, int64_t ILg, int64_t XL
         ws = g_scratch[dev].load(std::memory_order_acquire);
     }
     return launch_fuse(Sm, Tg, ILg, XLg, *fusion, D, mask, T, IL, XL, s, W_out, S_out, ws, (hipStream_t)stream);
+}
+
+sal_status sal_fuse_noalloc(const float* Sm, int64_t Tg, int64_t ILg, int64_t XLg, const sal_fusion* fusion,
+                            const float* D, const uint8_t* mask, int64_t T, int64_t IL, int64_t XL, int32_t s,
+                            double* W_out, float* S_out, sal_stream stream) {
+    CallScope cs("sal_fuse_noalloc");
+    return cs.done(sal_fuse_noalloc_body(Sm, Tg, ILg, XLg, fusion, D, mask, T, IL, XL, s, W_out, S_out, stream));
 }
 
 }  // extern "C"

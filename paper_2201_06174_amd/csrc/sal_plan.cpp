@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -36,6 +37,48 @@ size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int, int, int>, int> g_tuned;  // class key + log2(tiles) -> tile depth
+
+// Tile depths tuned by earlier processes: with SAL_AUTOTUNE_CACHE naming a file, each tuned
+// class is appended as one line "arch n s precision window log2(tiles) depth", and a later
+// plan on the same architecture reads the depth instead of timing the candidates again.
+std::string cache_path() {
+    const char* v = std::getenv("SAL_AUTOTUNE_CACHE");
+    return v ? std::string(v) : std::string();
+}
+
+std::string device_arch(int device) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+bool cache_lookup(const std::string& arch, int n, int s, int prec, int window, int bucket, int* ct) {
+    const std::string path = cache_path();
+    if (path.empty()) return false;
+    FILE* f = std::fopen(path.c_str(), "r");
+    if (!f) return false;
+    char a[64];
+    int v[6];
+    bool hit = false;
+    while (std::fscanf(f, "%63s %d %d %d %d %d %d", a, &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]) == 7)
+        if (arch == a && v[0] == n && v[1] == s && v[2] == prec && v[3] == window && v[4] == bucket && v[5] > 0) {
+            *ct = v[5];  // the last matching line wins
+            hit = true;
+        }
+    std::fclose(f);
+    return hit;
+}
+
+void cache_store(const std::string& arch, int n, int s, int prec, int window, int bucket, int ct) {
+    const std::string path = cache_path();
+    if (path.empty()) return;
+    FILE* f = std::fopen(path.c_str(), "a");
+    if (!f) return;  // a cache that cannot be written only costs a re-tune later
+    std::fprintf(f, "%s %d %d %d %d %d %d\n", arch.c_str(), n, s, prec, window, bucket, ct);
+    std::fclose(f);
+}
 
 int log2_bucket(int64_t v) {
     int b = 0;
@@ -162,12 +205,20 @@ sal_status autotune_class(sal_plan* plan, Class& c) {
     }
     auto key_b = std::make_tuple(std::get<0>(key), std::get<1>(key), std::get<2>(key), std::get<3>(key),
                                  std::get<4>(key), log2_bucket(tiles0));
+    const std::string arch = device_arch(plan->device);
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         auto it = g_tuned.find(key_b);
         if (it != g_tuned.end()) {
             c.timing = "cached";
             return build_class_params(plan, c, it->second);
+        }
+        int ct = 0;
+        if (cache_lookup(arch, c.spec.n, c.spec.s, c.spec.precision, c.spec.window, std::get<5>(key_b), &ct) &&
+            std::find(c.candidates.begin(), c.candidates.end(), ct) != c.candidates.end()) {
+            g_tuned[key_b] = ct;
+            c.timing = "cached in " + cache_path();
+            return build_class_params(plan, c, ct);
         }
     }
     hipStream_t s = nullptr;
@@ -208,6 +259,7 @@ sal_status autotune_class(sal_plan* plan, Class& c) {
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         g_tuned[key_b] = best_ct;
+        cache_store(arch, c.spec.n, c.spec.s, c.spec.precision, c.spec.window, std::get<5>(key_b), best_ct);
     }
     return build_class_params(plan, c, best_ct);
 }
@@ -230,7 +282,7 @@ using namespace sal;
 
 extern "C" {
 
-sal_status sal_plan_create(const sal_batch_item* items, int64_t count, uint32_t flags, sal_plan** out) {
+static sal_status sal_plan_create_body(const sal_batch_item* items, int64_t count, uint32_t flags, sal_plan** out) {
     if (!out) return fail(SAL_ERR_ARG, "out is NULL");
     *out = nullptr;
     if (!items || count < 1) return fail(SAL_ERR_ARG, "a plan needs at least one member");
@@ -390,10 +442,20 @@ sal_status sal_plan_create(const sal_batch_item* items, int64_t count, uint32_t 
     return SAL_OK;
 }
 
-sal_status sal_plan_launch(sal_plan* plan, sal_stream stream) {
+sal_status sal_plan_create(const sal_batch_item* items, int64_t count, uint32_t flags, sal_plan** out) {
+    CallScope cs("sal_plan_create");
+    return cs.done(sal_plan_create_body(items, count, flags, out));
+}
+
+static sal_status sal_plan_launch_body(sal_plan* plan, sal_stream stream) {
     if (!plan) return fail(SAL_ERR_ARG, "plan is NULL");
     if (plan->flags & SAL_PLAN_NO_GRAPH) return enqueue_all(plan, (hipStream_t)stream);
     return check_hip(hipGraphLaunch(plan->exec, (hipStream_t)stream), "hipGraphLaunch");
+}
+
+sal_status sal_plan_launch(sal_plan* plan, sal_stream stream) {
+    CallScope cs("sal_plan_launch");
+    return cs.done(sal_plan_launch_body(plan, stream));
 }
 
 sal_status sal_plan_status(const sal_plan* plan, sal_stream stream, int64_t* fallback_count, int64_t* first_fallback) {

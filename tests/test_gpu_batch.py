@@ -146,3 +146,35 @@ def test_plan_status_word(torch_sal):
     for i in range(4):
         assert plan.output(i)["W"][3].item() == (1.0 if i in (1, 3) else 0.0)
     plan.close()
+
+
+def test_autotune_cache_persists_across_processes(tmp_path):
+    """SAL_AUTOTUNE_CACHE: a first process times the candidate tile depths and appends them
+    to the file; a second process on the same architecture reads them instead of timing."""
+    import os
+    import subprocess
+    import sys
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    script = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import torch\n"
+        "import paper_2201_06174_amd as sal\n"
+        "from paper_2201_06174_amd import synth\n"
+        "ms = []\n"
+        "for i, shape in enumerate(((40, 36, 44), (44, 40, 36))):\n"
+        "    V = synth.make_volume(synth.VolumeSpec(shape, faults=[synth.centre_fault(shape)]), 300 + i)\n"
+        "    ms.append({'V': torch.from_numpy(V).cuda(), 'cfg': sal.Config(n=16, s=2, offsets=synth.axis_stencil(8))})\n"
+        "p = sal.Plan(ms, autotune=True)\n"
+        "print(p.describe())\n" % root)
+    env = dict(os.environ, SAL_AUTOTUNE_CACHE=str(tmp_path / "tune.txt"))
+    first = subprocess.run([sys.executable, "-c", script], env=env, capture_output=True, text=True, timeout=110)
+    print(first.stdout, first.stderr[-2000:])
+    assert first.returncode == 0 and "CT=" in first.stdout
+    lines = (tmp_path / "tune.txt").read_text().split("\n")
+    assert lines[0].startswith("gfx") and len(lines[0].split()) == 7
+    second = subprocess.run([sys.executable, "-c", script], env=env, capture_output=True, text=True, timeout=110)
+    print(second.stdout)
+    assert second.returncode == 0 and "cached in" in second.stdout and "CT=" not in second.stdout
