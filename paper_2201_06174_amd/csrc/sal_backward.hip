@@ -90,6 +90,9 @@ struct AdjGeom {
     // one 16-row register tile (banded operand over K = (centre, packed row), 16 per-lane
     // values per centre pair kept in LDS), stored once
     static constexpr bool BANDC = PAIR && RT <= 16;
+    // the banded paired operand spans K = 12 samples: both centres of a pair fit for s <= 4
+    // (the stride of an n = 8 window is at most 3)
+    static_assert(!PAIR || N + S <= 12, "paired contraction too short for this stride");
     static_assert(lds_floats * sizeof(float) <= 160 * 1024, "adjoint tile exceeds the LDS");
 };
 
@@ -139,11 +142,11 @@ __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_
     for (int e = tid; e < KH * N * 2; e += 512) tab[e] = p.passA[e];
     if constexpr (Gm::BANDB) {
         // banded transposed pass B: lane l at step k has row il = l & 15 and K slot
-        // 4 k + (l >> 4) = (il-centre K >> 3, packed row K & 7): the adjoint coefficient of
-        // sample il - centre*S
+        // (il-centre l >> 4, packed row k): the adjoint coefficient of sample il - centre*S.
+        // Every lane of a step takes the same packed row, so the inputs are formed alike.
         for (int e = tid; e < 8 * 64; e += 512) {
-            const int l = e & 63, k = e >> 6, K = 4 * k + (l >> 4), a = (l & 15) - (K >> 3) * S;
-            btab[e] = a >= 0 && a < N ? p.inv[a * 16 + (K & 7)] : 0.f;
+            const int l = e & 63, k = e >> 6, a = (l & 15) - (l >> 4) * S;
+            btab[e] = a >= 0 && a < N ? p.inv[a * 16 + k] : 0.f;
         }
     }
     if constexpr (Gm::BANDC) {
@@ -215,12 +218,49 @@ __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_
         }
         __syncthreads();
         // ---- forward pass B
-        {
+        if constexpr (Gm::PAIR) {
+            // two il-centres per contraction: rows 8..15 of the banded operand (the one pass C
+            // uses along t) hold the second centre of a pair, so the columns are (t row parity,
+            // centre pair, xc) and one product covers two t rows
+            const int pp = (col >> 2) & 1, xc = col & 3;
+            // this lane's sample of step ks, 2 pp S + 4 ks + grp; in the last step the samples past
+            // the row (they meet zero coefficients) read its last one
+            const int ib = (2 * pp * S + grp) * 4 + xc, i2 = min(2 * pp * S + 8 + grp, RI - 1) * 4 + xc;
+            const int cw = (2 * pp + (grp >> 1)) * 4 + xc;  // window column of this lane's rows
+            for (int it = wave; it < (RT + 1) / 2; it += 8) {
+                const int rt = 2 * it + (col >> 3);
+                const float* ar = Ab + (rt < RT ? rt : RT - 1) * RI * 4;
+                f4 dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};
+                // raised issue priority while a wave issues a run of products (in every pass B and
+                // the banded inverse t- and il-DFTs): about 1.5 % off the adjoint in A/B runs
+                __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+                for (int ks = 0; ks < 3; ks++) {
+                    const int io = ks < 2 ? ib + 16 * ks : i2;
+                    dr = mfma4b(amatP[ks], ar[io], dr);
+                    di = mfma4b(amatP[ks], ar[abStride + io], di);
+                }
+                __builtin_amdgcn_s_setprio(0);
+                // a lane's rows are packed rows 4 (grp & 1) + j of centre 2 pp + (grp >> 1); the
+                // row of a t row past the tile is dropped
+                if (rt < RT) {
+#pragma unroll
+                    for (int pr = 0; pr < 2; pr++) {
+                        const int q = 2 * (grp & 1) + pr;  // rows 2q, 2q + 1: ki 0 and n/2 for q = 0
+                        const bool sp = q == 0;
+                        const float Ca = dr[2 * pr], Sb = dr[2 * pr + 1], Cai = di[2 * pr], Sbi = di[2 * pr + 1];
+                        const int u1 = sp ? 0 : q, u2 = sp ? N / 2 : N - q;
+                        Gb[(u1 * RT + rt) * 16 + cw] = sp ? Ca : Ca + Sbi;
+                        Gb[gbStride + (u1 * RT + rt) * 16 + cw] = sp ? Cai : Cai - Sb;
+                        Gb[(u2 * RT + rt) * 16 + cw] = sp ? Sb : Ca - Sbi;
+                        Gb[gbStride + (u2 * RT + rt) * 16 + cw] = sp ? Sbi : Cai + Sb;
+                    }
+                }
+            }
+        } else {
             const int ilc = col >> 2, xc = col & 3;
             for (int rt = wave; rt < RT; rt += 8) {
                 f4 dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};
-                // raised issue priority while a wave issues a run of products (here and in the
-                // banded inverse t- and il-DFTs below): about 1.5 % off the adjoint in A/B runs
                 __builtin_amdgcn_s_setprio(1);
 #pragma unroll
                 for (int ks = 0; ks < NK; ks++) {
@@ -255,9 +295,23 @@ __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_
         __syncthreads();
         // ---- pass C, Y = c F/|F|, and the transposed pass C with overlap-add over the t-centres.
         // One wave owns each ki slot u, so its rows of the inverse buffer are written by it alone.
+        // On the planes kx = 0 and kx = n/2 (their own Hermitian mirrors, Y(-k) = conj Y(k)) only
+        // the real part of the synthesis is kept, to which the bins k and -k contribute equally:
+        // the ki slots (0, n/2) are visited with twice their weight, their mirrors not at all
+        // (zero rows), and the self-mirrored slots 0 and n/2 as they are.
+        const bool mirror = kx == 0 || 2 * kx == N;
         for (int u = wave; u < N; u += 8) {
+            if (mirror && 2 * u > N) {
+                for (int e = lane; e < RT * 16; e += 64) {
+                    Gi[u * RT * 16 + e] = 0.f;
+                    Gi[gbStride + u * RT * 16 + e] = 0.f;
+                }
+                continue;
+            }
+            const float fold = mirror && u > 0 && 2 * u < N ? 2.f : 1.f;
+            auto scaled = [&](float4 w) { return make_float4(fold * w.x, fold * w.y, fold * w.z, fold * w.w); };
             const float4* wrow = p.wts + ((size_t)(kx * N + u) * 16 + 4 * grp);
-            const float4 w0 = wrow[0], w1 = wrow[1], w2 = wrow[2], w3 = wrow[3];
+            const float4 w0 = scaled(wrow[0]), w1 = scaled(wrow[1]), w2 = scaled(wrow[2]), w3 = scaled(wrow[3]);
             // forward contraction of t-centre tc and Y = c F/|F| as packed inverse-DFT inputs
             auto fwd_y = [&](int tc, float (&y)[8]) {
                 f4 dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};
@@ -321,7 +375,7 @@ __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_
                 f4 Zr = {0.f, 0.f, 0.f, 0.f}, Zi = {0.f, 0.f, 0.f, 0.f};  // banded: rows t of slot u
                 // a lane's rows belong to centre tc0 + (grp >> 1), packed rows 4 (grp & 1) + j
                 const float4* wp = p.wts + ((size_t)(kx * N + u) * 16 + 4 * (grp & 1));
-                const float4 v0 = wp[0], v1 = wp[1], v2 = wp[2], v3 = wp[3];
+                const float4 v0 = scaled(wp[0]), v1 = scaled(wp[1]), v2 = scaled(wp[2]), v3 = scaled(wp[3]);
 #pragma unroll 1
                 for (int tc0 = 0; tc0 < CT; tc0 += 2) {
                     f4 dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};
@@ -429,34 +483,39 @@ __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_
         if constexpr (!Gm::BANDB)
             for (int e = tid; e < 2 * abStride; e += 512) Ab[e] = 0.f;
         __syncthreads();
-        // packed inverse-DFT input of row r (0: ki 0, 1: ki n/2, 2q: cos q, 2q+1: sin q) for t row
-        // rt and window column cw, real (ch 0) or imaginary (ch 1) channel
-        auto packed_x = [&](int r, int rt, int cw, int ch) {
-            if (r == 0 || r == 1) {
-                const int u = r == 0 ? 0 : N / 2;
-                return Gi[ch * gbStride + (u * RT + rt) * 16 + cw];
-            }
-            const int q = r >> 1;
-            const float pr_ = Gi[(q * RT + rt) * 16 + cw], pi_ = Gi[gbStride + (q * RT + rt) * 16 + cw];
-            const float mr_ = Gi[((N - q) * RT + rt) * 16 + cw], mi_ = Gi[gbStride + ((N - q) * RT + rt) * 16 + cw];
-            if (r & 1) return ch ? pr_ - mr_ : mi_ - pi_;  // sin row: i (G(+q) - G(-q))
-            return ch ? pi_ + mi_ : pr_ + mr_;
-        };
         if constexpr (Gm::BANDB) {
             // ---- transposed pass B as one banded contraction per (4 t rows, channel): output
             // rows il, columns (t row, xc), K = (il-centre, packed row); the overlap-add over the
-            // il-centres happens inside the contraction and every output is stored once
+            // il-centres happens inside the contraction and every output is stored once.  Step k
+            // takes packed row k (0: ki 0, 1: ki n/2, 2q: cos q, 2q+1: sin q) of il-centre grp,
+            // formed from this channel's plane P and the other one, Q: the cos row of the real
+            // channel is G(+q) + G(-q), its sin row i (G(+q) - G(-q)).
             const int rtp = col >> 2, xc = col & 3;
             for (int item = wave; item < 2 * ((RT + 3) / 4); item += 8) {
                 const int ch = item & 1, rt = 4 * (item >> 1) + rtp;
+                // a t row past the tile reads the last one; its outputs are dropped
+                const int at = (rt < RT ? rt : RT - 1) * 16 + grp * 4 + xc;
+                const float* P = Gi + ch * gbStride + at;
+                const float* Q = Gi + (1 - ch) * gbStride + at;
+                float gp[N], gq[N];
+#pragma unroll
+                for (int u = 0; u < N; u++) {
+                    gp[u] = P[u * RT * 16];
+                    gq[u] = 2 * u % N ? Q[u * RT * 16] : 0.f;
+                }
+                float x[8];
+                x[0] = gp[0];
+                x[1] = gp[N / 2];
+#pragma unroll
+                for (int q = 1; q < N / 2; q++) {
+                    x[2 * q] = gp[q] + gp[N - q];
+                    const float d = gq[q] - gq[N - q];
+                    x[2 * q + 1] = ch ? d : -d;
+                }
                 f4 z = {0.f, 0.f, 0.f, 0.f};
                 __builtin_amdgcn_s_setprio(1);
 #pragma unroll
-                for (int k = 0; k < 8; k++) {
-                    const int K = 4 * k + grp;
-                    const float x = rt < RT ? packed_x(K & 7, rt, (K >> 3) * 4 + xc, ch) : 0.f;
-                    z = mfma4b(btab[k * 64 + lane], x, z);
-                }
+                for (int k = 0; k < 8; k++) z = mfma4b(btab[k * 64 + lane], x[k], z);
                 __builtin_amdgcn_s_setprio(0);
                 if (rt < RT) {
 #pragma unroll
