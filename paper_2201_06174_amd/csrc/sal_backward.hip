@@ -19,6 +19,7 @@
 
 #include "sal_aux.h"
 #include "sal_device.h"
+#include "sal_passb.h"
 #include "sal_stage.h"
 
 namespace sal {
@@ -219,44 +220,10 @@ __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_
         __syncthreads();
         // ---- forward pass B
         if constexpr (Gm::PAIR) {
-            // two il-centres per contraction: rows 8..15 of the banded operand (the one pass C
-            // uses along t) hold the second centre of a pair, so the columns are (t row parity,
-            // centre pair, xc) and one product covers two t rows
-            const int pp = (col >> 2) & 1, xc = col & 3;
-            // this lane's sample of step ks, 2 pp S + 4 ks + grp; in the last step the samples past
-            // the row (they meet zero coefficients) read its last one
-            const int ib = (2 * pp * S + grp) * 4 + xc, i2 = min(2 * pp * S + 8 + grp, RI - 1) * 4 + xc;
-            const int cw = (2 * pp + (grp >> 1)) * 4 + xc;  // window column of this lane's rows
-            for (int it = wave; it < (RT + 1) / 2; it += 8) {
-                const int rt = 2 * it + (col >> 3);
-                const float* ar = Ab + (rt < RT ? rt : RT - 1) * RI * 4;
-                f4 dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};
-                // raised issue priority while a wave issues a run of products (in every pass B and
-                // the banded inverse t- and il-DFTs): about 1.5 % off the adjoint in A/B runs
-                __builtin_amdgcn_s_setprio(1);
-#pragma unroll
-                for (int ks = 0; ks < 3; ks++) {
-                    const int io = ks < 2 ? ib + 16 * ks : i2;
-                    dr = mfma4b(amatP[ks], ar[io], dr);
-                    di = mfma4b(amatP[ks], ar[abStride + io], di);
-                }
-                __builtin_amdgcn_s_setprio(0);
-                // a lane's rows are packed rows 4 (grp & 1) + j of centre 2 pp + (grp >> 1); the
-                // row of a t row past the tile is dropped
-                if (rt < RT) {
-#pragma unroll
-                    for (int pr = 0; pr < 2; pr++) {
-                        const int q = 2 * (grp & 1) + pr;  // rows 2q, 2q + 1: ki 0 and n/2 for q = 0
-                        const bool sp = q == 0;
-                        const float Ca = dr[2 * pr], Sb = dr[2 * pr + 1], Cai = di[2 * pr], Sbi = di[2 * pr + 1];
-                        const int u1 = sp ? 0 : q, u2 = sp ? N / 2 : N - q;
-                        Gb[(u1 * RT + rt) * 16 + cw] = sp ? Ca : Ca + Sbi;
-                        Gb[gbStride + (u1 * RT + rt) * 16 + cw] = sp ? Cai : Cai - Sb;
-                        Gb[(u2 * RT + rt) * 16 + cw] = sp ? Sb : Ca - Sbi;
-                        Gb[gbStride + (u2 * RT + rt) * 16 + cw] = sp ? Sbi : Cai + Sb;
-                    }
-                }
-            }
+            // two il-centres per contraction with the banded operand pass C uses along t;
+            // raised issue priority while a wave issues a run of products (in every pass B and
+            // the banded inverse t- and il-DFTs): about 1.5 % off the adjoint in A/B runs
+            pass_b_pair8<true>(Ab, abStride, Gb, gbStride, RT, RI, S, amatP, wave, 8, col, grp);
         } else {
             const int ilc = col >> 2, xc = col & 3;
             for (int rt = wave; rt < RT; rt += 8) {

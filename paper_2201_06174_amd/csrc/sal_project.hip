@@ -25,6 +25,7 @@
 
 #include "sal_aux.h"
 #include "sal_grid.h"
+#include "sal_passb.h"
 #include "sal_stage.h"
 
 namespace sal {
@@ -187,7 +188,9 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
             Wl[e] = make_float4(f * w.x, f * w.y, f * w.z, f * w.w);
         }
         // ---- pass B: complex DFT along il on the matrix cores, combined into signed ki slots
-        {
+        if constexpr (PAIR) {
+            pass_b_pair8<false>(Ab, abStride, Gb, gbStride, RT, RI, s, amatP, wave, kNT / 64, col, grp);
+        } else {
             const int ilc = col >> 2, xc = col & 3;
             for (int rt = wave; rt < RT; rt += kNT / 64) {
                 f4 dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};

@@ -29,7 +29,7 @@ CSRC = os.path.join(HERE, "csrc")
 
 # the sources of the FP32 feature kernel's code, launch shape and memory accesses (the
 # host-built constant tables change values, not traffic)
-FP32_KERNEL_SOURCES = ("sal_project.hip", "sal_stage.h", "sal_grid.h", "sal_aux.h", "sal_internal.h")
+FP32_KERNEL_SOURCES = ("sal_project.hip", "sal_stage.h", "sal_grid.h", "sal_passb.h", "sal_aux.h", "sal_internal.h")
 
 
 LOWP_KERNEL_SOURCES = ("sal_lowp.hip", "sal_stage.h", "sal_grid.h", "sal_aux.h", "sal_internal.h")
