@@ -181,7 +181,10 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
         // planes kx = 0 and kx = n/2 are their own Hermitian mirrors (|F(-k)| = |F(k)|): only
         // the ki slots [0, n/2] are visited there, and a slot whose mirror is skipped counts twice.
         const bool mirror = kx == 0 || 2 * kx == N;
-        for (int e = tid; e < N * 16; e += kNT) {
+        // at n = 8 pass B keeps waves 0..7 busy, so waves from 8 on copy the weights: the latency
+        // of their global loads overlaps the products instead of delaying them
+        for (int e = PAIR ? tid - kNT / 2 : tid; e < N * 16; e += kNT) {
+            if (e < 0) break;
             const int u = e >> 4;
             const float f = mirror && u >= 1 && u < N / 2 ? 2.f : 1.f;
             const float4 w = p.wts[(size_t)kx * N * 16 + e];

@@ -53,6 +53,11 @@ __device__ __forceinline__ void stage_tile_with(const float* __restrict__ V, int
             float v[kStageBatch];
 #pragma unroll
             for (int u = 0; u < kStageBatch; u++) {
+                // a group of a small region owns far fewer planes than a batch: steps past every
+                // group's last plane are not issued (a test uniform over the workgroup, fixed at
+                // compile time for fixed extents); a group's last step may still read the last
+                // plane again
+                if (u * G >= RT) break;
                 const int rt = min(rt0 + u * G, RT - 1);
                 const float* pb = V + reflect_clamp_s(t0 + rt, T) * PS;
                 // a plane below 2^30 samples takes a 32-bit lane offset on a scalar base
