@@ -117,7 +117,7 @@ __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_
     extern __shared__ float lds[];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: loops over waves stay scalar
     const int col = lane & 15;
     const int grp = lane >> 4;
 

@@ -247,7 +247,7 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
     constexpr int NPL = L::split ? 4 : 2;  // Ab planes: (hi, lo) x (real, imaginary)
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: loops over waves stay scalar
     const int col = lane & 15;
     const int grp = lane >> 4;
 
@@ -397,6 +397,22 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
                 const f4 d = contract<PREC>(ah, al, pbh, pbl, f4{0.f, 0.f, 0.f, 0.f});
                 if (col < 8) {
                     const int h = col >> 2, xc = col & 3;
+                    if constexpr (2 * ab_iq2(S > 0 ? S : 1) == FG.RIE) {
+                        // the Ab rows hold exactly the il pairs of a staged row set (pitch RIE / 2
+                        // pairs), so row pair r / 2 of the staged planes lands at dword r / 2 * 4 + xc:
+                        // a running address instead of a division per row
+                        uint32_t* dst = (uint32_t*)(Ab + (size_t)h * abPlane) + (mt * 8 + 2 * grp) * 4 + xc;
+                        const bool full = (mt + 1) * 16 <= FG.MROWS;  // only the last tile is partial
+#pragma unroll
+                        for (int pr = 0; pr < 2; pr++) {
+                            if (full || mt * 16 + 4 * grp + 2 * pr < FG.MROWS) {
+                                const uint32_t hw = L::pack_hi(d[2 * pr], d[2 * pr + 1]);
+                                dst[4 * pr] = hw;
+                                if constexpr (L::split) dst[abPlane + 4 * pr] = L::pack_lo(d[2 * pr], d[2 * pr + 1], hw);
+                            }
+                        }
+                        continue;
+                    }
 #pragma unroll
                     for (int pr = 0; pr < 2; pr++) {
                         const int r = mt * 16 + 4 * grp + 2 * pr;

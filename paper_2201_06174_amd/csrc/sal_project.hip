@@ -83,7 +83,7 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
     static_assert(NW == 16, "the ki slots are split between two halves of 8 waves");
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: loops over waves stay scalar
     const int col = lane & 15;
     const int grp = lane >> 4;
 
