@@ -64,9 +64,11 @@ struct Lp<SAL_PREC_SPLIT_BF16> {
         const bf2 v = {(__bf16)a, (__bf16)b};
         return __builtin_bit_cast(uint32_t, v);
     }
-    // the rounded residuals x - hi (exact in fp32) of the pair packed by pack_hi
+    // the rounded residuals x - hi (exact in fp32) of the pair packed by pack_hi.  The low
+    // element's hi is h << 16, written as a byte alignment so that it stays one instruction
+    // (a plain shift is turned back into a second rounding of a plus a shift)
     __device__ static __forceinline__ uint32_t pack_lo(float a, float b, uint32_t h) {
-        return pack_hi(a - __uint_as_float(h << 16), b - __uint_as_float(h & 0xffff0000u));
+        return pack_hi(a - __uint_as_float(__builtin_amdgcn_alignbyte(h, 0u, 2)), b - __uint_as_float(h & 0xffff0000u));
     }
     __device__ static __forceinline__ f4 mma(vec a, vec b, f4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
