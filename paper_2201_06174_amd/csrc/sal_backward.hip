@@ -139,7 +139,7 @@ __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_
     constexpr int gbStride = N * RT * 16;
 
     const int64_t t0 = tt * CT * S - N / 2, i0 = ti * 4 * S - N / 2, x0 = tx * 4 * S - N / 2;
-    stage_tile<512>(p.V, p.T, p.IL, p.XL, t0, i0, x0, RT, RI, RX, RXp, Vt);
+    stage_tile<512, stage_batch<512>(RT, RI, RX)>(p.V, p.T, p.IL, p.XL, t0, i0, x0, RT, RI, RX, RXp, Vt);
     for (int e = tid; e < KH * N * 2; e += 512) tab[e] = p.passA[e];
     if constexpr (Gm::BANDB) {
         // banded transposed pass B: lane l at step k has row il = l & 15 and K slot

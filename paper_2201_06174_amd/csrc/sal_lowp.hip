@@ -309,7 +309,7 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
     if (staged) {
         // region and pads are in place (the pads are never overwritten)
     } else if constexpr (FIX) {
-        stage_tile_with<kNTL>(p.V, p.T, p.IL, p.XL, t0, i0, x0, RT, RI, RX, [&](int rt, int ri, int rx, float v) {
+        stage_tile_with<kNTL, stage_batch<kNTL>(FG.RT, FG.RI, FG.RX)>(p.V, p.T, p.IL, p.XL, t0, i0, x0, RT, RI, RX, [&](int rt, int ri, int rx, float v) {
             const int at = (rt * FG.RIE + ri) * FG.XP + rx;
             const uint16_t h = L::hi(v);
             Vb[at] = h;

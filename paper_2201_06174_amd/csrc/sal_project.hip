@@ -104,7 +104,9 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
     // stage the tile and its halo, reflected at the volume borders
     if (!staged) {
         const int64_t t0 = tt * CT * s - N / 2, i0 = ti * 4 * s - N / 2, x0 = tx * 4 * s - N / 2;
-        stage_tile<kNT>(p.V, p.T, p.IL, p.XL, t0, i0, x0, RT, RI, RX, RXp, Vt);
+        // with a compile-time stride the deepest region is (8 CTW - 1) s + n planes
+        constexpr int MAXU = S > 0 ? stage_batch<kNT>((8 * CTW - 1) * S + N, 3 * S + N, 3 * S + N) : kStageBatch;
+        stage_tile<kNT, MAXU>(p.V, p.T, p.IL, p.XL, t0, i0, x0, RT, RI, RX, RXp, Vt);
     }
 
     // A operand of both MFMA passes: packed taper*DFT rows

@@ -5,12 +5,20 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 namespace sal {
 
 // Half-sample reflection, then a clamp that keeps the (never used) positions of
 // centres beyond the grid inside the volume.
 __device__ __forceinline__ int64_t reflect_clamp_s(int64_t p, int64_t N) {
+    if (p < 0) p = -1 - p;
+    if (p >= N) p = 2 * N - 1 - p;
+    return p < 0 ? 0 : (p >= N ? N - 1 : p);
+}
+// The same in 32 bits: for a wave-uniform plane index it stays on the scalar unit, which
+// has no 64-bit signed compare.
+__device__ __forceinline__ int32_t reflect_clamp_s32(int32_t p, int32_t N) {
     if (p < 0) p = -1 - p;
     if (p >= N) p = 2 * N - 1 - p;
     return p < 0 ? 0 : (p >= N ? N - 1 : p);
@@ -27,7 +35,10 @@ __device__ __forceinline__ int64_t reflect_clamp_s(int64_t p, int64_t N) {
 // unconditional and only the stores are masked.
 constexpr int kStageBatch = 16;
 
-template <int NT, typename Store>
+// MAXU bounds the t planes one group loads per batch (at most kStageBatch); a kernel whose
+// region extents are fixed at compile time passes stage_batch(...) so the unrolled batch has
+// only the steps a group can own.
+template <int NT, int MAXU = kStageBatch, typename Store>
 __device__ __forceinline__ void stage_tile_with(const float* __restrict__ V, int64_t T, int64_t IL, int64_t XL,
                                                 int64_t t0, int64_t i0, int64_t x0, int RT, int RI, int RX,
                                                 Store store) {
@@ -40,6 +51,8 @@ __device__ __forceinline__ void stage_tile_with(const float* __restrict__ V, int
     const int g = wave / WPG;
     if (g >= G) return;
     const int64_t PS = IL * XL;
+    // a volume below 2^31 samples takes 32-bit plane offsets (scalar) on a 32-bit lane offset
+    const bool small = T * PS < (int64_t(1) << 31);
     // waves of a group (or, with fewer waves than a column set, all waves in turn) take
     // consecutive 64-column slices
     const int wstep = G == 1 ? NWV : WPG;
@@ -49,26 +62,34 @@ __device__ __forceinline__ void stage_tile_with(const float* __restrict__ V, int
         const int ri = qc / RX, rx = qc - ri * RX;
         const int64_t off = reflect_clamp_s(i0 + ri, IL) * XL + reflect_clamp_s(x0 + rx, XL);
         const uint32_t off32 = (uint32_t)off;
-        for (int rt0 = g; rt0 < RT; rt0 += G * kStageBatch) {
-            float v[kStageBatch];
+        // SMALL: 32-bit plane offsets, reflected on the scalar unit
+        auto planes = [&](auto is_small) {
+            constexpr bool SMALL = decltype(is_small)::value;
+            for (int rt0 = g; rt0 < RT; rt0 += G * MAXU) {
+                float v[MAXU];
 #pragma unroll
-            for (int u = 0; u < kStageBatch; u++) {
-                // a group of a small region owns far fewer planes than a batch: steps past every
-                // group's last plane are not issued (a test uniform over the workgroup, fixed at
-                // compile time for fixed extents); a group's last step may still read the last
-                // plane again
-                if (u * G >= RT) break;
-                const int rt = min(rt0 + u * G, RT - 1);
-                const float* pb = V + reflect_clamp_s(t0 + rt, T) * PS;
-                // a plane below 2^30 samples takes a 32-bit lane offset on a scalar base
-                v[u] = PS < (int64_t(1) << 30) ? pb[off32] : pb[off];
-            }
+                for (int u = 0; u < MAXU; u++) {
+                    // a group of a small region owns far fewer planes than a batch: steps past
+                    // every group's last plane are not issued (a test uniform over the workgroup,
+                    // fixed at compile time for fixed extents); a group's last step may still
+                    // read the last plane again
+                    if (u * G >= RT) break;
+                    const int rt = min(rt0 + u * G, RT - 1);
+                    const float* pb =
+                        SMALL ? V + (uint32_t)reflect_clamp_s32((int32_t)t0 + rt, (int32_t)T) * (uint32_t)PS
+                              : V + reflect_clamp_s(t0 + rt, T) * PS;
+                    // a plane below 2^30 samples takes a 32-bit lane offset on a scalar base
+                    v[u] = SMALL || PS < (int64_t(1) << 30) ? pb[off32] : pb[off];
+                }
 #pragma unroll
-            for (int u = 0; u < kStageBatch; u++) {
-                const int rt = rt0 + u * G;
-                if (rt < RT && act) store(rt, ri, rx, v[u]);
+                for (int u = 0; u < MAXU; u++) {
+                    const int rt = rt0 + u * G;
+                    if (rt < RT && act) store(rt, ri, rx, v[u]);
+                }
             }
-        }
+        };
+        if (small) planes(std::true_type{});
+        else planes(std::false_type{});
     }
 }
 
@@ -106,6 +127,14 @@ __host__ __device__ constexpr int stage_planes(int RT, int RI, int RX) {
     return (RI * RX + 63) / 64 > NT / 64 ? 0 : (RT + NT / 64 / ((RI * RX + 63) / 64) - 1) / (NT / 64 / ((RI * RX + 63) / 64));
 }
 
+// Batch bound of stage_tile for a region of at most RT x RI x RX samples: the planes a group
+// owns, or a full batch where the columns take several passes.
+template <int NT>
+__host__ __device__ constexpr int stage_batch(int RT, int RI, int RX) {
+    return stage_planes<NT>(RT, RI, RX) > 0 && stage_planes<NT>(RT, RI, RX) < kStageBatch ? stage_planes<NT>(RT, RI, RX)
+                                                                                           : kStageBatch;
+}
+
 template <int NT, int NPL>
 __device__ __forceinline__ void stage_issue(float (&v)[NPL], const float* __restrict__ V, int64_t T, int64_t IL,
                                             int64_t XL, int64_t t0, int64_t i0, int64_t x0, int RT, int RI, int RX) {
@@ -113,6 +142,16 @@ __device__ __forceinline__ void stage_issue(float (&v)[NPL], const float* __rest
     if (L.g >= L.G) return;  // wave-uniform: idle waves issue nothing
     const int64_t PS = IL * XL;
     const int64_t off = reflect_clamp_s(i0 + L.ri, IL) * XL + reflect_clamp_s(x0 + L.rx, XL);
+    // a volume below 2^31 samples takes 32-bit offsets (the plane's on the scalar unit)
+    if (T * PS < (int64_t(1) << 31)) {
+#pragma unroll
+        for (int u = 0; u < NPL; u++) {
+            const int rt = min(L.g + u * L.G, RT - 1);
+            const float* pb = V + (uint32_t)reflect_clamp_s32((int32_t)t0 + rt, (int32_t)T) * (uint32_t)PS;
+            v[u] = pb[(uint32_t)off];
+        }
+        return;
+    }
 #pragma unroll
     for (int u = 0; u < NPL; u++) {
         const int rt = min(L.g + u * L.G, RT - 1);
@@ -133,11 +172,11 @@ __device__ __forceinline__ void stage_commit(const float (&v)[NPL], int RT, int 
 }
 
 // fp32 rows of pitch RXp: Vt[(rt * RI + ri) * RXp + rx]
-template <int NT>
+template <int NT, int MAXU = kStageBatch>
 __device__ __forceinline__ void stage_tile(const float* __restrict__ V, int64_t T, int64_t IL, int64_t XL,
                                            int64_t t0, int64_t i0, int64_t x0, int RT, int RI, int RX, int RXp,
                                            float* __restrict__ Vt) {
-    stage_tile_with<NT>(V, T, IL, XL, t0, i0, x0, RT, RI, RX,
+    stage_tile_with<NT, MAXU>(V, T, IL, XL, t0, i0, x0, RT, RI, RX,
                         [&](int rt, int ri, int rx, float v) { Vt[(rt * RI + ri) * RXp + rx] = v; });
 }
 
