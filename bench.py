@@ -265,21 +265,19 @@ def time_fwd_bwd(torch, w_name, steps, warmup, peaks=None, V=None):
         r = sal.saliency(Vd, cfg)
         sal.backward(Vd, cfg, r["E"], r["Sm"], r["W"], gS)
     torch.cuda.synchronize()
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    c = torch.cuda.Event(enable_timing=True)
-    fwd = bwd = 0.0
-    for _ in range(steps):
+    # steps back to back, as a training loop runs them: events around each forward and each
+    # backward, one synchronization after the last step (a host wait per step would add the
+    # host's launch latency of every step's first kernel to the forward)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    for a, b, c in ev:
         a.record()
         r = sal.saliency(Vd, cfg)
         b.record()
         sal.backward(Vd, cfg, r["E"], r["Sm"], r["W"], gS)
         c.record()
-        torch.cuda.synchronize()
-        fwd += a.elapsed_time(b)
-        bwd += b.elapsed_time(c)
-    fwd /= steps
-    bwd /= steps
+    torch.cuda.synchronize()
+    fwd = sum(a.elapsed_time(b) for a, b, _ in ev) / steps
+    bwd = sum(b.elapsed_time(c) for _, b, c in ev) / steps
     nvox = int(np.prod(V.shape))
     nwin = int(np.prod([-(-N // w.s) for N in V.shape]))
     # forward, recomputed spectra and the adjoint synthesis: three dense-DFT passes of FP32 work
@@ -287,8 +285,8 @@ def time_fwd_bwd(torch, w_name, steps, warmup, peaks=None, V=None):
     # the algorithmic count: three real-input 3D FFTs of each local cube (forward, recomputed,
     # adjoint synthesis)
     alg = 3 * algorithmic_flops_per_window(w.n) * nwin / ((fwd + bwd) * 1e-3) / 1e12
-    kern = {"grad": ["k_project_fp32<8, 1, 1>", "k_spectral_adjoint<8, 1>"],
-            "salt": ["k_project_fp32<16, 2, 1>", "k_spectral_adjoint<16, 2>"]}.get(w_name)
+    kern = {"grad": ["k_project_fp32<8, 1, 1, false>", "k_spectral_adjoint<8, 1, false>"],
+            "salt": ["k_project_fp32<16, 2, 1, false>", "k_spectral_adjoint<16, 2, false>"]}.get(w_name)
     roof = {"bound": "mfma", "t_roof_ms": round(t_roof, 4), "frac": round(t_roof / (fwd + bwd), 4),
             "peak_tflops": PEAK_FP32_MFMA_TFLOPS,
             "algorithmic_tflops": round(alg, 3), "algorithmic_frac": round(alg / PEAK_FP32_MFMA_TFLOPS, 4),
@@ -449,7 +447,7 @@ def stored_traffic(workload, precision):
 # (file, kernel, source set)
 MFMA_PROFILES = {}
 for _wl in ("salt", "survey"):
-    MFMA_PROFILES[(_wl, "fp32")] = ("k_project_fp32_%s_mfma.txt" % _wl, "k_project_fp32<16, 2, 1>", "fp32")
+    MFMA_PROFILES[(_wl, "fp32")] = ("k_project_fp32_%s_mfma.txt" % _wl, "k_project_fp32<16, 2, 1, false>", "fp32")
     MFMA_PROFILES[(_wl, "split_bf16")] = ("k_project_lowp_%s_split_bf16_mfma.txt" % _wl,
                                           "k_project_lowp<16, 2, 1, 1, true>", "lowp")
     MFMA_PROFILES[(_wl, "fp16")] = ("k_project_lowp_%s_fp16_mfma.txt" % _wl, "k_project_lowp<16, 2, 2, 1, true>",
