@@ -107,6 +107,32 @@ constexpr int adj_waves_per_simd() {
     return Gm::SEP && Gm::ROWS * Gm::RX <= 40 ? (N <= 8 && S <= 2 ? 6 : 4) : 2;
 }
 
+// Y = c F/|F| (EN: Y = 2 c F) of the two bins of a packed row pair, as packed inverse-DFT
+// inputs.  (Ca, Sb) and (Cai, Sbi) are the pair's cos and sin rows from the real and imaginary
+// channels, giving the bins +q and -q; the special pair sp (cos 0, cos n/2) holds the bins 0 and
+// n/2 directly.  c = sum_m gE_m w_m with the window's upstream gradient ge and the bins' weights
+// wa, wb.  The cos row of the output takes Y(+q) + Y(-q), the sin row i (Y(+q) - Y(-q)).
+// The special pair's selections are products with f = 0 where they can be (fma(f, x, y) is y + x
+// for f = 1, y for f = 0), and |F|^2 is floored at the smallest normal float instead of tested:
+// a zero spectrum still gives Y = 0, as c F times any finite scale.
+template <bool EN>
+__device__ __forceinline__ void pack_y(bool sp, float Ca, float Sb, float Cai, float Sbi, float4 wa, float4 wb,
+                                       const float* ge, float* y) {
+    const float f = sp ? 0.f : 1.f;
+    const float re1 = fmaf(f, Sbi, Ca), im1 = fmaf(-f, Sb, Cai);
+    const float re2 = sp ? Sb : Ca - Sbi, im2 = sp ? Sbi : Cai + Sb;
+    const float c1 = fmaf(ge[0], wa.x, fmaf(ge[1], wa.y, ge[2] * wa.z));
+    const float c2 = fmaf(ge[0], wb.x, fmaf(ge[1], wb.y, ge[2] * wb.z));
+    const float q1 = fmaf(re1, re1, im1 * im1), q2 = fmaf(re2, re2, im2 * im2);
+    const float s1 = EN ? 2.f * c1 : c1 * __builtin_amdgcn_rsqf(fmaxf(q1, 1.17549435e-38f));
+    const float s2 = EN ? 2.f * c2 : c2 * __builtin_amdgcn_rsqf(fmaxf(q2, 1.17549435e-38f));
+    const float y1r = s1 * re1, y1i = s1 * im1, y2r = s2 * re2, y2i = s2 * im2;
+    y[0] = fmaf(f, y2r, y1r);           // real chain, cos row
+    y[1] = sp ? y2r : y2i - y1i;        // real chain, sin row
+    y[2] = fmaf(f, y2i, y1i);           // imaginary chain, cos row
+    y[3] = sp ? y2i : y1r - y2r;        // imaginary chain, sin row
+}
+
 // EN: the adjoint of the energy feature, Y = 2 c(k) F(k) with c(k) from the squared projection
 // weights (p.wts), instead of c(k) F(k) / |F(k)|.
 template <int N, int S, bool EN = false>
@@ -292,21 +318,8 @@ __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_
 #pragma unroll
                 for (int pr = 0; pr < 2; pr++) {
                     const bool sp = (grp == 0) && (pr == 0);
-                    const float Ca = dr[2 * pr], Sb = dr[2 * pr + 1], Cai = di[2 * pr], Sbi = di[2 * pr + 1];
-                    const float re1 = sp ? Ca : Ca + Sbi, im1 = sp ? Cai : Cai - Sb;
-                    const float re2 = sp ? Sb : Ca - Sbi, im2 = sp ? Sbi : Cai + Sb;
-                    const float4 wa = pr ? w2 : w0, wb = pr ? w3 : w1;
-                    const float c1 = fmaf(ge[0], wa.x, fmaf(ge[1], wa.y, ge[2] * wa.z));
-                    const float c2 = fmaf(ge[0], wb.x, fmaf(ge[1], wb.y, ge[2] * wb.z));
-                    const float q1 = fmaf(re1, re1, im1 * im1), q2 = fmaf(re2, re2, im2 * im2);
-                    const float s1 = EN ? 2.f * c1 : (q1 > 0.f ? c1 * __builtin_amdgcn_rsqf(q1) : 0.f);
-                    const float s2 = EN ? 2.f * c2 : (q2 > 0.f ? c2 * __builtin_amdgcn_rsqf(q2) : 0.f);
-                    const float y1r = s1 * re1, y1i = s1 * im1, y2r = s2 * re2, y2i = s2 * im2;
-                    // packed inverse-DFT inputs: cos row gets Y(+q) + Y(-q), sin row i (Y(+q) - Y(-q))
-                    y[4 * pr + 0] = sp ? y1r : y1r + y2r;   // real chain, cos row
-                    y[4 * pr + 1] = sp ? y2r : y2i - y1i;   // real chain, sin row
-                    y[4 * pr + 2] = sp ? y1i : y1i + y2i;   // imaginary chain, cos row
-                    y[4 * pr + 3] = sp ? y2i : y1r - y2r;   // imaginary chain, sin row
+                    pack_y<EN>(sp, dr[2 * pr], dr[2 * pr + 1], di[2 * pr], di[2 * pr + 1], pr ? w2 : w0, pr ? w3 : w1, ge,
+                           &y[4 * pr]);
                 }
             };
             // inverse contraction of t-centre tc, overlap-added into rows tc*S + a of slot u;
@@ -359,20 +372,8 @@ __global__ __launch_bounds__(512, (adj_waves_per_simd<N, S>())) void k_spectral_
 #pragma unroll
                     for (int pr = 0; pr < 2; pr++) {
                         const bool sp = ((grp & 1) == 0) && (pr == 0);
-                        const float Ca = dr[2 * pr], Sb = dr[2 * pr + 1], Cai = di[2 * pr], Sbi = di[2 * pr + 1];
-                        const float re1 = sp ? Ca : Ca + Sbi, im1 = sp ? Cai : Cai - Sb;
-                        const float re2 = sp ? Sb : Ca - Sbi, im2 = sp ? Sbi : Cai + Sb;
-                        const float4 wa = pr ? v2 : v0, wb = pr ? v3 : v1;
-                        const float c1 = fmaf(ge[0], wa.x, fmaf(ge[1], wa.y, ge[2] * wa.z));
-                        const float c2 = fmaf(ge[0], wb.x, fmaf(ge[1], wb.y, ge[2] * wb.z));
-                        const float q1 = fmaf(re1, re1, im1 * im1), q2 = fmaf(re2, re2, im2 * im2);
-                        const float s1 = EN ? 2.f * c1 : (q1 > 0.f ? c1 * __builtin_amdgcn_rsqf(q1) : 0.f);
-                        const float s2 = EN ? 2.f * c2 : (q2 > 0.f ? c2 * __builtin_amdgcn_rsqf(q2) : 0.f);
-                        const float y1r = s1 * re1, y1i = s1 * im1, y2r = s2 * re2, y2i = s2 * im2;
-                        y[4 * pr + 0] = sp ? y1r : y1r + y2r;
-                        y[4 * pr + 1] = sp ? y2r : y2i - y1i;
-                        y[4 * pr + 2] = sp ? y1i : y1i + y2i;
-                        y[4 * pr + 3] = sp ? y2i : y1r - y2r;
+                        pack_y<EN>(sp, dr[2 * pr], dr[2 * pr + 1], di[2 * pr], di[2 * pr + 1], pr ? v2 : v0, pr ? v3 : v1, ge,
+                               &y[4 * pr]);
                     }
                     if constexpr (Gm::BANDC) {
                         const float* at = atab + (tc0 >> 1) * 256 + lane;
