@@ -338,7 +338,10 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
                     for (int pr = 0; pr < 2; pr++) {
                         const bool sp = (grp == 0) && (pr == 0);
                         const float Ca = dr[2 * pr], Sb = dr[2 * pr + 1], Cai = di[2 * pr], Sbi = di[2 * pr + 1];
-                        const float re1 = sp ? Ca : Ca + Sbi, im1 = sp ? Cai : Cai - Sb;
+                        // the special pair (cos 0, cos n/2) only drops a term in re1, im1: fma(f, x, y)
+                        // is y + x for f = 1 and y for f = 0
+                        const float f = sp ? 0.f : 1.f;
+                        const float re1 = fmaf(f, Sbi, Ca), im1 = fmaf(-f, Sb, Cai);
                         const float re2 = sp ? Sb : Ca - Sbi, im2 = sp ? Sbi : Cai + Sb;
                         const float q1 = fmaf(re1, re1, im1 * im1), q2 = fmaf(re2, re2, im2 * im2);
                         const float m1 = EN ? q1 : __builtin_amdgcn_sqrtf(q1);
