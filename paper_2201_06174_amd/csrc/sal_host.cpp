@@ -129,7 +129,7 @@ static uint16_t to_f16(float f) {
 // not be inside a stream capture).
 constexpr int kSides[4] = {4, 8, 12, 16};
 constexpr int kTableSlots = 4 * 2;                  // (n, window)
-constexpr size_t kTableSlotBytes = 160 * 1024;      // 159,744 B at n = 16
+constexpr size_t kTableSlotBytes = 240 * 1024;      // 233,472 B at n = 16
 constexpr int kStridesPerWindow = 1 + 3 + 5 + 7;    // 1 <= s < n/2 for n = 4, 8, 12, 16
 constexpr int kPassASlots = kStridesPerWindow * 2;  // (n, s, window)
 constexpr size_t kPassASlotBytes = 27648;           // (n/2 + 1) x 3 x 16 x 32 x 2 B at n = 16
@@ -245,6 +245,25 @@ static std::vector<unsigned char> build_table_slot(int n, int window, Tables* t)
                 clo[(c * 16 + r) * 32 + k] = to_bf16(f - from_bf16(bh));
                 ch16[(c * 16 + r) * 32 + k] = to_f16(f);
             }
+    // the projection operand of the reduced-precision pass C: bf16 pairs of the weights, split
+    // into hi = bf16(w) (columns m) and lo = bf16(w - hi) (columns 4 + m)
+    std::vector<uint32_t> wproj(size_t(KH) * n * 64 * 2, 0u);
+    for (int kx = 0; kx < KH; kx++)
+        for (int u = 0; u < n; u++)
+            for (int lane = 0; lane < 64; lane++) {
+                const int col = lane & 15, g = lane >> 4, m = col & 3;
+                if (m == 3 || col >= 8) continue;
+                uint16_t v[4];
+                for (int i = 0; i < 4; i++) {
+                    const int r = 4 * g + i;
+                    const float w = r < n ? wnat_h[((size_t(kx) * n + u) * 16 + r) * 4 + m] : 0.f;
+                    const uint16_t h = to_bf16(w);
+                    v[i] = col < 4 ? h : to_bf16(w - from_bf16(h));
+                }
+                uint32_t* o = &wproj[((size_t(kx) * n + u) * 64 + lane) * 2];
+                o[0] = uint32_t(v[0]) | uint32_t(v[1]) << 16;
+                o[1] = uint32_t(v[2]) | uint32_t(v[3]) << 16;
+            }
     std::vector<unsigned char> img(kTableSlotBytes, 0);
     size_t off = 0;
     auto put = [&](const void* src, size_t nb) -> size_t {
@@ -254,7 +273,7 @@ static std::vector<unsigned char> build_table_slot(int n, int window, Tables* t)
         off += (nb + 255) / 256 * 256;  // keep every table 256-byte aligned
         return at;
     };
-    size_t o[10];
+    size_t o[11];
     o[9] = 0;
     o[0] = put(passA.data(), passA.size() * 4);
     o[1] = put(mat.data(), mat.size() * 4);
@@ -266,6 +285,7 @@ static std::vector<unsigned char> build_table_slot(int n, int window, Tables* t)
     o[7] = put(clo.data(), clo.size() * 2);
     o[8] = put(ch16.data(), ch16.size() * 2);
     o[9] = put(wts_e.data(), wts_e.size() * 4);
+    o[10] = put(wproj.data(), wproj.size() * 4);
     for (size_t v : o)
         if (v == SIZE_MAX) return {};  // cannot happen for n <= 16 (the slot is sized for n = 16)
     t->n = n;
@@ -281,6 +301,7 @@ static std::vector<unsigned char> build_table_slot(int n, int window, Tables* t)
     t->cpx_lo = (const uint16_t*)o[7];
     t->cpx_h16 = (const uint16_t*)o[8];
     t->wts_e = (const float*)o[9];
+    t->wproj = (const uint32_t*)o[10];
     return img;
 }
 
@@ -348,6 +369,7 @@ static sal_status init_device_tables(int dev) {
             t.cpx_lo = (const uint16_t*)(b + (size_t)t.cpx_lo);
             t.cpx_h16 = (const uint16_t*)(b + (size_t)t.cpx_h16);
             t.wts_e = (const float*)(b + (size_t)t.wts_e);
+            t.wproj = (const uint32_t*)(b + (size_t)t.wproj);
             d.t[slot] = t;
         }
     std::vector<uint16_t> pimg(size_t(kPassASlots) * kPassASlotBytes / 2);

@@ -75,6 +75,11 @@ struct Tables {
     const uint16_t* cpx_hi = nullptr;
     const uint16_t* cpx_lo = nullptr;
     const uint16_t* cpx_h16 = nullptr;
+    // projection operand of the reduced-precision pass C, [KH][n slots u][64 lanes][2 words]: lane
+    // col + 16 g holds four bf16 values, the weights (wts_nat_h) of plane m for the bins
+    // r = 4g .. 4g + 3 of slot u: their hi parts in column m, their lo parts in column 4 + m
+    // (m = 0, 1, 2), zero in the other columns
+    const uint32_t* wproj = nullptr;
 };
 
 // The tables of the current device.  If they are not uploaded yet and `stream` is not being

@@ -7,8 +7,10 @@
 // instruction pair (real and imaginary output tiles) covers a whole 1D DFT of
 // 16 windows.  Operands are rounded to bfloat16 twice (hi = bf16(x),
 // lo = bf16(x - hi)) and the three products hi*hi + hi*lo + lo*hi are
-// accumulated in fp32 (SPLIT_BF16), or rounded once to fp16 (FP16).  Pass A,
-// the magnitudes and the projection sums stay in fp32.
+// accumulated in fp32 (SPLIT_BF16), or rounded once to fp16 (FP16).  Pass A
+// and the magnitudes stay in fp32; so do the projection sums of the split form,
+// while FP16 takes them on the bf16 matrix cores (magnitudes rounded once,
+// weights split into hi + lo, fp32 accumulation).
 #include <algorithm>
 #include <cstring>
 #include <type_traits>
@@ -37,6 +39,7 @@ struct LowpParams {
     const uint16_t* cpx_a;  // hi (bf16) or fp16 operand table [2][16][32]
     const uint16_t* cpx_b;  // lo (bf16) table, unused for fp16
     const float4* wts;      // natural-order weights, Hermitian mirror folded in (wts_nat_h)
+    const uint32_t* wproj;  // FP16 projection operand [KH][N][64 lanes][2 words] (Tables::wproj)
     const uint16_t* pa_ops; // pass-A operands of this stride (fixed tiles)
     float* E;
 };
@@ -173,6 +176,12 @@ __host__ __device__ constexpr int lowp_rtp(int CT, int s) {
 // position (rows of 16 consecutive banks, or of an odd dword pitch) never share a bank.
 __host__ __device__ constexpr int plane_pitch16(int n16) {
     return 2 * (n16 / 2 + (16 - (n16 / 2) % 32 + 32) % 32);
+}
+
+// Two magnitudes rounded to bf16 (nearest even), a in the low half.
+__device__ __forceinline__ uint32_t bf16_pair(float a, float b) {
+    const bf2 v = {(__bf16)a, (__bf16)b};
+    return __builtin_bit_cast(uint32_t, v);
 }
 
 // Sum over the 16 lanes of a DPP row (the bins kt of one lane group): rotations by 8, 4, 2
@@ -368,12 +377,17 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
     if constexpr (FIX) pass_a_ops(0, pbh, pbl);
 
     const int wtc = wave & 7;
-    // acc[c][j][m]: window 4*grp + j of t slot wtc + 8c, plane m, summed over this lane's bins
+    // split form: acc[c][j][m], window 4*grp + j of t slot wtc + 8c, plane m, summed over this
+    // lane's bins.  FP16: pacc[c], row m' = 4 grp + j of window col of t slot wtc + 8c (j = 0..2:
+    // plane m = j from the weights' hi parts in lane group 0, from their lo parts in group 1).
     float acc[CTW][4][3];
+    f4 pacc[CTW];
 #pragma unroll
-    for (int c = 0; c < CTW; c++)
+    for (int c = 0; c < CTW; c++) {
+        pacc[c] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int j = 0; j < 4; j++) acc[c][j][0] = acc[c][j][1] = acc[c][j][2] = 0.f;
+    }
 
     __syncthreads();
     // the samples past the last staged row only meet zero coefficients; keep them finite.
@@ -493,7 +507,7 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
         // skipped mirrors folded into the table's weights.
         const bool mirror = kx == 0 || 2 * kx == N;
         const float4* wk = p.wts + (size_t)kx * N * 16;
-        if constexpr (!FIX)
+        if constexpr (!FIX && L::split)
             for (int e = tid; e < N * 16; e += kNTL) Wl[e] = wk[e];
         // ---- pass B: complex DFT along il for a pair of rows per wave; the outputs of the
         // two rows are rounded and written as packed pairs along t
@@ -535,12 +549,17 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
             }
         }
         __syncthreads();
-        // ---- pass C along t and the projection epilogue.  The product is taken transposed
-        // (windows x bins), so a lane holds one bin kt = col of four windows and needs one
-        // weight triple per ki.  Slot u+1 is contracted before the epilogue of slot u so the
-        // matrix cores and the VALU overlap.  The two wave halves split the ki slots to visit,
-        // [0, n) or [0, n/2] on a mirror plane.
+        // ---- pass C along t and the projection.  Split form: the product is taken transposed
+        // (windows x bins), so a lane holds one bin kt = col of four windows and needs one weight
+        // triple per ki, summed in fp32.  FP16: the product puts the bins in the rows and the 16
+        // windows of the t-centre in the columns, so a lane holds bins 4 grp .. 4 grp + 3 of window
+        // col; the magnitudes of two ki slots, rounded to bf16, form the B operand of one bf16
+        // product against the weights (rows m: their hi parts, rows 4 + m: their lo parts),
+        // accumulated in fp32 over all slots and kx.  Slot u+1 is contracted before the epilogue
+        // of slot u so the matrix cores and the VALU overlap.  The two wave halves split the ki
+        // slots to visit, [0, n) or [0, n/2] on a mirror plane.
         const int ua = (wave >> 3) ? (mirror ? (N / 2 + 2) / 2 : UH) : 0;
+        const uint32_t* wpk = p.wproj + ((size_t)kx * N * 64 + lane) * 2;  // FP16: this lane's words of slot 0
 #pragma unroll
         for (int c = 0; c < CTW; c++) {
             const int tc = wtc + 8 * c;
@@ -594,11 +613,64 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
                     }
                 }
             };
+            auto run16 = [&](auto odd, auto count) {
+                constexpr bool ODD = decltype(odd)::value;
+                constexpr int CNT = decltype(count)::value;
+                auto contract_c = [&](int u, f4& dre, f4& dim) {
+                    uint32_t wh[4];
+                    load8_u16<ODD>(ghb + u * 16 * gRow, ts, wh);
+                    const vec vh = vec_from_words<PREC>(wh);
+                    dre = contract<PREC>(are_h, are_l, vh, vh, f4{0.f, 0.f, 0.f, 0.f});
+                    dim = contract<PREC>(aim_h, aim_l, vh, vh, f4{0.f, 0.f, 0.f, 0.f});
+                };
+                auto weight = [&](int u) { return *(const uint2*)(wpk + (size_t)u * 128); };
+                f4 dre, dim;
+                // wp[q]: weights of the slot at position q of the current pair
+                uint2 wp[2] = {weight(ua), make_uint2(0u, 0u)};
+                uint32_t mag[4];
+                contract_c(ua, dre, dim);
+#pragma unroll
+                for (int uu = 0; uu < CNT; uu++) {
+                    const int u = ua + uu;
+                    f4 nre, nim;
+                    uint2 wn;
+                    if (uu + 1 < CNT) {
+                        wn = weight(u + 1);
+                        contract_c(u + 1, nre, nim);
+                    }
+                    float m[4];
+#pragma unroll
+                    for (int j = 0; j < 4; j++) m[j] = __builtin_amdgcn_sqrtf(fmaf(dre[j], dre[j], dim[j] * dim[j]));
+                    const int q = 2 * (uu & 1);
+                    mag[q] = bf16_pair(m[0], m[1]);
+                    mag[q + 1] = bf16_pair(m[2], m[3]);
+                    if ((uu & 1) || uu + 1 == CNT) {
+                        // a lone last slot pairs with zero weights and magnitudes
+                        if (!(uu & 1)) {
+                            mag[2] = mag[3] = 0u;
+                            wp[1] = make_uint2(0u, 0u);
+                        }
+                        typedef uint32_t u4w __attribute__((ext_vector_type(4)));
+                        pacc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            __builtin_bit_cast(bf8, u4w{wp[0].x, wp[0].y, wp[1].x, wp[1].y}),
+                            __builtin_bit_cast(bf8, u4w{mag[0], mag[1], mag[2], mag[3]}), pacc[c], 0, 0, 0);
+                    }
+                    if (uu + 1 < CNT) {
+                        dre = nre;
+                        dim = nim;
+                        wp[(uu + 1) & 1] = wn;
+                    }
+                }
+            };
             // slot counts are compile-time per case so each loop stays fully unrolled
+            auto run_form = [&](auto odd, auto count) {
+                if constexpr (L::split) run(odd, count);
+                else run16(odd, count);
+            };
             auto run_slots = [&](auto odd) {
-                if (!mirror) run(odd, std::integral_constant<int, UH>{});
-                else if (wave >> 3) run(odd, std::integral_constant<int, (N / 2 + 1) / 2>{});
-                else run(odd, std::integral_constant<int, (N / 2 + 2) / 2>{});
+                if (!mirror) run_form(odd, std::integral_constant<int, UH>{});
+                else if (wave >> 3) run_form(odd, std::integral_constant<int, (N / 2 + 1) / 2>{});
+                else run_form(odd, std::integral_constant<int, (N / 2 + 2) / 2>{});
             };
             // the window start's parity is the same for the whole wave
             if ((S > 0 && (S & 1) == 0) || (ts & 1) == 0) run_slots(std::false_type{});
@@ -637,10 +709,42 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
         for (int kx = 0; kx < KH; kx++) kstep(kx);
     }
 
+    const int64_t G = p.Tg * p.ILg * p.XLg;
+    float* red = (float*)Gh;  // [CTW][8][16][3]
+    if constexpr (!L::split) {
+        // plane m of window col: row m (lane group 0) plus row 4 + m (lane group 1), then the two
+        // halves of the ki slots through LDS
+        __syncthreads();
+        float e[CTW][3];
+#pragma unroll
+        for (int c = 0; c < CTW; c++)
+#pragma unroll
+            for (int m = 0; m < 3; m++) e[c][m] = pacc[c][m] + __shfl_down(pacc[c][m], 16);
+        if (NW > 8 && wave >= 8 && lane < 16) {
+#pragma unroll
+            for (int c = 0; c < CTW; c++)
+#pragma unroll
+                for (int m = 0; m < 3; m++) red[((c * 8 + wtc) * 16 + col) * 3 + m] = e[c][m];
+        }
+        __syncthreads();
+        if (wave < 8 && lane < 16) {
+#pragma unroll
+            for (int c = 0; c < CTW; c++) {
+                const int tc = wtc + 8 * c;
+                const int64_t gt = tt * CT + tc, gi = ti * 4 + (col >> 2), gx = tx * 4 + (col & 3);
+                if (tc < CT && gt < p.Tg && gi < p.ILg && gx < p.XLg) {
+                    const int64_t at = (gt * p.ILg + gi) * p.XLg + gx;
+#pragma unroll
+                    for (int m = 0; m < 3; m++)
+                        p.E[m * G + at] = e[c][m] + (NW > 8 ? red[((c * 8 + wtc) * 16 + col) * 3 + m] : 0.f);
+                }
+            }
+        }
+        return;
+    }
     // reduce over the 16 bins of a lane group, then over the two halves of the ki slots
     // through LDS
     __syncthreads();
-    float* red = (float*)Gh;  // [CTW][8][16][3]
 #pragma unroll
     for (int c = 0; c < CTW; c++)
 #pragma unroll
@@ -658,7 +762,6 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
                 for (int m = 0; m < 3; m++) red[((c * 8 + wtc) * 16 + 4 * grp + j) * 3 + m] = acc[c][j][m];
     }
     __syncthreads();
-    const int64_t G = p.Tg * p.ILg * p.XLg;
     if (wave < 8 && col == 0) {
 #pragma unroll
         for (int c = 0; c < CTW; c++) {
@@ -802,6 +905,7 @@ sal_status project_lowp_params(int n, int s, int precision, int CT, const float*
     p.cpx_a = split ? tb->cpx_hi : tb->cpx_h16;
     p.cpx_b = tb->cpx_lo;
     p.wts = (const float4*)tb->wts_nat_h;
+    p.wproj = tb->wproj;
     p.pa_ops = nullptr;
     if (lowp_fixed(n, s, CT)) {
         sal_status st = get_pass_a_ops(nullptr, n, s, tb->window, &p.pa_ops);  // the tables are uploaded by now
