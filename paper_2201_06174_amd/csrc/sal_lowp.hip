@@ -401,7 +401,10 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
         if constexpr (L::split) Gl[at] = 0;
     }
 
-    auto kstep = [&](const int kx) {
+    // PLANE: 0 when kx may be a mirror plane (tested at run time), 1 for a plane known not to be one,
+    // 2 for a mirror plane (kx = 0 or n/2)
+    auto kstep = [&](const int kx, auto plane) {
+        constexpr int PLANE = decltype(plane)::value;
         if constexpr (FIX) {
             // ---- pass A on the matrix cores: 16 staged rows x 32 samples times the 32 x 16
             // operand of this kx (columns cos|sin x window column); the il pairs of the result
@@ -505,7 +508,7 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
         // bin weights of this kx.  The planes kx = 0 and kx = n/2 are their own Hermitian
         // mirrors (|F(-k)| = |F(k)|): only the ki slots [0, n/2] are visited there, with the
         // skipped mirrors folded into the table's weights.
-        const bool mirror = kx == 0 || 2 * kx == N;
+        const bool mirror = PLANE == 2 || (PLANE == 0 && (kx == 0 || 2 * kx == N));
         const float4* wk = p.wts + (size_t)kx * N * 16;
         if constexpr (!FIX && L::split)
             for (int e = tid; e < N * 16; e += kNTL) Wl[e] = wk[e];
@@ -668,7 +671,7 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
                 else run16(odd, count);
             };
             auto run_slots = [&](auto odd) {
-                if (!mirror) run_form(odd, std::integral_constant<int, UH>{});
+                if (PLANE == 1 || !mirror) run_form(odd, std::integral_constant<int, UH>{});
                 else if (wave >> 3) run_form(odd, std::integral_constant<int, (N / 2 + 1) / 2>{});
                 else run_form(odd, std::integral_constant<int, (N / 2 + 2) / 2>{});
             };
@@ -678,7 +681,8 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
         }
     };
     if constexpr (lowp_prefetch<N, S, PREC, CTW, FIX>()) {
-        for (int kx = 0; kx + 1 < KH; kx++) kstep(kx);
+        kstep(0, std::integral_constant<int, 2>{});
+        for (int kx = 1; kx + 1 < KH; kx++) kstep(kx, std::integral_constant<int, 1>{});
         // the last kx step reads the staged planes in pass A only; the next region's loads
         // are in flight meanwhile and are stored after the step
         constexpr int NPF = lowp_prefetch_planes<N, S, PREC, CTW, FIX>();
@@ -689,7 +693,7 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
             stage_issue<kNTL, NPF>(pf, q.V, q.T, q.IL, q.XL, nt * CT * s - N / 2, ni * 4 * s - N / 2,
                                    nx * 4 * s - N / 2, RT, RI, RX);
         }
-        kstep(KH - 1);
+        kstep(KH - 1, std::integral_constant<int, 2>{});
         if (has_next) {
             const StageLane sl = stage_lane<kNTL>(RI, RX);
             if (sl.g < sl.G) {
@@ -706,7 +710,9 @@ __device__ __forceinline__ void project_tile_lowp(const LowpParams& p, const int
             }
         }
     } else {
-        for (int kx = 0; kx < KH; kx++) kstep(kx);
+        kstep(0, std::integral_constant<int, 2>{});
+        for (int kx = 1; kx + 1 < KH; kx++) kstep(kx, std::integral_constant<int, 1>{});
+        kstep(KH - 1, std::integral_constant<int, 2>{});
     }
 
     const int64_t G = p.Tg * p.ILg * p.XLg;

@@ -132,7 +132,10 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
 
     __syncthreads();
 
-    auto kstep = [&](const int kx) {
+    // PLANE: 0 when kx may be a mirror plane (tested at run time), 1 for a plane known not to be one,
+    // 2 for a mirror plane (kx = 0 or n/2)
+    auto kstep = [&](const int kx, auto plane) {
+        constexpr int PLANE = decltype(plane)::value;
         // ---- pass A: real DFT along xl at bin kx for every staged (t, il) row
         {
             float cA[N], sA[N];
@@ -182,7 +185,7 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
         // bin weights of this kx (their previous readers all passed the barrier above).  The
         // planes kx = 0 and kx = n/2 are their own Hermitian mirrors (|F(-k)| = |F(k)|): only
         // the ki slots [0, n/2] are visited there, and a slot whose mirror is skipped counts twice.
-        const bool mirror = kx == 0 || 2 * kx == N;
+        const bool mirror = PLANE == 2 || (PLANE == 0 && (kx == 0 || 2 * kx == N));
         // at n = 8 pass B keeps waves 0..7 busy, so waves from 8 on copy the weights: the latency
         // of their global loads overlaps the products instead of delaying them
         for (int e = PAIR ? tid - kNT / 2 : tid; e < N * 16; e += kNT) {
@@ -358,14 +361,15 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
                 }
             };
             // slot counts are compile-time per case so each loop stays fully unrolled
-            if (!mirror) run(std::integral_constant<int, UH>{});
+            if (PLANE == 1 || !mirror) run(std::integral_constant<int, UH>{});
             else if (wave >> 3) run(std::integral_constant<int, (N / 2 + 1) / 2>{});
             else run(std::integral_constant<int, (N / 2 + 2) / 2>{});
         }
         // the next pass A writes only Ab, whose readers (pass B) all passed the barrier above
     };
     if constexpr (fp32_prefetch<N, S, CTW>()) {
-        for (int kx = 0; kx + 1 < KH; kx++) kstep(kx);
+        kstep(0, std::integral_constant<int, 2>{});
+        for (int kx = 1; kx + 1 < KH; kx++) kstep(kx, std::integral_constant<int, 1>{});
         // the last kx step reads the region in pass A only; its loads for the next tile are in
         // flight meanwhile and land after the step (every wave passed the barrier behind pass A)
         constexpr int NPL = fp32_prefetch_planes<N, S, CTW>();
@@ -376,10 +380,13 @@ __device__ __forceinline__ void project_tile_fp32(const ProjParams& p, const int
             stage_issue<kNT, NPL>(pf, q.V, q.T, q.IL, q.XL, nt * CT * s - N / 2, ni * 4 * s - N / 2,
                                   nx * 4 * s - N / 2, RT, RI, RX);
         }
-        kstep(KH - 1);
+        kstep(KH - 1, std::integral_constant<int, 2>{});
         if (has_next) stage_commit<kNT, NPL>(pf, RT, RI, RX, RXp, Vt);
     } else {
-        for (int kx = 0; kx < KH; kx++) kstep(kx);
+        // the mirror planes kx = 0 and n/2 peeled off, so every step's slot counts are fixed
+        kstep(0, std::integral_constant<int, 2>{});
+        for (int kx = 1; kx + 1 < KH; kx++) kstep(kx, std::integral_constant<int, 1>{});
+        kstep(KH - 1, std::integral_constant<int, 2>{});
     }
 
     const int64_t G = p.Tg * p.ILg * p.XLg;
